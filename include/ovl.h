@@ -1,0 +1,202 @@
+/*
+ * ovl.h -- C ABI of the MI355X (gfx950) overlap-operator library.
+ *
+ * Method: N. Cundy, W. Lee, "The eigSUMR inverter for overlap fermions"
+ * (arXiv:1501.01855).  The library applies the overlap operator
+ *     D[mu] = (1 + mu + (1 - mu) gamma_5 sign(K)) / 2          (Sec. 1, eq. 1)
+ * with the Wilson kernel K = gamma_5 D_W(-rho)                  (Sec. 1, eq. 2)
+ * and solves D[mu] x = b with GMRESR(relSUMR)                   (Secs. 2-3, Algs. 1-3)
+ * with eigSUMR deflation                                        (Secs. 4-5, Algs. 5-6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status:   every function returns an ovl_status; 0 = OVL_OK.  On error a
+ *           message is available from ovl_last_error() (per thread).  No C++
+ *           exception crosses the ABI.
+ * Memory:   field buffers are caller-owned DEVICE memory unless the argument
+ *           name ends in _host.  The library never frees them.  Handles own
+ *           their internal (packed) copies and workspace, released by the
+ *           matching destroy call.
+ * Layout:   canonical complex128, real and imaginary parts interleaved:
+ *             spinor  psi[site][spin][colour]        (12 complex per site)
+ *             gauge   U[site][mu][a][b]              (36 complex per site)
+ *           site = x + Lx*(y + Ly*(z + Lz*t)), mu = 0..3 = x, y, z, t,
+ *           periodic boundaries.  nrhs right-hand sides are contiguous
+ *           fields (rhs-major).
+ * Gammas:   chiral basis, gamma_k = [[0, -i s_k], [i s_k, 0]] (s_k Pauli),
+ *           gamma_4 = [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1).
+ * Kernel:   K = gamma_5 [(4 - rho) - H/2],
+ *           H psi(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                     + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu),
+ *           i.e. the paper's kernel times (8 - 2 rho)/2 (kappa = 1/(8 - 2 rho));
+ *           sign(K) is unchanged by that positive factor.
+ * Streams:  all device work of a context runs on the HIP stream given at
+ *           creation (0 = the null stream).  Operator calls are asynchronous;
+ *           solver calls and calls that return host data block until done.
+ * Precision: OVL_F64 (FP64 storage and arithmetic), OVL_F32 (FP32 storage and
+ *           arithmetic, FP64 reductions and scalars), OVL_HALF (BF16 links,
+ *           FP16 spinors with one FP32 scale per site, FP32 arithmetic).
+ */
+#ifndef OVL_H
+#define OVL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OVL_OK = 0,
+    OVL_ERR_ARG = -1,           /* invalid argument (null pointer, size, range) */
+    OVL_ERR_HIP = -2,           /* a HIP runtime call failed                   */
+    OVL_ERR_NOMEM = -3,         /* device allocation failed                    */
+    OVL_ERR_NOT_CONVERGED = -4, /* iteration limit reached; best iterate written */
+    OVL_ERR_BREAKDOWN = -5,     /* NaN / Inf or a breakdown of a recurrence    */
+    OVL_ERR_UNSUPPORTED = -6,   /* valid request this build does not provide   */
+    OVL_ERR_STATE = -7          /* missing set-up (no gauge field loaded, ...) */
+} ovl_status;
+
+typedef enum { OVL_F64 = 0, OVL_F32 = 1, OVL_HALF = 2 } ovl_prec;
+
+typedef enum { OVL_SRC_POINT = 0, OVL_SRC_GAUSS = 1, OVL_SRC_Z2 = 2 } ovl_source_kind;
+
+#define OVL_MAX_NZ 64
+
+/* Zolotarev optimal rational approximation (Sec. 3, eq. 7):
+ *   eps(x) = x sum_{l<n_z} omega[l] / (x^2 + sigma[l]),  |eps| in [1-delta, 1+delta]
+ *   for a <= |x| <= b. */
+typedef struct {
+    int32_t n_z;
+    double a, b, delta;
+    double omega[OVL_MAX_NZ];
+    double sigma[OVL_MAX_NZ];
+} ovl_zolo;
+
+/* Counters of one call (or, for the solver, one right-hand side).
+ * dslash_calls[p] counts hopping-term applications in precision p (the paper
+ * counts a double-precision Wilson call as two units, single as one, Sec. 6). */
+typedef struct {
+    int64_t dslash_calls[3];
+    int64_t sign_calls[3];
+    int64_t mscg_iters;
+    int64_t sumr_iters;
+    int64_t gmresr_steps;
+    int64_t restarts;
+    double computed_relres;     /* solver: final recurrence residual / ||b|| */
+    double seconds;             /* wall time of the call                     */
+} ovl_stats;
+
+/* Parameters of ovl_sumr_gmresr_solve (defaults from ovl_solver_defaults). */
+typedef struct {
+    double rho;            /* kernel mass parameter, K = gamma_5 D_W(-rho)          */
+    double mu;             /* overlap mass parameter, 0 <= mu < 1                   */
+    double tol;            /* outer target ||b - D x|| <= tol ||b|| (Alg. 3 eps)    */
+    double eta_tilde;      /* middle-solve relative accuracy (Alg. 3 eta~)          */
+    double relax_floor;    /* worst sign accuracy allowed in relSUMR (Sec. 3: 1e-2) */
+    double f32_threshold;  /* sign accuracies >= this use OVL_F32 (Sec. 3: ~1e-7, larger) */
+    double half_threshold; /* sign accuracies >= this use OVL_HALF; > 1 disables    */
+    double norm_restart;   /* SUMR restart when | ||q|| - 1 | exceeds this (Sec. 6: 0.1) */
+    int32_t max_outer;     /* GMRESR steps                                          */
+    int32_t max_middle;    /* SUMR iterations per middle solve                      */
+    int32_t max_mscg;      /* multi-shift CG iterations per sign call               */
+    int32_t use_deflation; /* 1: start middle solves from the eigenspace projection  */
+    int32_t eig_calc;      /* 1: collect eigSUMR vectors during this solve (Alg. 5)  */
+    int32_t verbose;
+} ovl_solver_params;
+
+typedef struct ovl_context ovl_context;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context for one lattice of extents dims[4] (x, y, z, t, each >= 2)
+ * on the current HIP device, issuing work on hip_stream (a hipStream_t; 0 =
+ * null stream).  Allocates the context's workspace. */
+ovl_status ovl_create(const int32_t dims[4], void *hip_stream, ovl_context **out);
+ovl_status ovl_destroy(ovl_context *ctx);
+const char *ovl_last_error(void);
+void ovl_solver_defaults(ovl_solver_params *p);
+/* Device bytes currently held by the context (workspace + packed fields). */
+int64_t ovl_device_bytes(const ovl_context *ctx);
+
+/* ---- set-up: gauge field, sources (not part of the method; Sec. 6 inputs) -- */
+
+/* Load a gauge field from canonical complex128 device memory U_dev[V*36*2]
+ * and pack it into the internal layouts of every precision. */
+ovl_status ovl_gauge_load(ovl_context *ctx, const double *U_dev);
+
+/* Generate U_mu(x) = exp(i eps sum_a g_a T^a), g_a ~ N(0,1) from the seeded
+ * Philox4x32-10 stream, on the GPU, and load it; if U_out_dev is not null the
+ * canonical field is also written there.  Bit-identical to the reference
+ * generator of the test suite. */
+ovl_status ovl_gauge_generate(ovl_context *ctx, uint64_t seed, double eps, double *U_out_dev);
+
+/* Write one source field (canonical, device): point source at
+ * (site, spin, colour); complex Gaussian (Re, Im ~ N(0,1)); or Z2 noise (each
+ * real component +-1, Sec. 6). */
+ovl_status ovl_source_generate(ovl_context *ctx, int kind, uint64_t seed, int64_t site,
+                               int32_t spin, int32_t colour, double *out_dev);
+
+/* ---- operators (Sec. 1, eqs. 1-2; Sec. 3, eq. 7) ------------------------- */
+
+/* out = H in (the hopping term, 8-point stencil), nrhs fields. */
+ovl_status ovl_wilson_dslash(ovl_context *ctx, const double *in_dev, double *out_dev,
+                             int32_t nrhs, int32_t prec);
+
+/* out = K in = gamma_5 [(4 - rho) in - H in / 2], nrhs fields. */
+ovl_status ovl_kernel_K_apply(ovl_context *ctx, double rho, const double *in_dev,
+                              double *out_dev, int32_t nrhs, int32_t prec);
+
+/* Zolotarev coefficients for n_z poles on [a, b] (host, FP64; Sec. 3, eq. 7).
+ * 1 <= n_z <= OVL_MAX_NZ, 0 < a < b. */
+ovl_status ovl_zolotarev_coeffs(int32_t n_z, double a, double b, ovl_zolo *out_host);
+
+/* Kernel low modes (Sec. 1 after eq. 4; Sec. 3): compute the n_low eigenpairs
+ * of K with the smallest |lambda| (FP64, on the GPU) and keep them in the
+ * context; the sign function then treats them exactly.  evals_host (may be
+ * null) receives the n_low eigenvalues, ordered by |lambda|; lmax_host (may
+ * be null) receives an upper bound for |lambda| (largest Ritz value of K^2,
+ * square-rooted, times 1.01).  tol is the eigen-residual target
+ * ||K v - lambda v|| <= tol. */
+ovl_status ovl_lowmodes_compute(ovl_context *ctx, double rho, int32_t n_low, double tol,
+                                double *evals_host, double *lmax_host);
+/* Install caller-provided low modes instead (n vectors, canonical, device;
+ * orthonormal).  n = 0 removes them. */
+ovl_status ovl_lowmodes_set(ovl_context *ctx, int32_t n, const double *evals_host,
+                            const double *evecs_dev);
+/* Copy the context's low modes out (canonical, device, n_low fields). */
+ovl_status ovl_lowmodes_get(ovl_context *ctx, double *evecs_dev);
+
+/* out = sign(K) in: the context's low modes exactly, eps(K) on the rest,
+ * eps(K) by multi-shift CG on (K^2 + sigma_l) to sign accuracy eta
+ * (||error|| <= eta ||in|| in exact arithmetic, plus zolo->delta). */
+ovl_status ovl_sign_zolotarev_mscg(ovl_context *ctx, double rho, const ovl_zolo *zolo,
+                                   const double *in_dev, double *out_dev, int32_t nrhs,
+                                   double eta, int32_t prec, ovl_stats *stats_host);
+
+/* out = D[mu] in (Sec. 1, eq. 1) with the sign function as above. */
+ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_zolo *zolo,
+                             const double *in_dev, double *out_dev, int32_t nrhs, double eta,
+                             int32_t prec, ovl_stats *stats_host);
+
+/* ---- solver (Algs. 1-3, Sec. 3 relaxation, Secs. 4-5 deflation) ---------- */
+
+/* Solve D[mu] x = b for nrhs right-hand sides (one after another) with
+ * GMRESR(relSUMR).  b_dev, x_dev canonical; x is overwritten.  stats_host
+ * (may be null) has nrhs entries.  Returns OVL_ERR_NOT_CONVERGED with the best
+ * iterate in x when an iteration limit is hit. */
+ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo,
+                                 const ovl_solver_params *params, const double *b_dev,
+                                 double *x_dev, int32_t nrhs, ovl_stats *stats_host);
+
+/* Per-kernel timing of the context (HIP events around each launch on the
+ * context's stream), for roofline reporting.  kernel: 0 = hopping stencil
+ * (all K / Dslash launches), 1 = multi-shift update.  Enabling resets. */
+ovl_status ovl_profile_enable(ovl_context *ctx, int32_t on);
+ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int64_t *launches,
+                            double *milliseconds, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

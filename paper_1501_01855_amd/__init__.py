@@ -1,0 +1,281 @@
+"""MI355X (gfx950) overlap-operator library: Python binding of the C ABI.
+
+Argument marshalling only: every step runs in the HIP library ``libovl.so``
+built from ``csrc/``.  Fields are torch complex128 tensors on the GPU in the
+canonical layout (``psi[..., V, 4, 3]``, ``U[V, 4, 3, 3]``, site
+lexicographic with x fastest).  The library must be built
+(``python -m paper_1501_01855_amd.build``); importing this module on a
+machine without it raises immediately -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libovl.so")
+
+F64, F32, HALF = 0, 1, 2
+SRC_POINT, SRC_GAUSS, SRC_Z2 = 0, 1, 2
+MAX_NZ = 64
+KERN_STENCIL, KERN_SHIFT = 0, 1
+
+STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_NOMEM", -4: "ERR_NOT_CONVERGED",
+          -5: "ERR_BREAKDOWN", -6: "ERR_UNSUPPORTED", -7: "ERR_STATE"}
+
+
+class OvlError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Zolo(ctypes.Structure):
+    _fields_ = [("n_z", ctypes.c_int32), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("delta", ctypes.c_double), ("omega", ctypes.c_double * MAX_NZ),
+                ("sigma", ctypes.c_double * MAX_NZ)]
+
+    @property
+    def omegas(self):
+        return [self.omega[i] for i in range(self.n_z)]
+
+    @property
+    def sigmas(self):
+        return [self.sigma[i] for i in range(self.n_z)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("dslash_calls", ctypes.c_int64 * 3), ("sign_calls", ctypes.c_int64 * 3),
+                ("mscg_iters", ctypes.c_int64), ("sumr_iters", ctypes.c_int64),
+                ("gmresr_steps", ctypes.c_int64), ("restarts", ctypes.c_int64),
+                ("computed_relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"dslash_calls": list(self.dslash_calls), "sign_calls": list(self.sign_calls),
+                "mscg_iters": self.mscg_iters, "sumr_iters": self.sumr_iters,
+                "gmresr_steps": self.gmresr_steps, "restarts": self.restarts,
+                "computed_relres": self.computed_relres, "seconds": self.seconds,
+                # the paper's cost unit: a double-precision Wilson call counts 2, single 1
+                "wilson_units": 2 * self.dslash_calls[0] + self.dslash_calls[1] + self.dslash_calls[2]}
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("mu", ctypes.c_double), ("tol", ctypes.c_double),
+                ("eta_tilde", ctypes.c_double), ("relax_floor", ctypes.c_double),
+                ("f32_threshold", ctypes.c_double), ("half_threshold", ctypes.c_double),
+                ("norm_restart", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("max_middle", ctypes.c_int32), ("max_mscg", ctypes.c_int32),
+                ("use_deflation", ctypes.c_int32), ("eig_calc", ctypes.c_int32),
+                ("verbose", ctypes.c_int32)]
+
+
+EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults", "ovl_device_bytes",
+           "ovl_gauge_load", "ovl_gauge_generate", "ovl_source_generate", "ovl_wilson_dslash",
+           "ovl_kernel_K_apply", "ovl_zolotarev_coeffs", "ovl_lowmodes_compute", "ovl_lowmodes_set",
+           "ovl_lowmodes_get", "ovl_sign_zolotarev_mscg", "ovl_overlap_apply",
+           "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read"]
+
+_lib = None
+
+
+def lib():
+    """Load libovl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1501_01855_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ovl_create": ([P, P, P], I32),
+        "ovl_destroy": ([P], I32),
+        "ovl_last_error": ([], ctypes.c_char_p),
+        "ovl_solver_defaults": ([P], None),
+        "ovl_device_bytes": ([P], I64),
+        "ovl_gauge_load": ([P, P], I32),
+        "ovl_gauge_generate": ([P, ctypes.c_uint64, D, P], I32),
+        "ovl_source_generate": ([P, I32, ctypes.c_uint64, I64, I32, I32, P], I32),
+        "ovl_wilson_dslash": ([P, P, P, I32, I32], I32),
+        "ovl_kernel_K_apply": ([P, D, P, P, I32, I32], I32),
+        "ovl_zolotarev_coeffs": ([I32, D, D, P], I32),
+        "ovl_lowmodes_compute": ([P, D, I32, D, P, P], I32),
+        "ovl_lowmodes_set": ([P, I32, P, P], I32),
+        "ovl_lowmodes_get": ([P, P], I32),
+        "ovl_sign_zolotarev_mscg": ([P, D, P, P, P, I32, D, I32, P], I32),
+        "ovl_overlap_apply": ([P, D, D, P, P, P, I32, D, I32, P], I32),
+        "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
+        "ovl_profile_enable": ([P, I32], I32),
+        "ovl_profile_read": ([P, I32, I32, P, P, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(code, allow=()):
+    if code != 0 and code not in allow:
+        msg = lib().ovl_last_error()
+        raise OvlError(code, msg.decode() if msg else "")
+    return code
+
+
+def _dev(t, shape_tail, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.complex128:
+        raise TypeError(f"{name}: expected a complex128 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name}: trailing shape {tuple(t.shape)} does not end with {shape_tail}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def zolotarev_coeffs(n_z, a, b):
+    z = Zolo()
+    _check(lib().ovl_zolotarev_coeffs(int(n_z), float(a), float(b), ctypes.byref(z)))
+    return z
+
+
+def zolo_from(n_z, a, b, delta, omega, sigma):
+    """Build coefficients from given data (e.g. shared with a reference)."""
+    z = Zolo()
+    z.n_z, z.a, z.b, z.delta = int(n_z), float(a), float(b), float(delta)
+    for i in range(int(n_z)):
+        z.omega[i] = float(omega[i])
+        z.sigma[i] = float(sigma[i])
+    return z
+
+
+def solver_defaults(**kw):
+    p = SolverParams()
+    lib().ovl_solver_defaults(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """One lattice (extents dims = (Lx, Ly, Lz, Lt)) on the current GPU."""
+
+    def __init__(self, dims, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        d = (ctypes.c_int32 * 4)(*self.dims)
+        _check(lib().ovl_create(d, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ovl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self):
+        return lib().ovl_device_bytes(self._h)
+
+    # -- inputs
+    def gauge_load(self, U):
+        _check(lib().ovl_gauge_load(self._h, _dev(U, (self.V, 4, 3, 3), "U")))
+
+    def gauge_generate(self, seed, eps, out=None):
+        p = _dev(out, (self.V, 4, 3, 3), "out") if out is not None else None
+        _check(lib().ovl_gauge_generate(self._h, int(seed), float(eps), p))
+        return out
+
+    def source(self, kind, seed=0, site=0, spin=0, colour=0):
+        out = torch.empty((self.V, 4, 3), dtype=torch.complex128, device="cuda")
+        _check(lib().ovl_source_generate(self._h, int(kind), int(seed), int(site), int(spin),
+                                         int(colour), _dev(out, (self.V, 4, 3), "out")))
+        return out
+
+    # -- operators
+    def _nrhs(self, psi):
+        return 1 if psi.dim() == 3 else int(psi.shape[0])
+
+    def wilson_dslash(self, psi, prec=F64):
+        out = torch.empty_like(psi)
+        _check(lib().ovl_wilson_dslash(self._h, _dev(psi, (self.V, 4, 3), "psi"),
+                                       _dev(out, (self.V, 4, 3), "out"), self._nrhs(psi), prec))
+        return out
+
+    def kernel_K_apply(self, psi, rho, prec=F64):
+        out = torch.empty_like(psi)
+        _check(lib().ovl_kernel_K_apply(self._h, float(rho), _dev(psi, (self.V, 4, 3), "psi"),
+                                        _dev(out, (self.V, 4, 3), "out"), self._nrhs(psi), prec))
+        return out
+
+    def lowmodes_compute(self, rho, n_low, tol=1e-10):
+        ev = (ctypes.c_double * n_low)()
+        lmax = ctypes.c_double()
+        _check(lib().ovl_lowmodes_compute(self._h, float(rho), int(n_low), float(tol), ev,
+                                          ctypes.byref(lmax)))
+        self.n_low = n_low
+        return list(ev), lmax.value
+
+    def lowmodes_set(self, evals, evecs):
+        n = len(evals)
+        ev = (ctypes.c_double * max(n, 1))(*[float(e) for e in evals])
+        p = _dev(evecs, (self.V, 4, 3), "evecs") if n else None
+        _check(lib().ovl_lowmodes_set(self._h, n, ev, p))
+        self.n_low = n
+
+    def lowmodes_get(self):
+        out = torch.empty((self.n_low, self.V, 4, 3), dtype=torch.complex128, device="cuda")
+        _check(lib().ovl_lowmodes_get(self._h, _dev(out, (self.V, 4, 3), "out")))
+        return out
+
+    def sign(self, psi, rho, zolo, eta, prec=F64, allow=()):
+        out = torch.empty_like(psi)
+        st = Stats()
+        code = _check(lib().ovl_sign_zolotarev_mscg(self._h, float(rho), ctypes.byref(zolo),
+                                                    _dev(psi, (self.V, 4, 3), "psi"),
+                                                    _dev(out, (self.V, 4, 3), "out"),
+                                                    self._nrhs(psi), float(eta), prec,
+                                                    ctypes.byref(st)), allow)
+        return out, st
+
+    def overlap(self, psi, rho, mu, zolo, eta, prec=F64):
+        out = torch.empty_like(psi)
+        st = Stats()
+        _check(lib().ovl_overlap_apply(self._h, float(rho), float(mu), ctypes.byref(zolo),
+                                       _dev(psi, (self.V, 4, 3), "psi"),
+                                       _dev(out, (self.V, 4, 3), "out"), self._nrhs(psi),
+                                       float(eta), prec, ctypes.byref(st)))
+        return out, st
+
+    def solve(self, b, zolo, params, allow=()):
+        """GMRESR(relSUMR) solve of D[mu] x = b; returns (x, [Stats per rhs], status)."""
+        nrhs = self._nrhs(b)
+        x = torch.empty_like(b)
+        st = (Stats * nrhs)()
+        code = _check(lib().ovl_sumr_gmresr_solve(self._h, ctypes.byref(zolo), ctypes.byref(params),
+                                                  _dev(b, (self.V, 4, 3), "b"),
+                                                  _dev(x, (self.V, 4, 3), "x"), nrhs, st), allow)
+        return x, list(st), code
+
+    # -- profiling
+    def profile(self, on=True):
+        _check(lib().ovl_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, kernel, prec):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(lib().ovl_profile_read(self._h, int(kernel), int(prec), ctypes.byref(n),
+                                      ctypes.byref(ms), ctypes.byref(by)))
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value}

@@ -1,0 +1,216 @@
+// BLAS-1 on packed FP64 spinor fields (12 V complex numbers per field):
+// dots, norms and vector updates for SUMR (Alg. 2), GMRESR (Alg. 3) and the
+// eigenspace code.  Reductions: per-thread sums over a fixed grid-stride
+// pattern, wave64 shuffles, one partial per block, then one block sums the
+// partials in a fixed order, so results are run-to-run reproducible.
+#include "context.h"
+#include "fields.h"
+#include "kernels.h"
+
+namespace ovl {
+
+static constexpr int RB = 512;   // reduction blocks per field
+
+__global__ __launch_bounds__(256) void k_dot(const double2 *__restrict__ x, const double2 *__restrict__ y,
+                                             int64_t n, double *partial)
+{
+    const int f = blockIdx.y;
+    const double2 *xf = x + (int64_t)f * n, *yf = y + (int64_t)f * n;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = xf[i], b = yf[i];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+    }
+    __shared__ double lds[4];
+    const double tr = block_sum<256>(re, lds);
+    const double ti = block_sum<256>(im, lds);
+    if (threadIdx.x == 0) {
+        partial[((int64_t)f * 2 + 0) * gridDim.x + blockIdx.x] = tr;
+        partial[((int64_t)f * 2 + 1) * gridDim.x + blockIdx.x] = ti;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum_rows(const double *partial, int nblk, double *out)
+{
+    __shared__ double lds[4];
+    double v = 0.0;
+    const double *p = partial + (int64_t)blockIdx.x * nblk;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += p[i];
+    const double t = block_sum<256>(v, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+void sum_partials(Context &c, const double *partial, int nblk, int rows, double *out)
+{
+    k_sum_rows<<<rows, 256, 0, c.stream>>>(partial, nblk, out);
+    OVL_HIP(hipGetLastError());
+}
+
+void dot_f64(Context &c, const double2 *x, const double2 *y, int nf, std::vector<cplx<double>> &out)
+{
+    const int64_t n = 12 * c.g.V;
+    double *part = (double *)c.buf("blas_part", sizeof(double) * RB * 2 * nf);
+    double *res = (double *)c.buf("blas_res", sizeof(double) * 2 * nf);
+    k_dot<<<dim3(RB, nf), 256, 0, c.stream>>>(x, y, n, part);
+    k_sum_rows<<<2 * nf, 256, 0, c.stream>>>(part, RB, res);
+    OVL_HIP(hipGetLastError());
+    double *h = (double *)c.host_stage(sizeof(double) * 2 * nf);
+    OVL_HIP(hipMemcpyAsync(h, res, sizeof(double) * 2 * nf, hipMemcpyDeviceToHost, c.stream));
+    OVL_HIP(hipStreamSynchronize(c.stream));
+    out.resize(nf);
+    for (int f = 0; f < nf; ++f) out[f] = {h[2 * f], h[2 * f + 1]};
+}
+
+void norm2_f64(Context &c, const double2 *x, int nf, std::vector<double> &out)
+{
+    std::vector<cplx<double>> d;
+    dot_f64(c, x, x, nf, d);
+    out.resize(nf);
+    for (int f = 0; f < nf; ++f) out[f] = d[f].re;
+}
+
+struct Coef {
+    double re, im;
+};
+
+static constexpr int MAXNF = 16;
+
+struct AxpbyCoef {
+    Coef a[MAXNF], b[MAXNF];
+};
+
+__global__ __launch_bounds__(256) void k_axpby(AxpbyCoef k, const double2 *__restrict__ x,
+                                               double2 *__restrict__ y, int64_t n)
+{
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const cplx<double> af = {k.a[f].re, k.a[f].im}, bf = {k.b[f].re, k.b[f].im};
+    const double2 xv = x[(int64_t)f * n + i];
+    cplx<double> r = af * cplx<double>{xv.x, xv.y};
+    if (bf.re != 0.0 || bf.im != 0.0) {   // b = 0: y is not read (it may be uninitialised)
+        const double2 yv = y[(int64_t)f * n + i];
+        r = r + bf * cplx<double>{yv.x, yv.y};
+    }
+    y[(int64_t)f * n + i] = make_double2(r.re, r.im);
+}
+
+void axpby_f64(Context &c, const cplx<double> *a, const double2 *x, const cplx<double> *b, double2 *y, int nf)
+{
+    OVL_REQUIRE(nf >= 1 && nf <= MAXNF, OVL_ERR_ARG, "too many fields in one update");
+    const int64_t n = 12 * c.g.V;
+    AxpbyCoef k{};
+    for (int f = 0; f < nf; ++f) {
+        k.a[f] = {a[f].re, a[f].im};
+        k.b[f] = {b[f].re, b[f].im};
+    }
+    k_axpby<<<dim3((unsigned)((n + 255) / 256), nf), 256, 0, c.stream>>>(k, x, y, n);
+    OVL_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void k_gamma5(double2 *__restrict__ y, int64_t V)
+{
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 6 * V) return;
+    double2 *p = y + (int64_t)f * 12 * V + 6 * V;   // planes of spins 2, 3
+    const double2 v = p[i];
+    p[i] = make_double2(-v.x, -v.y);
+}
+
+void gamma5_f64(Context &c, double2 *y, int nf)
+{
+    const int64_t V = c.g.V;
+    k_gamma5<<<dim3((unsigned)((6 * V + 255) / 256), nf), 256, 0, c.stream>>>(y, V);
+    OVL_HIP(hipGetLastError());
+}
+
+void copy_fields(Context &c, const void *src, void *dst, int nf, int prec)
+{
+    OVL_HIP(hipMemcpyAsync(dst, src, field_bytes(c.g, prec) * nf, hipMemcpyDeviceToDevice, c.stream));
+}
+
+__global__ void k_zero(uint4 *p, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+void zero_fields(Context &c, void *dst, int nf, int prec)
+{
+    const int64_t n = (int64_t)(field_bytes(c.g, prec) * nf / 16);
+    k_zero<<<(unsigned)((n + 255) / 256), 256, 0, c.stream>>>((uint4 *)dst, n);
+    OVL_HIP(hipGetLastError());
+}
+
+// out[f][j] = (V_j, x_f)
+__global__ __launch_bounds__(256) void k_multidot(const double2 *__restrict__ Vb, int nv,
+                                                  const double2 *__restrict__ x, int64_t n, double *partial)
+{
+    const int f = blockIdx.y;
+    const int j = blockIdx.z;
+    const double2 *xf = x + (int64_t)f * n, *vj = Vb + (int64_t)j * n;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = vj[i], b = xf[i];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+    }
+    __shared__ double lds[4];
+    const double tr = block_sum<256>(re, lds);
+    const double ti = block_sum<256>(im, lds);
+    if (threadIdx.x == 0) {
+        const int64_t row = ((int64_t)f * nv + j) * 2;
+        partial[(row + 0) * gridDim.x + blockIdx.x] = tr;
+        partial[(row + 1) * gridDim.x + blockIdx.x] = ti;
+    }
+}
+
+void multidot_f64(Context &c, const double2 *Vb, int nv, const double2 *x, int nf,
+                  std::vector<cplx<double>> &out)
+{
+    out.assign((size_t)nf * nv, {0.0, 0.0});
+    if (nv == 0) return;
+    const int64_t n = 12 * c.g.V;
+    const int nb = 128;
+    double *part = (double *)c.buf("mdot_part", sizeof(double) * nb * 2 * nf * nv);
+    double *res = (double *)c.buf("mdot_res", sizeof(double) * 2 * nf * nv);
+    k_multidot<<<dim3(nb, nf, nv), 256, 0, c.stream>>>(Vb, nv, x, n, part);
+    k_sum_rows<<<2 * nf * nv, 256, 0, c.stream>>>(part, nb, res);
+    OVL_HIP(hipGetLastError());
+    double *h = (double *)c.host_stage(sizeof(double) * 2 * nf * nv);
+    OVL_HIP(hipMemcpyAsync(h, res, sizeof(double) * 2 * nf * nv, hipMemcpyDeviceToHost, c.stream));
+    OVL_HIP(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < nf * nv; ++i) out[i] = {h[2 * i], h[2 * i + 1]};
+}
+
+// x_f += sum_j coef[f*nv + j] V_j
+__global__ __launch_bounds__(256) void k_multiaxpy(const double2 *__restrict__ Vb, int nv, const Coef *coef,
+                                                   double2 *__restrict__ x, int64_t n)
+{
+    const int f = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 xv = x[(int64_t)f * n + i];
+    cplx<double> acc = {xv.x, xv.y};
+    for (int j = 0; j < nv; ++j) {
+        const double2 v = Vb[(int64_t)j * n + i];
+        acc = acc + cplx<double>{coef[f * nv + j].re, coef[f * nv + j].im} * cplx<double>{v.x, v.y};
+    }
+    x[(int64_t)f * n + i] = make_double2(acc.re, acc.im);
+}
+
+void multiaxpy_f64(Context &c, const double2 *Vb, int nv, const cplx<double> *coef, double2 *x, int nf)
+{
+    if (nv == 0) return;
+    const int64_t n = 12 * c.g.V;
+    Coef *d = (Coef *)c.buf("maxpy_coef", sizeof(Coef) * nf * nv);
+    std::vector<Coef> h((size_t)nf * nv);   // pageable: the copy is staged before return
+    for (int i = 0; i < nf * nv; ++i) h[i] = {coef[i].re, coef[i].im};
+    OVL_HIP(hipMemcpyAsync(d, h.data(), sizeof(Coef) * nf * nv, hipMemcpyHostToDevice, c.stream));
+    k_multiaxpy<<<dim3((unsigned)((n + 255) / 256), nf), 256, 0, c.stream>>>(Vb, nv, d, x, n);
+    OVL_HIP(hipGetLastError());
+}
+
+}  // namespace ovl

@@ -1,0 +1,341 @@
+// extern "C" entry points (include/ovl.h): argument checks, layout packing
+// between the canonical complex128 layout and the internal planes, error
+// translation.  No exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <exception>
+
+#include "context.h"
+#include "kernels.h"
+#include "ops.h"
+
+namespace ovl {
+const char *last_error();
+}
+
+using namespace ovl;
+
+struct ovl_context : public ovl::Context {};
+
+template <class F>
+static ovl_status guard(F &&f)
+{
+    try {
+        f();
+        return OVL_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return OVL_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return OVL_ERR_ARG;
+    }
+}
+
+static void check_prec(int prec, bool allow_half = false)
+{
+    OVL_REQUIRE(prec == OVL_F64 || prec == OVL_F32 || (allow_half && prec == OVL_HALF), OVL_ERR_ARG,
+                "precision must be OVL_F64 or OVL_F32" + std::string(allow_half ? " or OVL_HALF" : ""));
+}
+
+static void check_ctx(ovl_context *ctx) { OVL_REQUIRE(ctx != nullptr, OVL_ERR_ARG, "null context"); }
+
+static void check_zolo(const ovl_zolo *z)
+{
+    OVL_REQUIRE(z != nullptr, OVL_ERR_ARG, "null Zolotarev coefficients");
+    OVL_REQUIRE(z->n_z >= 1 && z->n_z <= OVL_MAX_NZ, OVL_ERR_ARG, "n_z out of range");
+    for (int l = 0; l < z->n_z; ++l)
+        OVL_REQUIRE(z->omega[l] > 0.0 && z->sigma[l] > 0.0 && std::isfinite(z->omega[l]) &&
+                        std::isfinite(z->sigma[l]),
+                    OVL_ERR_ARG, "Zolotarev omega and sigma must be positive and finite");
+}
+
+static constexpr int MAX_NRHS = 16;
+
+extern "C" {
+
+const char *ovl_last_error(void) { return ovl::last_error(); }
+
+void ovl_solver_defaults(ovl_solver_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->rho = 1.4;
+    p->mu = 0.05;
+    p->tol = 1e-10;
+    p->eta_tilde = 1e-3;
+    p->relax_floor = 1e-2;
+    p->f32_threshold = 1e-6;
+    p->half_threshold = 2.0;
+    p->norm_restart = 0.1;
+    p->max_outer = 16;
+    p->max_middle = 2000;
+    p->max_mscg = 20000;
+    p->use_deflation = 0;
+    p->eig_calc = 0;
+    p->verbose = 0;
+}
+
+ovl_status ovl_create(const int32_t dims[4], void *hip_stream, ovl_context **out)
+{
+    return guard([&] {
+        OVL_REQUIRE(dims != nullptr && out != nullptr, OVL_ERR_ARG, "null argument");
+        int64_t V = 1;
+        for (int m = 0; m < 4; ++m) {
+            OVL_REQUIRE(dims[m] >= 2 && dims[m] <= 4096, OVL_ERR_ARG, "lattice extents must be in [2, 4096]");
+            V *= dims[m];
+        }
+        OVL_REQUIRE(V < (int64_t)1 << 30, OVL_ERR_ARG, "lattice volume must be below 2^30 sites");
+        auto *c = new ovl_context();
+        c->g = make_geom(dims);
+        c->stream = (hipStream_t)hip_stream;
+        hipError_t e = hipGetDevice(&c->device);
+        if (e != hipSuccess) {
+            delete c;
+            throw Error{OVL_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e)};
+        }
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+            c->num_cu = ncu;
+        *out = c;
+    });
+}
+
+ovl_status ovl_destroy(ovl_context *ctx)
+{
+    return guard([&] { delete ctx; });
+}
+
+int64_t ovl_device_bytes(const ovl_context *ctx) { return ctx ? ctx->bytes_held : 0; }
+
+ovl_status ovl_gauge_load(ovl_context *ctx, const double *U_dev)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(U_dev != nullptr, OVL_ERR_ARG, "null gauge field");
+        pack_gauge(*ctx, U_dev);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_gauge_generate(ovl_context *ctx, uint64_t seed, double eps, double *U_out_dev)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(std::isfinite(eps), OVL_ERR_ARG, "eps must be finite");
+        gauge_generate(*ctx, seed, eps, U_out_dev);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_source_generate(ovl_context *ctx, int kind, uint64_t seed, int64_t site, int32_t spin,
+                               int32_t colour, double *out_dev)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(out_dev != nullptr, OVL_ERR_ARG, "null output");
+        OVL_REQUIRE(kind == OVL_SRC_POINT || kind == OVL_SRC_GAUSS || kind == OVL_SRC_Z2, OVL_ERR_ARG,
+                    "unknown source kind");
+        if (kind == OVL_SRC_POINT)
+            OVL_REQUIRE(site >= 0 && site < ctx->g.V && spin >= 0 && spin < 4 && colour >= 0 && colour < 3,
+                        OVL_ERR_ARG, "point source index out of range");
+        source_generate(*ctx, kind, seed, site, spin, colour, out_dev);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_wilson_dslash(ovl_context *ctx, const double *in_dev, double *out_dev, int32_t nrhs, int32_t prec)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        check_prec(prec);
+        OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        const size_t FB = field_bytes(ctx->g, prec) * nrhs;
+        void *a = ctx->buf("api_a", FB);
+        void *b = ctx->buf("api_b", FB);
+        pack_spinor(*ctx, in_dev, a, nrhs, prec);
+        launch_hop(*ctx, a, b, nrhs, prec);
+        unpack_spinor(*ctx, b, out_dev, nrhs, prec);
+        ctx->prof_collect();
+    });
+}
+
+ovl_status ovl_kernel_K_apply(ovl_context *ctx, double rho, const double *in_dev, double *out_dev, int32_t nrhs,
+                              int32_t prec)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        check_prec(prec);
+        OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(std::isfinite(rho), OVL_ERR_ARG, "rho must be finite");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        const size_t FB = field_bytes(ctx->g, prec) * nrhs;
+        void *a = ctx->buf("api_a", FB);
+        void *b = ctx->buf("api_b", FB);
+        pack_spinor(*ctx, in_dev, a, nrhs, prec);
+        launch_K(*ctx, rho, a, b, nrhs, prec);
+        unpack_spinor(*ctx, b, out_dev, nrhs, prec);
+        ctx->prof_collect();
+    });
+}
+
+ovl_status ovl_zolotarev_coeffs(int32_t n_z, double a, double b, ovl_zolo *out_host)
+{
+    return guard([&] {
+        OVL_REQUIRE(out_host != nullptr, OVL_ERR_ARG, "null output");
+        zolotarev(n_z, a, b, *out_host);
+    });
+}
+
+ovl_status ovl_lowmodes_compute(ovl_context *ctx, double rho, int32_t n_low, double tol, double *evals_host,
+                                double *lmax_host)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(n_low >= 1 && n_low <= 256, OVL_ERR_ARG, "n_low must be in [1, 256]");
+        OVL_REQUIRE(tol > 0.0, OVL_ERR_ARG, "tol must be positive");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        lowmodes_compute(*ctx, rho, n_low, tol, evals_host, lmax_host);
+    });
+}
+
+ovl_status ovl_lowmodes_set(ovl_context *ctx, int32_t n, const double *evals_host, const double *evecs_dev)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(n >= 0 && n <= 256, OVL_ERR_ARG, "n must be in [0, 256]");
+        if (n > 0) OVL_REQUIRE(evals_host && evecs_dev, OVL_ERR_ARG, "null low-mode data");
+        if (ctx->low) {
+            OVL_HIP(hipStreamSynchronize(ctx->stream));
+            OVL_HIP(hipFree(ctx->low));
+            ctx->bytes_held -= (int64_t)field_bytes(ctx->g, OVL_F64) * ctx->n_low;
+            ctx->low = nullptr;
+        }
+        ctx->n_low = 0;
+        ctx->low_evals.clear();
+        if (n == 0) return;
+        const size_t FB = field_bytes(ctx->g, OVL_F64);
+        OVL_HIP(hipMalloc(&ctx->low, FB * n));
+        ctx->bytes_held += (int64_t)FB * n;
+        pack_spinor(*ctx, evecs_dev, ctx->low, n, OVL_F64);
+        ctx->low_evals.assign(evals_host, evals_host + n);
+        ctx->n_low = n;
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_lowmodes_get(ovl_context *ctx, double *evecs_dev)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(evecs_dev != nullptr, OVL_ERR_ARG, "null output");
+        if (ctx->n_low > 0) unpack_spinor(*ctx, ctx->low, evecs_dev, ctx->n_low, OVL_F64);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_sign_zolotarev_mscg(ovl_context *ctx, double rho, const ovl_zolo *zolo, const double *in_dev,
+                                   double *out_dev, int32_t nrhs, double eta, int32_t prec, ovl_stats *stats_host)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        check_prec(prec);
+        check_zolo(zolo);
+        OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(eta > 0.0 && std::isfinite(rho), OVL_ERR_ARG, "eta must be positive, rho finite");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        const size_t FB = field_bytes(ctx->g, prec) * nrhs;
+        void *a = ctx->buf("api_a", FB);
+        void *b = ctx->buf("api_b", FB);
+        pack_spinor(*ctx, in_dev, a, nrhs, prec);
+        sign_mscg(*ctx, rho, *zolo, a, b, nrhs, eta, prec, 100000, stats_host);
+        unpack_spinor(*ctx, b, out_dev, nrhs, prec);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->prof_collect();
+    });
+}
+
+ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_zolo *zolo, const double *in_dev,
+                             double *out_dev, int32_t nrhs, double eta, int32_t prec, ovl_stats *stats_host)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        check_prec(prec);
+        check_zolo(zolo);
+        OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(eta > 0.0 && std::isfinite(rho) && mu >= 0.0 && mu < 1.0, OVL_ERR_ARG,
+                    "need eta > 0, finite rho, 0 <= mu < 1");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        const size_t FB = field_bytes(ctx->g, OVL_F64) * nrhs;
+        double2 *a = (double2 *)ctx->buf("api_a64", FB);
+        double2 *b = (double2 *)ctx->buf("api_b64", FB);
+        pack_spinor(*ctx, in_dev, a, nrhs, OVL_F64);
+        overlap_f64(*ctx, rho, mu, *zolo, a, b, nrhs, eta, prec, 100000, stats_host);
+        unpack_spinor(*ctx, b, out_dev, nrhs, OVL_F64);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->prof_collect();
+    });
+}
+
+ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo, const ovl_solver_params *params,
+                                 const double *b_dev, double *x_dev, int32_t nrhs, ovl_stats *stats_host)
+{
+    ovl_status worst = OVL_OK;
+    ovl_status st = guard([&] {
+        check_ctx(ctx);
+        check_zolo(zolo);
+        OVL_REQUIRE(params != nullptr && b_dev && x_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG,
+                    "bad solver arguments");
+        const ovl_solver_params &p = *params;
+        OVL_REQUIRE(p.mu >= 0.0 && p.mu < 1.0 && p.tol > 0.0 && p.eta_tilde > 0.0 && p.relax_floor > 0.0 &&
+                        p.max_outer >= 1 && p.max_middle >= 1 && p.max_mscg >= 1 && p.norm_restart > 0.0,
+                    OVL_ERR_ARG, "invalid solver parameters");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        const size_t FB = field_bytes(ctx->g, OVL_F64);
+        double2 *b = (double2 *)ctx->buf("api_b64", FB);
+        double2 *x = (double2 *)ctx->buf("api_x64", FB);
+        for (int f = 0; f < nrhs; ++f) {
+            ovl_stats *s = stats_host ? stats_host + f : nullptr;
+            if (s) std::memset(s, 0, sizeof(*s));
+            pack_spinor(*ctx, b_dev + (size_t)f * ctx->g.V * 24, b, 1, OVL_F64);
+            const ovl_status r = solve_one(*ctx, *zolo, p, b, x, s);
+            unpack_spinor(*ctx, x, x_dev + (size_t)f * ctx->g.V * 24, 1, OVL_F64);
+            if (r != OVL_OK && worst == OVL_OK) worst = r;
+        }
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->prof_collect();
+        if (worst != OVL_OK) set_error("solver: iteration limit reached");
+    });
+    return st != OVL_OK ? st : worst;
+}
+
+ovl_status ovl_profile_enable(ovl_context *ctx, int32_t on)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        ctx->prof_collect();
+        ctx->prof = on != 0;
+        for (auto &row : ctx->slots)
+            for (auto &s : row) s = ProfileSlot{};
+    });
+}
+
+ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int64_t *launches, double *milliseconds,
+                            double *bytes)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(kernel >= 0 && kernel < KERN_COUNT && prec >= 0 && prec < 3, OVL_ERR_ARG, "bad slot");
+        ctx->prof_collect();
+        const ProfileSlot &s = ctx->slots[kernel][prec];
+        if (launches) *launches = s.launches;
+        if (milliseconds) *milliseconds = s.ms;
+        if (bytes) *bytes = s.bytes;
+    });
+}
+
+}  // extern "C"

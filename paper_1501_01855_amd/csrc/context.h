@@ -1,0 +1,78 @@
+// The library context: one lattice geometry, its gauge field in every
+// precision, the kernel low modes, workspace and profiling state.
+#pragma once
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace ovl {
+
+struct PendingEvent {
+    int kern, prec;
+    double bytes;
+    hipEvent_t a, b;
+};
+
+struct Context {
+    Geom g{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cu = 256;
+
+    // gauge field, packed per precision
+    double2 *U64 = nullptr;   // [4][9][V]
+    float2 *U32 = nullptr;    // [4][9][V]
+    bool have_gauge = false;
+
+    // kernel low modes: FP64 packed [n][12][V] and eigenvalues
+    int n_low = 0;
+    double2 *low = nullptr;
+    std::vector<double> low_evals;
+
+    // named workspace; grows on demand, freed at destroy
+    std::map<std::string, DevBuf> pool;
+    int64_t bytes_held = 0;
+
+    // host staging (pinned)
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+
+    // profiling
+    bool prof = false;
+    std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> free_events;
+    ProfileSlot slots[KERN_COUNT][3];
+    int64_t last_mscg_iters = 0;
+
+    void *buf(const std::string &name, size_t bytes);
+    void *host_stage(size_t bytes);
+    hipEvent_t event();
+    void prof_begin(PendingEvent &pe, int kern, int prec, double bytes);
+    void prof_end(PendingEvent &pe);
+    void prof_collect();
+    ~Context();
+};
+
+// Bytes of one packed spinor field.
+inline size_t field_bytes(const Geom &g, int prec)
+{
+    return prec == OVL_F64 ? (size_t)g.V * 192 : prec == OVL_F32 ? (size_t)g.V * 96 : (size_t)g.V * 52;
+}
+
+// Blocks of 256 threads covering V sites.
+inline unsigned site_blocks(const Geom &g, int nt = 256) { return (unsigned)((g.V + nt - 1) / nt); }
+
+// ---- entry points implemented in the .hip files (host side) -------------
+// pack / unpack between canonical complex128 [nf][V][12] and packed fields.
+void pack_spinor(Context &c, const double *canon, void *packed, int nf, int prec);
+void unpack_spinor(Context &c, const void *packed, double *canon, int nf, int prec);
+void convert_spinor(Context &c, const void *src, int sprec, void *dst, int dprec, int nf);
+void pack_gauge(Context &c, const double *canon);
+
+// stencil: out = H in / K in; nf fields in packed layout of precision prec
+void launch_hop(Context &c, const void *in, void *out, int nf, int prec);
+void launch_K(Context &c, double rho, const void *in, void *out, int nf, int prec);
+
+}  // namespace ovl

@@ -1,0 +1,109 @@
+// Context life cycle, workspace, profiling events.
+#include <cstring>
+
+#include "context.h"
+#include "kernels.h"
+
+namespace ovl {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error() { return g_last_error.c_str(); }
+
+void *Context::buf(const std::string &name, size_t bytes)
+{
+    DevBuf &b = pool[name];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            OVL_HIP(hipStreamSynchronize(stream));
+            OVL_HIP(hipFree(b.p));
+            bytes_held -= (int64_t)b.bytes;
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        hipError_t e = hipMalloc(&b.p, bytes);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            throw Error{OVL_ERR_NOMEM, "workspace '" + name + "': hipMalloc of " + std::to_string(bytes) +
+                                           " bytes failed"};
+        }
+        b.bytes = bytes;
+        bytes_held += (int64_t)bytes;
+    }
+    return b.p;
+}
+
+void *Context::host_stage(size_t bytes)
+{
+    if (pinned_bytes < bytes) {
+        if (pinned) {
+            OVL_HIP(hipStreamSynchronize(stream));
+            OVL_HIP(hipHostFree(pinned));
+            pinned = nullptr;
+        }
+        OVL_HIP(hipHostMalloc(&pinned, bytes, hipHostMallocDefault));
+        pinned_bytes = bytes;
+    }
+    return pinned;
+}
+
+hipEvent_t Context::event()
+{
+    hipEvent_t e;
+    OVL_HIP(hipEventCreate(&e));
+    free_events.push_back(e);   // owned by the context; destroyed at exit
+    return e;
+}
+
+void Context::prof_begin(PendingEvent &pe, int kern, int prec, double bytes)
+{
+    pe.kern = kern;
+    pe.prec = prec;
+    pe.bytes = bytes;
+    OVL_HIP(hipEventCreate(&pe.a));
+    OVL_HIP(hipEventCreate(&pe.b));
+    OVL_HIP(hipEventRecord(pe.a, stream));
+}
+
+void Context::prof_end(PendingEvent &pe)
+{
+    OVL_HIP(hipEventRecord(pe.b, stream));
+    pending.push_back(pe);
+    if (pending.size() > 4096) prof_collect();
+}
+
+void Context::prof_collect()
+{
+    if (pending.empty()) return;
+    OVL_HIP(hipEventSynchronize(pending.back().b));
+    for (auto &pe : pending) {
+        float ms = 0.f;
+        OVL_HIP(hipEventElapsedTime(&ms, pe.a, pe.b));
+        ProfileSlot &s = slots[pe.kern][pe.prec];
+        s.launches += 1;
+        s.ms += ms;
+        s.bytes += pe.bytes;
+        OVL_HIP(hipEventDestroy(pe.a));
+        OVL_HIP(hipEventDestroy(pe.b));
+    }
+    pending.clear();
+}
+
+Context::~Context()
+{
+    hipStreamSynchronize(stream);
+    for (auto &pe : pending) {
+        hipEventDestroy(pe.a);
+        hipEventDestroy(pe.b);
+    }
+    for (auto e : free_events) hipEventDestroy(e);
+    for (auto &kv : pool)
+        if (kv.second.p) hipFree(kv.second.p);
+    if (U64) hipFree(U64);
+    if (U32) hipFree(U32);
+    if (low) hipFree(low);
+    if (pinned) hipHostFree(pinned);
+}
+
+}  // namespace ovl

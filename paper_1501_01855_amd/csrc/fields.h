@@ -1,0 +1,186 @@
+// Device-side field access in the internal (packed) layouts.
+//
+// Spinor fields are site-major structure-of-arrays planes so that a wavefront
+// of 64 consecutive sites reads each plane with one coalesced 16-byte load
+// per lane:
+//   FP64: double2 [12][V]   (plane c = spin*3 + colour holds one complex)
+//   FP32: float4  [6][V]    (plane k holds complex components 2k, 2k+1)
+//   HALF: uint4   [3][V]    (plane k holds 4 complex FP16 values, 4k..4k+3)
+//         + float scale[V]  (the site's largest |real component|)
+// Gauge fields, one plane per complex entry and direction:
+//   FP64: double2 [4][9][V]; FP32: float2 [4][9][V];
+//   HALF: uint4 [4][3][V] + uint2 [4][1][V]... see ld_link below: 18 BF16
+//         values in two uint4 and one uint (36 bytes) per link, stored as
+//         uint4 [4][2][V] and uint32 [4][V].
+#pragma once
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+
+namespace ovl {
+
+// ------------------------------------------------------------------ spinors
+__device__ __forceinline__ void ld_sp(const double2 *__restrict__ p, int64_t V, int64_t s,
+                                      cplx<double> v[12])
+{
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        double2 t = p[c * V + s];
+        v[c] = {t.x, t.y};
+    }
+}
+__device__ __forceinline__ void st_sp(double2 *__restrict__ p, int64_t V, int64_t s,
+                                      const cplx<double> v[12])
+{
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c * V + s] = make_double2(v[c].re, v[c].im);
+}
+__device__ __forceinline__ void ld_sp(const float4 *__restrict__ p, int64_t V, int64_t s,
+                                      cplx<float> v[12])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float4 t = p[k * V + s];
+        v[2 * k] = {t.x, t.y};
+        v[2 * k + 1] = {t.z, t.w};
+    }
+}
+__device__ __forceinline__ void st_sp(float4 *__restrict__ p, int64_t V, int64_t s,
+                                      const cplx<float> v[12])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        p[k * V + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+}
+
+// Number of storage elements of one field per site (planes).
+template <typename ST> struct Planes;
+template <> struct Planes<double2> { static constexpr int n = 12; using R = double; };
+template <> struct Planes<float4> { static constexpr int n = 6; using R = float; };
+
+// ------------------------------------------------------------------ links
+__device__ __forceinline__ void ld_link(const double2 *__restrict__ U, int64_t V, int mu,
+                                        int64_t s, cplx<double> u[9])
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        double2 t = U[(mu * 9 + k) * V + s];
+        u[k] = {t.x, t.y};
+    }
+}
+__device__ __forceinline__ void ld_link(const float2 *__restrict__ U, int64_t V, int mu,
+                                        int64_t s, cplx<float> u[9])
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        float2 t = U[(mu * 9 + k) * V + s];
+        u[k] = {t.x, t.y};
+    }
+}
+
+// ------------------------------------------------------------------ spin algebra
+// Chiral basis: gamma_mu = [[0, A_mu], [B_mu, 0]] in 2x2 spin blocks with
+// A_k = -i s_k, B_k = i s_k = -A_k (k = x, y, z), A_t = B_t = 1, A B = 1.
+// (1 -+ gamma_mu) psi: upper = h = psi_u -+ A psi_d, lower = -+ B h.
+// apply_A: w = A_mu v for a 2-spinor (v0, v1) of colour vectors, component-wise.
+template <int MU, typename R>
+__device__ __forceinline__ void apply_A(const cplx<R> &v0, const cplx<R> &v1, cplx<R> &w0,
+                                        cplx<R> &w1)
+{
+    if constexpr (MU == 0) {          // -i s_x: (-i v1, -i v0)
+        w0 = times_mi(v1);
+        w1 = times_mi(v0);
+    } else if constexpr (MU == 1) {   // -i s_y: (-v1, v0)
+        w0 = -v1;
+        w1 = v0;
+    } else if constexpr (MU == 2) {   // -i s_z: (-i v0, i v1)
+        w0 = times_mi(v0);
+        w1 = times_i(v1);
+    } else {                          // 1
+        w0 = v0;
+        w1 = v1;
+    }
+}
+
+// acc += (1 - gamma_mu) W psi_fwd   (FWD = true,  W = U_mu(x))
+// acc += (1 + gamma_mu) W^+ psi_bwd (FWD = false, W = U_mu(x - mu))
+template <int MU, bool FWD, typename R>
+__device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[9], cplx<R> acc[12])
+{
+    cplx<R> h[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cplx<R> a0, a1;
+        apply_A<MU>(psi[6 + c], psi[9 + c], a0, a1);
+        if constexpr (FWD) {
+            h[c] = psi[c] - a0;
+            h[3 + c] = psi[3 + c] - a1;
+        } else {
+            h[c] = psi[c] + a0;
+            h[3 + c] = psi[3 + c] + a1;
+        }
+    }
+    cplx<R> g[6];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cplx<R> t;
+            if constexpr (FWD) {
+                t = u[a * 3 + 0] * h[sp * 3 + 0];
+                t = t + u[a * 3 + 1] * h[sp * 3 + 1];
+                t = t + u[a * 3 + 2] * h[sp * 3 + 2];
+            } else {
+                t = cmul_conj(u[0 * 3 + a], h[sp * 3 + 0]);
+                t = t + cmul_conj(u[1 * 3 + a], h[sp * 3 + 1]);
+                t = t + cmul_conj(u[2 * 3 + a], h[sp * 3 + 2]);
+            }
+            g[sp * 3 + a] = t;
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = acc[c] + g[c];
+        acc[3 + c] = acc[3 + c] + g[3 + c];
+        if constexpr (MU == 3) {
+            if constexpr (FWD) {          // lower = -g
+                acc[6 + c] = acc[6 + c] - g[c];
+                acc[9 + c] = acc[9 + c] - g[3 + c];
+            } else {                      // lower = +g
+                acc[6 + c] = acc[6 + c] + g[c];
+                acc[9 + c] = acc[9 + c] + g[3 + c];
+            }
+        } else {
+            cplx<R> a0, a1;
+            apply_A<MU>(g[c], g[3 + c], a0, a1);
+            if constexpr (FWD) {          // lower = -B g = A g
+                acc[6 + c] = acc[6 + c] + a0;
+                acc[9 + c] = acc[9 + c] + a1;
+            } else {                      // lower = B g = -A g
+                acc[6 + c] = acc[6 + c] - a0;
+                acc[9 + c] = acc[9 + c] - a1;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ reductions
+// Sum over a 64-lane wavefront, then over the block through LDS.  Every
+// thread of the block must call it; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) r += lds[w];
+    }
+    return r;
+}
+
+}  // namespace ovl

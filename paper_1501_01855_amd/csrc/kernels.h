@@ -1,0 +1,52 @@
+// Host-side launchers of the device kernels, shared by the drivers.
+#pragma once
+#include "context.h"
+
+namespace ovl {
+
+enum Epilogue {
+    EPI_HOP = 0,    // out = H in
+    EPI_K = 1,      // out = K in
+    EPI_K2DOT = 2,  // out = K in + sigma aux, partial[(aux, out)]
+    EPI_KPLUS = 3   // out = K in + aux
+};
+
+template <typename ST>
+struct StencilArgs {
+    Geom g;
+    const ST *in;
+    ST *out;
+    const ST *aux;
+    double diag;     // 4 - rho
+    double sigma;
+    double *partial; // [nf][gridDim.x] (EPI_K2DOT)
+    const int *stop; // per-field: skip when it >= stop[f] (nullable)
+    int it;
+};
+
+void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
+             double sigma, const void *aux, double *partial, const int *stop = nullptr, int it = 0);
+double stencil_bytes(const Geom &g, int prec, int epi);
+
+// ---------------------------------------------------------------- BLAS-1 (packed FP64 fields)
+// All take nf fields; scalars are per field (host arrays of nf complex / real).
+// dots[f] = (x_f, y_f) complex, computed with a fixed reduction order.
+void dot_f64(Context &c, const double2 *x, const double2 *y, int nf, std::vector<cplx<double>> &out);
+void norm2_f64(Context &c, const double2 *x, int nf, std::vector<double> &out);
+// y_f = a_f x_f + b_f y_f (y not read when b_f = 0)
+void axpby_f64(Context &c, const cplx<double> *a, const double2 *x, const cplx<double> *b, double2 *y, int nf);
+// out[row] = sum_i partial[row][i], i < nblk (fixed order)
+void sum_partials(Context &c, const double *partial, int nblk, int rows, double *out);
+// y_f = gamma_5 y_f
+void gamma5_f64(Context &c, double2 *y, int nf);
+// dst = src
+void copy_fields(Context &c, const void *src, void *dst, int nf, int prec);
+void zero_fields(Context &c, void *dst, int nf, int prec);
+
+// multi-dot: out[f][j] = (V_j, x_f) for j < nv (V: nv packed FP64 fields)
+void multidot_f64(Context &c, const double2 *Vb, int nv, const double2 *x, int nf,
+                  std::vector<cplx<double>> &out);
+// x_f += sum_j coef[f][j] V_j
+void multiaxpy_f64(Context &c, const double2 *Vb, int nv, const cplx<double> *coef, double2 *x, int nf);
+
+}  // namespace ovl

@@ -1,0 +1,31 @@
+// Host drivers of the method's steps (each in its own .hip file).
+#pragma once
+#include "context.h"
+
+namespace ovl {
+
+// sign(K) in -> out, packed fields of precision prec (mscg.hip).
+void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
+               double eta, int prec, int maxiter, ovl_stats *st);
+
+// out = D[mu] in, packed FP64 in/out; the sign function in precision prec
+// (conversions at its boundary) (solver.hip).
+void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in,
+                 double2 *out, int nf, double eta, int prec, int maxiter, ovl_stats *st);
+
+// Zolotarev coefficients (zolo.cpp).
+void zolotarev(int nz, double a, double b, ovl_zolo &out);
+
+// GMRESR(relSUMR) for one right-hand side, packed FP64 b and x (solver.hip).
+ovl_status solve_one(Context &c, const ovl_zolo &z, const ovl_solver_params &p, const double2 *b,
+                     double2 *x, ovl_stats *st);
+
+// Kernel low modes (lowmodes.hip).
+void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *evals, double *lmax);
+
+// Generators (gen.hip).
+void gauge_generate(Context &c, uint64_t seed, double eps, double *canon_out);
+void source_generate(Context &c, int kind, uint64_t seed, int64_t site, int spin, int colour,
+                     double *canon_out);
+
+}  // namespace ovl

@@ -242,6 +242,15 @@ def gauge_field(dims, seed, eps, chunk=1 << 18):
     return out.reshape(V, 4, 3, 3)
 
 
+def gauge_links(link_index, seed, eps):
+    """The links with flat indices site*4 + mu only, [n,3,3] (same values as gauge_field)."""
+    idx = np.asarray(link_index, dtype=np.uint64)
+    g = normals(idx, 4, TAG_GAUGE, seed)
+    xr, xi = _su3_algebra(g, eps)
+    ur, ui = su3_exp(xr, xi)
+    return ur + 1j * ui
+
+
 def unit_gauge(dims):
     V = volume(dims)
     return np.broadcast_to(np.eye(3, dtype=np.complex128), (V, 4, 3, 3)).copy()

@@ -1,0 +1,76 @@
+"""GPU parity: Wilson hopping stencil and kernel K (paper Sec. 1, eq. 2) in
+FP64 and FP32 against the oracle, element by element."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.lattice import WilsonKernel
+from gpu_util import max_rel_elem, rel, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+# several tiles plus a ragged tail (V not a multiple of 256), unequal extents
+CASES = [(4, 4, 4, 4), (4, 6, 2, 8), (6, 4, 6, 5), (2, 2, 2, 2)]
+
+
+@pytest.mark.parametrize("dims", CASES)
+def test_hop_and_K_f64(dims):
+    ovl = require_gpu()
+    print("case", dims, flush=True)
+    U = synth.gauge_field(dims, 11, 0.4)
+    ora = WilsonKernel(dims, U, 1.4)
+    psi = np.stack([synth.gaussian_source(dims, s) for s in (1, 2, 3)])
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(U))
+    h = to_host(ctx.wilson_dslash(to_dev(psi)))
+    k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4))
+    for r in range(3):
+        assert max_rel_elem(h[r], ora.hop(psi[r])) < 1e-14
+        assert max_rel_elem(k[r], ora.K(psi[r])) < 1e-14
+
+
+@pytest.mark.parametrize("dims", CASES[:2])
+def test_hop_and_K_f32(dims):
+    ovl = require_gpu()
+    U = synth.gauge_field(dims, 12, 0.4)
+    ora = WilsonKernel(dims, U, 1.4)
+    psi = synth.gaussian_source(dims, 4)
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(U))
+    h = to_host(ctx.wilson_dslash(to_dev(psi), prec=ovl.F32))
+    k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4, prec=ovl.F32))
+    # FP32 storage and arithmetic: a few units of 2^-24 per term, 8 terms
+    assert max_rel_elem(h, ora.hop(psi)) < 2e-6
+    assert max_rel_elem(k, ora.K(psi)) < 2e-6
+    assert rel(k, ora.K(psi)) < 1e-6
+
+
+def test_K_full_size_sampled():
+    """16^3 x 32 (the FP64 solve workload), K on 256 sampled sites vs the oracle."""
+    ovl = require_gpu()
+    dims = (16, 16, 16, 32)
+    V = 16 * 16 * 16 * 32
+    ctx = ovl.Context(dims)
+    Ud = to_dev(np.zeros((V, 4, 3, 3)))
+    ctx.gauge_generate(2, 0.25, out=Ud)
+    U = to_host(Ud)
+    psi = synth.gaussian_source(dims, 102)
+    k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4))
+    ora = WilsonKernel(dims, U, 1.4)
+    rng = np.random.default_rng(0)
+    sites = np.concatenate([[0, V - 1, 15, 16 * 16 * 16 - 1], rng.integers(0, V, 252)])
+    ref = ora.K_sites(psi, sites)
+    assert max_rel_elem(k[sites], ref) < 1e-14
+
+
+def test_gamma5_hermiticity_gpu():
+    """(chi, K psi) = (K chi, psi) for the GPU operator (K Hermitian, Sec. 1)."""
+    ovl = require_gpu()
+    dims = (4, 4, 4, 6)
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(synth.gauge_field(dims, 3, 0.5)))
+    a, b = synth.gaussian_source(dims, 5), synth.gaussian_source(dims, 6)
+    Ka = to_host(ctx.kernel_K_apply(to_dev(a), 1.4))
+    Kb = to_host(ctx.kernel_K_apply(to_dev(b), 1.4))
+    lhs, rhs = np.vdot(a, Kb), np.vdot(Ka, b)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)

@@ -1,0 +1,122 @@
+"""GPU parity: sign(K) by multi-shift CG with exact low modes (Sec. 1 eq. 4,
+Sec. 3 eq. 7), the overlap operator (Sec. 1 eq. 1) and the GMRESR(relSUMR)
+solve (Algs. 1-3) against the oracle on small lattices."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov
+from oracle.lattice import WilsonKernel, norm
+from oracle.zolotarev import Zolotarev
+from gpu_util import rel, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+class Setup:
+    def __init__(self, dims, seed, eps, nz, nlow=0, rho=1.4):
+        self.dims = dims
+        self.U = synth.gauge_field(dims, seed, eps)
+        self.k = WilsonKernel(dims, self.U, rho)
+        w, Q = np.linalg.eigh(self.k.dense("K"))
+        self.w, self.Q = w, Q
+        order = np.argsort(np.abs(w))
+        self.low = None
+        a = np.abs(w).min()
+        if nlow:
+            idx = order[:nlow]
+            self.low = krylov.LowModes(w[idx], Q[:, idx].T.reshape(nlow, self.k.V, 4, 3))
+            a = np.abs(w[order[nlow - 1]])
+        self.z = Zolotarev(nz, a, np.abs(w).max())
+        self.sign = krylov.SignFunction(self.k, self.z, self.low)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    # the plain-method configuration: 4^4, eps 0.3, seed 1, rho 1.4, N_Z = 16
+    return Setup((4, 4, 4, 4), 1, 0.3, 16)
+
+
+def _ctx(ovl, s):
+    ctx = ovl.Context(s.dims)
+    ctx.gauge_load(to_dev(s.U))
+    if s.low is not None:
+        ctx.lowmodes_set(list(s.low.evals), to_dev(s.low.evecs))
+    zg = ovl.zolo_from(s.z.nz, s.z.a, s.z.b, s.z.delta, s.z.omega, s.z.sigma)
+    return ctx, zg
+
+
+def test_sign_f64(c1):
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    psi = np.stack([synth.gaussian_source(c1.dims, 21), synth.z2_source(c1.dims, 22)])
+    out, st = ctx.sign(to_dev(psi), 1.4, zg, 1e-13)
+    got = to_host(out)
+    for r in range(2):
+        ref = c1.sign(psi[r], 1e-13)
+        assert rel(got[r], ref) < 1e-12
+    assert st.mscg_iters > 0
+
+
+def test_sign_lowmodes_f64():
+    ovl = require_gpu()
+    s = Setup((4, 4, 2, 6), 5, 0.5, 12, nlow=6)
+    ctx, zg = _ctx(ovl, s)
+    psi = synth.gaussian_source(s.dims, 23)
+    got = to_host(ctx.sign(to_dev(psi), 1.4, zg, 1e-13)[0])
+    assert rel(got, s.sign(psi, 1e-13)) < 1e-12
+
+
+def test_sign_f32_error(c1):
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    psi = synth.gaussian_source(c1.dims, 24)
+    got = to_host(ctx.sign(to_dev(psi), 1.4, zg, 1e-5, prec=ovl.F32)[0])
+    ref = c1.sign(psi, 1e-14)
+    # asked-for accuracy 1e-5 plus FP32 rounding of the accumulated result
+    assert rel(got, ref) < 1e-5
+
+
+def test_overlap_f64(c1):
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    psi = synth.gaussian_source(c1.dims, 25)
+    got = to_host(ctx.overlap(to_dev(psi), 1.4, 0.05, zg, 1e-13)[0])
+    ref = krylov.Overlap(c1.sign, 0.05)(psi, 1e-13)
+    assert rel(got, ref) < 1e-12
+
+
+def test_zero_source(c1):
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    psi = np.zeros((c1.k.V, 4, 3), complex)
+    got = to_host(ctx.sign(to_dev(psi), 1.4, zg, 1e-10)[0])
+    assert np.all(got == 0)
+
+
+@pytest.mark.parametrize("ladder", ["f64", "mixed"])
+def test_solve_c1(c1, ladder):
+    """GMRESR(relSUMR) on the 4^4 plain-method case: true residual <= 1e-10
+    with the oracle's FP64 D, and agreement with a dense LU solve."""
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    mu = 0.05
+    b = synth.point_source(c1.dims)
+    p = ovl.solver_defaults(rho=1.4, mu=mu, tol=1e-10, eta_tilde=1e-3,
+                            f32_threshold=(1e-6 if ladder == "mixed" else 10.0))
+    x, st, code = ctx.solve(to_dev(b), zg, p)
+    assert code == 0
+    x = to_host(x)
+    D = krylov.Overlap(c1.sign, mu)
+    assert norm(b - D(x, 1e-15)) / norm(b) <= 1e-10
+    n = c1.k.V * 12
+    G5 = np.kron(np.eye(c1.k.V), np.kron(np.diag([1.0, 1, -1, -1]), np.eye(3)))
+    S = c1.Q @ np.diag(np.sign(c1.w)) @ c1.Q.conj().T
+    Dd = 0.5 * (1 + mu) * np.eye(n) + 0.5 * (1 - mu) * G5 @ S
+    xd = np.linalg.solve(Dd, b.reshape(-1))
+    assert rel(x, xd) <= 2e-10 / mu
+    s = st[0]
+    assert s.gmresr_steps >= 1 and s.sumr_iters > 0
+    if ladder == "mixed":
+        assert s.sign_calls[1] > 0          # single-precision sign calls used
+    print("stats", s.as_dict())

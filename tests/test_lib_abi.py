@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every symbol include/ovl.h declares;
+host-only entry points (no GPU needed) agree with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ovl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ovl_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_header_symbols():
+    import paper_1501_01855_amd as ovl
+    L = ovl.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(ovl.EXPORTS) == names
+
+
+@pytest.mark.parametrize("nz,a,b", [(1, 0.3, 5.0), (8, 1.0, 10.0), (16, 0.5, 6.6), (20, 0.05, 6.6)])
+def test_zolotarev_host_matches_oracle(nz, a, b):
+    import paper_1501_01855_amd as ovl
+    from oracle.zolotarev import Zolotarev
+    z = ovl.zolotarev_coeffs(nz, a, b)
+    o = Zolotarev(nz, a, b)
+    assert np.allclose(z.omegas, o.omega, rtol=1e-11, atol=0)
+    assert np.allclose(z.sigmas, o.sigma, rtol=1e-12, atol=0)
+    assert abs(z.delta - o.delta) <= 1e-3 * o.delta + 5e-14
+
+
+def test_argument_errors_are_reported():
+    import paper_1501_01855_amd as ovl
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.zolotarev_coeffs(0, 1.0, 2.0)
+    assert e.value.code == -1
+    with pytest.raises(ovl.OvlError):
+        ovl.zolotarev_coeffs(4, 2.0, 1.0)
+    p = ovl.solver_defaults()
+    assert p.tol == 1e-10 and p.relax_floor == 1e-2 and p.norm_restart == 0.1
