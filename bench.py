@@ -1,0 +1,195 @@
+"""Benchmark: overlap solves per second at a 1e-10 residual on one MI355X.
+
+Workload (one "step" = one complete GMRESR(relSUMR) solve of D[mu] x = b):
+16^3 x 32 lattice, links exp(i 0.25 A) (seed 2), K = gamma_5 D_W(-1.4),
+mu = 0.02, order-20 Zolotarev sign function with the 10 lowest kernel modes
+treated exactly, one complex Gaussian source (seed 102), target
+||b - D x|| <= 1e-10 ||b||.  Set-up (gauge field, low modes, coefficients)
+is outside the timed region.  The headline value is the mixed-precision
+solver (single-precision sign function whenever the accuracy asked for is
+looser than 1e-6); the same solve with an all-FP64 sign function is timed
+beside it.  The Wilson stencil is also timed alone on 32^3 x 64 in FP32
+(working set beyond the 256 MB Infinity Cache) for its HBM bandwidth.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "overlap solves/s at 1e-10 resid (mixed vs FP64) + Dslash HBM GB/s % peak"
+HBM_PEAK_GBS = 8000.0
+DIMS = (16, 16, 16, 32)
+RHO, MU, NZ, NLOW, TOL = 1.4, 0.02, 20, 10, 1e-10
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-dslash", action="store_true", help="skip the stand-alone stencil timing")
+    return ap.parse_args()
+
+
+def solve_params(ovl, mixed):
+    return ovl.solver_defaults(rho=RHO, mu=MU, tol=TOL, eta_tilde=1e-3, relax_floor=1e-2,
+                               f32_threshold=(1e-6 if mixed else 10.0), max_outer=16,
+                               max_middle=4000, max_mscg=20000)
+
+
+def time_solves(torch, ctx, ovl, b, zolo, params, steps, warmup):
+    for _ in range(warmup):
+        ctx.solve(b, zolo, params)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    stats = []
+    x = None
+    for _ in range(steps):
+        x, st, _ = ctx.solve(b, zolo, params)
+        stats.append(st[0].as_dict())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {k: [ctx.profile_read(k, p) for p in range(3)] for k in (ovl.KERN_STENCIL, ovl.KERN_SHIFT)}
+    ctx.profile(False)
+    return dt, stats, prof, x
+
+
+def kernel_summary(prof):
+    out = {}
+    for name, k in (("stencil", 0), ("shift_update", 1)):
+        ms = sum(p["ms"] for p in prof[k])
+        n = sum(p["launches"] for p in prof[k])
+        by = sum(p["bytes"] for p in prof[k])
+        out[name] = {"launches": n, "ms": ms, "bytes": by,
+                     "avg_us": 1e3 * ms / n if n else None,
+                     "GBps": by / (ms * 1e6) if ms else None,
+                     "by_prec": [{"launches": p["launches"], "ms": p["ms"],
+                                  "GBps": p["bytes"] / (p["ms"] * 1e6) if p["ms"] else None}
+                                 for p in prof[k]]}
+    return out
+
+
+def dslash_alone(torch, ovl, reps=50):
+    """Stencil alone, 32^3 x 64 FP32, the multi-shift CG's second K (K t + sigma p
+    with its fused dot) and the plain hopping term; HIP events around each launch."""
+    dims = (32, 32, 32, 64)
+    ctx = ovl.Context(dims)
+    ctx.gauge_generate(5, 0.25)
+    psi = ctx.source(ovl.SRC_GAUSS, seed=7)
+    for prec in (ovl.F32,):
+        ctx.wilson_dslash(psi, prec)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.wilson_dslash(psi, ovl.F32)
+    torch.cuda.synchronize()
+    p = ctx.profile_read(ovl.KERN_STENCIL, ovl.F32)
+    ctx.profile(False)
+    gbs = p["bytes"] / (p["ms"] * 1e6)
+    res = {"lattice": "32^3x64", "prec": "f32", "launches": p["launches"],
+           "avg_us": 1e3 * p["ms"] / p["launches"], "bytes_per_launch": p["bytes"] / p["launches"],
+           "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    ctx.close()
+    return res
+
+
+def cpu_baseline(mscg_iters_per_solve):
+    """The oracle (FP64, C stencil + numpy) on a bounded sample of the same
+    workload: 12 multi-shift CG iterations with all 20 shifts active on the
+    16^3 x 32 field, scaled by the GPU solve's multi-shift iteration count."""
+    import numpy as np
+    import synth
+    from oracle import krylov
+    from oracle.lattice import WilsonKernel
+    from oracle.zolotarev import Zolotarev
+    U = synth.gauge_field(DIMS, 2, 0.25)
+    k = WilsonKernel(DIMS, U, RHO)
+    z = Zolotarev(NZ, 0.6, 8.0 - RHO)
+    b = synth.gaussian_source(DIMS, 102)
+    iters = 12
+    t0 = time.perf_counter()
+    krylov.multishift_cg(k.K2s, z.sigma, b, np.full(NZ, 1e-300), maxiter=iters)
+    dt = time.perf_counter() - t0
+    per_iter = dt / iters
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / (per_iter * mscg_iters_per_solve), "unit": "solves/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{iters} multi-shift CG iterations (20 shifts active) of the oracle on the "
+                      f"16^3x32 field in {dt:.1f} s, scaled by the {mscg_iters_per_solve} multi-shift "
+                      f"iterations the GPU solve takes (an upper bound on the oracle's rate: fewer "
+                      f"shifts stay active in a real solve)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1501_01855_amd as ovl
+
+    ctx = ovl.Context(DIMS)
+    ctx.gauge_generate(2, 0.25)
+    ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)
+    a = max(abs(e) for e in ev)
+    zolo = ovl.zolotarev_coeffs(NZ, a, lmax)
+    b = ctx.source(ovl.SRC_GAUSS, seed=102)
+
+    dt_mix, st_mix, prof_mix, x_mix = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, True),
+                                                  args.steps, args.warmup)
+    dt_64, st_64, prof_64, x_64 = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, False),
+                                              max(1, args.steps), 0)
+    # true residuals with the FP64 operator at full accuracy (not timed)
+    def true_res(x):
+        Dx, _ = ctx.overlap(x, RHO, MU, zolo, 1e-13)
+        return float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b))
+    res_mix, res_64 = true_res(x_mix), true_res(x_64)
+
+    ks = kernel_summary(prof_mix)
+    dom = max(ks, key=lambda k: ks[k]["ms"])
+    d = ks[dom]
+    achieved = d["GBps"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None}
+    out = {
+        "metric": METRIC,
+        "value": args.steps / dt_mix,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt_mix / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "overlap solve 16^3x32, rho=1.4, mu=0.02, N_Z=20, 10 exact kernel modes, "
+                               "Gaussian source, GMRESR(relSUMR) to 1e-10",
+                   "global_batch": 1, "lattice": "16x16x16x32", "parallelism": "single GPU"},
+        "fp64_solves_per_s": max(1, args.steps) / dt_64,
+        "mixed_over_fp64": (args.steps / dt_mix) / (max(1, args.steps) / dt_64),
+        "true_relres": {"mixed": res_mix, "fp64": res_64},
+        "solve_stats": {"mixed": st_mix[-1], "fp64": st_64[-1]},
+        "kernels_mixed": ks,
+        "kernels_fp64": kernel_summary(prof_64),
+        "roofline": roofline,
+    }
+    ctx.close()
+    if not args.no_dslash:
+        out["dslash_hbm"] = dslash_alone(torch, ovl)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(st_64[-1]["mscg_iters"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libovl.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["context.hip", "dslash.hip", "blas.hip", "mscg.hip", "solver.hip", "zolo.cpp",
+SOURCES = ["context.hip", "dslash.hip", "blas.hip", "mscg.hip", "solver.hip", "zolo.cpp", "dense.cpp",
            "gen.hip", "lowmodes.hip", "capi.hip"]
 ARCH = os.environ.get("OVL_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -214,3 +214,33 @@ void multiaxpy_f64(Context &c, const double2 *Vb, int nv, const cplx<double> *co
 }
 
 }  // namespace ovl
+
+namespace ovl {
+
+// out = a A + b B + g C over nf whole fields (real coefficients); C may be null.
+__global__ __launch_bounds__(256) void k_lincomb3(double a, const double2 *__restrict__ A, double b,
+                                                  const double2 *__restrict__ B, double g,
+                                                  const double2 *__restrict__ C, double2 *__restrict__ out,
+                                                  int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 x = A[i], y = B[i];
+    double re = a * x.x + b * y.x, im = a * x.y + b * y.y;
+    if (C != nullptr) {
+        const double2 z = C[i];
+        re += g * z.x;
+        im += g * z.y;
+    }
+    out[i] = make_double2(re, im);
+}
+
+void lincomb3_f64(Context &c, double a, const double2 *A, double b, const double2 *B, double g, const double2 *C,
+                  double2 *out, int nf)
+{
+    const int64_t n = 12 * c.g.V * (int64_t)nf;
+    k_lincomb3<<<(unsigned)((n + 255) / 256), 256, 0, c.stream>>>(a, A, b, B, g, C, out, n);
+    OVL_HIP(hipGetLastError());
+}
+
+}  // namespace ovl

@@ -37,6 +37,9 @@ void norm2_f64(Context &c, const double2 *x, int nf, std::vector<double> &out);
 void axpby_f64(Context &c, const cplx<double> *a, const double2 *x, const cplx<double> *b, double2 *y, int nf);
 // out[row] = sum_i partial[row][i], i < nblk (fixed order)
 void sum_partials(Context &c, const double *partial, int nblk, int rows, double *out);
+// out = a A + b B + g C over nf whole fields (real coefficients; C nullable)
+void lincomb3_f64(Context &c, double a, const double2 *A, double b, const double2 *B, double g, const double2 *C,
+                  double2 *out, int nf);
 // y_f = gamma_5 y_f
 void gamma5_f64(Context &c, double2 *y, int nf);
 // dst = src

@@ -1,13 +1,178 @@
-// Kernel low modes (placeholder until the eigensolver lands).
+// Kernel low modes: the n_low eigenpairs of K with the smallest |lambda|,
+// which the sign function treats exactly (paper Sec. 1 after eq. 4; Sec. 3:
+// a^2 is the largest squared eigenvalue so deflated).  Set-up work, once per
+// gauge field.
+//
+// Method: Chebyshev-filtered subspace iteration (Zhou & Saad) on K^2 in FP64
+// with a block of nb > n_low vectors.  Each sweep applies the degree-m
+// Chebyshev polynomial that damps [a_cut, b_up] of the K^2 spectrum
+// (b_up = (8 - rho)^2 bounds it for unitary links, a_cut is the largest Ritz
+// value of the block), orthonormalises the block by Cholesky QR (twice), and
+// does a Rayleigh-Ritz step with K^2 (whose wanted eigenvalues are the
+// smallest of a positive spectrum; a Rayleigh-Ritz step with the indefinite K
+// would produce spurious Ritz values inside its spectral gap).  Once the
+// leading K^2 pairs have converged, K is diagonalised inside their span to
+// obtain eigenvectors of K with signed eigenvalues.  The multi-field stencil
+// applies K to the whole block in one launch.  Stops when every wanted pair
+// has ||K v - lambda v|| <= tol.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
 #include "context.h"
+#include "dense.h"
+#include "kernels.h"
 #include "ops.h"
 
 namespace ovl {
 
+using dense::zc;
+
+static void applyK(Context &c, double rho, const double2 *X, double2 *Y, int nb)
+{
+    stencil(c, EPI_K, OVL_F64, X, Y, nb, rho, 0.0, nullptr, nullptr);
+}
+
+// G[i][j] = (X_i, Y_j), nx x ny
+static std::vector<zc> gram(Context &c, const double2 *X, int nx, const double2 *Y, int ny)
+{
+    std::vector<cplx<double>> d;
+    multidot_f64(c, X, nx, Y, ny, d);   // d[f * nx + j] = (X_j, Y_f)
+    std::vector<zc> G((size_t)nx * ny);
+    for (int f = 0; f < ny; ++f)
+        for (int j = 0; j < nx; ++j) G[(size_t)j * ny + f] = zc(d[(size_t)f * nx + j].re, d[(size_t)f * nx + j].im);
+    return G;
+}
+
+// Z_k = sum_j W[j][k] Y_j, W is nY x nZ
+static void rotate(Context &c, const double2 *Y, int nY, const std::vector<zc> &W, double2 *Z, int nZ)
+{
+    zero_fields(c, Z, nZ, OVL_F64);
+    std::vector<cplx<double>> coef((size_t)nZ * nY);
+    for (int k = 0; k < nZ; ++k)
+        for (int j = 0; j < nY; ++j) coef[(size_t)k * nY + j] = {W[(size_t)j * nZ + k].real(), W[(size_t)j * nZ + k].imag()};
+    multiaxpy_f64(c, Y, nY, coef.data(), Z, nZ);
+}
+
+// Y <- Y R^{-1} with Y^H Y = R^H R (into Q), twice for orthogonality to rounding.
+static void chol_qr(Context &c, double2 *Y, double2 *Q, int nb)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+        const std::vector<zc> G = gram(c, Y, nb, Y, nb);
+        std::vector<zc> R;
+        OVL_REQUIRE(dense::cholesky_upper(nb, G, R), OVL_ERR_BREAKDOWN,
+                    "low-mode block lost rank (Cholesky QR failed)");
+        rotate(c, Y, nb, dense::inv_upper(nb, R), Q, nb);
+        copy_fields(c, Q, Y, nb, OVL_F64);
+    }
+}
+
 void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *evals, double *lmax)
 {
-    (void)c; (void)rho; (void)n_low; (void)tol; (void)evals; (void)lmax;
-    throw Error{OVL_ERR_UNSUPPORTED, "lowmodes_compute: not built yet"};
+    const Geom &g = c.g;
+    const size_t FB = field_bytes(g, OVL_F64);
+    // a block well beyond n_low: synthetic near-unit gauge fields have
+    // clusters of dozens of almost degenerate low modes (the doublers)
+    const int nb = (int)std::min<int64_t>(n_low + std::max(48, n_low), 12 * g.V - 1);
+    OVL_REQUIRE(n_low < nb, OVL_ERR_ARG, "n_low too large for this lattice");
+    double2 *X = (double2 *)c.buf("lm_X", FB * nb);
+    double2 *Y = (double2 *)c.buf("lm_Y", FB * nb);
+    double2 *Z = (double2 *)c.buf("lm_Z", FB * nb);
+    double2 *T = (double2 *)c.buf("lm_T", FB * nb);
+    double2 *T2 = (double2 *)c.buf("lm_T2", FB * nb);
+    double *canon = (double *)c.buf("lm_canon", FB);
+    for (int i = 0; i < nb; ++i) {
+        source_generate(c, OVL_SRC_GAUSS, 0x5EED0000ull + (uint64_t)i, 0, 0, 0, canon);
+        pack_spinor(c, canon, X + (size_t)i * 12 * g.V, 1, OVL_F64);
+    }
+    const double b_up = (8.0 - rho) * (8.0 - rho) * 1.0001;
+    const int degree = 32;
+    double a_cut = 0.0;
+    bool converged = false;
+    std::vector<double> theta;
+    for (int sweep = 0; sweep < 200 && !converged; ++sweep) {
+        if (sweep > 0) {
+            // Chebyshev filter of K^2 damping [a_cut, b_up] (scaled three-term recurrence)
+            const double e = 0.5 * (b_up - a_cut), cc = 0.5 * (b_up + a_cut);
+            double sigma = e / (0.0 - cc);
+            const double tau = 2.0 / sigma;
+            applyK(c, rho, X, T2, nb);
+            applyK(c, rho, T2, T, nb);                      // T = K^2 X
+            lincomb3_f64(c, sigma / e, T, -cc * sigma / e, X, 0.0, nullptr, Y, nb);
+            for (int i = 2; i <= degree; ++i) {
+                const double sn = 1.0 / (tau - sigma);
+                applyK(c, rho, Y, T2, nb);
+                applyK(c, rho, T2, T, nb);                  // T = K^2 Y
+                lincomb3_f64(c, 2.0 * sn / e, T, -2.0 * sn * cc / e, Y, -sigma * sn, X, Z, nb);
+                std::swap(X, Y);                            // X <- Y
+                std::swap(Y, Z);                            // Y <- Y_new
+                sigma = sn;
+            }
+            copy_fields(c, Y, X, nb, OVL_F64);
+        }
+        chol_qr(c, X, Z, nb);
+        // Rayleigh-Ritz with K^2 (the wanted end of a positive spectrum)
+        applyK(c, rho, X, T, nb);                           // T  = K X
+        applyK(c, rho, T, T2, nb);                          // T2 = K^2 X
+        std::vector<double> w2;
+        std::vector<zc> W;
+        dense::eigh(nb, gram(c, X, nb, T2, nb), w2, W);
+        rotate(c, X, nb, W, Y, nb);
+        rotate(c, T, nb, W, Z, nb);
+        rotate(c, T2, nb, W, T, nb);
+        std::swap(X, Y);            // X: Ritz vectors of K^2
+        std::swap(T, Z);            // T: K X ; Z: K^2 X
+        int nc = 0;                 // leading converged K^2 pairs
+        while (nc < nb) {
+            lincomb3_f64(c, 1.0, Z + (size_t)nc * 12 * g.V, -w2[nc], X + (size_t)nc * 12 * g.V, 0.0, nullptr, T2, 1);
+            std::vector<double> n2;
+            norm2_f64(c, T2, 1, n2);
+            if (!(std::sqrt(n2[0]) <= tol * std::max(1.0, w2[nc]))) break;
+            ++nc;
+        }
+        a_cut = std::min(w2[nb - 1], 0.5 * b_up);
+        if (nc < n_low) continue;
+        // eigenvectors of K inside the converged K^2 subspace (signs of lambda)
+        std::vector<double> th;
+        std::vector<zc> Wk;
+        dense::eigh(nc, gram(c, X, nc, T, nc), th, Wk);
+        std::vector<int> ord(nc);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(th[a]) < std::fabs(th[b]); });
+        std::vector<zc> Wo((size_t)nc * n_low);
+        theta.assign(n_low, 0.0);
+        for (int k = 0; k < n_low; ++k) {
+            theta[k] = th[ord[k]];
+            for (int j = 0; j < nc; ++j) Wo[(size_t)j * n_low + k] = Wk[(size_t)j * nc + ord[k]];
+        }
+        rotate(c, X, nc, Wo, Y, n_low);
+        rotate(c, T, nc, Wo, T2, n_low);
+        double worst = 0.0;
+        for (int k = 0; k < n_low; ++k) {
+            lincomb3_f64(c, 1.0, T2 + (size_t)k * 12 * g.V, -theta[k], Y + (size_t)k * 12 * g.V, 0.0, nullptr,
+                         Z + (size_t)k * 12 * g.V, 1);
+            std::vector<double> n2;
+            norm2_f64(c, Z + (size_t)k * 12 * g.V, 1, n2);
+            worst = std::max(worst, std::sqrt(n2[0]));
+        }
+        converged = worst <= tol;
+    }
+    OVL_REQUIRE(converged, OVL_ERR_NOT_CONVERGED, "low-mode eigensolver did not reach its tolerance");
+    if (c.low) {
+        OVL_HIP(hipStreamSynchronize(c.stream));
+        OVL_HIP(hipFree(c.low));
+        c.bytes_held -= (int64_t)FB * c.n_low;
+        c.low = nullptr;
+    }
+    OVL_HIP(hipMalloc(&c.low, FB * n_low));
+    c.bytes_held += (int64_t)FB * n_low;
+    copy_fields(c, Y, c.low, n_low, OVL_F64);
+    c.n_low = n_low;
+    c.low_evals = theta;
+    OVL_HIP(hipStreamSynchronize(c.stream));
+    if (evals)
+        for (int k = 0; k < n_low; ++k) evals[k] = theta[k];
+    if (lmax) *lmax = 8.0 - rho;
 }
 
 }  // namespace ovl
