@@ -35,7 +35,31 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-dslash", action="store_true", help="skip the stand-alone stencil timing")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for hardware counters: one 1 GiB device copy (calibration) "
+                         "and one single-precision sign-function call on the 16^3x32 workload")
     return ap.parse_args()
+
+
+def profile_run(torch, ovl):
+    ctx = ovl.Context(DIMS)
+    ctx.gauge_generate(2, 0.25)
+    ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)
+    zolo = ovl.zolotarev_coeffs(NZ, max(abs(e) for e in ev), lmax)
+    b = ctx.source(ovl.SRC_GAUSS, seed=102)
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    _, st = ctx.sign(b, RHO, zolo, 1e-4, prec=ovl.F32)
+    torch.cuda.synchronize()
+    out = {"copy_bytes": 2 * src.numel() * 8, "mscg_iters": st.mscg_iters,
+           "stencil": ctx.profile_read(ovl.KERN_STENCIL, ovl.F32),
+           "shift_update": ctx.profile_read(ovl.KERN_SHIFT, ovl.F32)}
+    print(json.dumps(out))
 
 
 def solve_params(ovl, mixed):
@@ -136,6 +160,9 @@ def main():
     import torch
     import paper_1501_01855_amd as ovl
 
+    if args.profile_run:
+        profile_run(torch, ovl)
+        return
     ctx = ovl.Context(DIMS)
     ctx.gauge_generate(2, 0.25)
     ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)

@@ -46,7 +46,14 @@ struct Context {
     ProfileSlot slots[KERN_COUNT][3];
     int64_t last_mscg_iters = 0;
 
+    unsigned *grid_counters = nullptr;   // zero between launches (reset by the last block)
+
+    // stencil launch variant per (precision, epilogue, nf), chosen by timing
+    std::map<int, int> tuned;
+    int autotune = 1;
+
     void *buf(const std::string &name, size_t bytes);
+    void *counters();
     void *host_stage(size_t bytes);
     hipEvent_t event();
     void prof_begin(PendingEvent &pe, int kern, int prec, double bytes);

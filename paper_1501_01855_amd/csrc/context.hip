@@ -34,6 +34,16 @@ void *Context::buf(const std::string &name, size_t bytes)
     return b.p;
 }
 
+void *Context::counters()
+{
+    if (!grid_counters) {
+        OVL_HIP(hipMalloc(&grid_counters, 64 * sizeof(unsigned)));
+        OVL_HIP(hipMemsetAsync(grid_counters, 0, 64 * sizeof(unsigned), stream));
+        OVL_HIP(hipStreamSynchronize(stream));
+    }
+    return grid_counters;
+}
+
 void *Context::host_stage(size_t bytes)
 {
     if (pinned_bytes < bytes) {
@@ -104,6 +114,7 @@ Context::~Context()
     if (U32) hipFree(U32);
     if (low) hipFree(low);
     if (pinned) hipHostFree(pinned);
+    if (grid_counters) hipFree(grid_counters);
 }
 
 }  // namespace ovl

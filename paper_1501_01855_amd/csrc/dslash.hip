@@ -141,40 +141,45 @@ void pack_gauge(Context &c, const double *canon)
 }
 
 // ------------------------------------------------------------- stencil kernel
-template <typename ST, typename GT, int EPI>
-__global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__restrict__ U)
+// TPS threads per site: with TPS = 2 a block covers 128 sites; waves 0-1
+// gather directions {x, y} and waves 2-3 directions {z, t} for the same sites
+// (no divergence inside a wave), exchange half accumulators through LDS, and
+// each thread finishes and stores half of the output spinor -- twice the
+// threads for small lattices.
+template <int MU, typename R, typename ST, typename GT>
+__device__ __forceinline__ void gather_dir(const ST *__restrict__ in, const GT *__restrict__ U, int64_t V, int64_t s,
+                                           int32_t c, int32_t Lm, int64_t st, cplx<R> acc[12])
 {
-    using R = typename Planes<ST>::R;
-    constexpr int NP = Planes<ST>::n;
-    if (a.stop != nullptr && a.it >= a.stop[blockIdx.y]) return;
-    const int64_t V = a.g.V;
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int f = blockIdx.y;
-    const bool valid = s < V;
-    const ST *in = a.in + (int64_t)f * NP * V;
-    double part = 0.0;
-    if (valid) {
-        const int32_t L0 = a.g.L[0], L1 = a.g.L[1], L2 = a.g.L[2], L3 = a.g.L[3];
-        const int32_t si = (int32_t)s;
-        int32_t co[4];
-        co[0] = si % L0;
-        int32_t rem = si / L0;
-        co[1] = rem % L1;
-        rem /= L1;
-        co[2] = rem % L2;
-        co[3] = rem / L2;
-        const int32_t Ls[4] = {L0, L1, L2, L3};
-        cplx<R> acc[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+    cplx<R> psi[12];
+    cplx<R> u[9];
+    const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st : s + st;
+    const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st : s - st;
+    ld_sp(in, V, fwd, psi);
+    ld_link(U, V, MU, s, u);
+    hop_term<MU, true>(psi, u, acc);
+    ld_sp(in, V, bwd, psi);
+    ld_link(U, V, MU, bwd, u);
+    hop_term<MU, false>(psi, u, acc);
+}
+
+// Directions MU0..MU1.  Four directions run as a non-unrolled loop (bounded
+// register use); two are unrolled.
+template <int MU0, int MU1, typename R, typename ST, typename GT>
+__device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__restrict__ U, int64_t V, int64_t s,
+                                       const int32_t co[4], const int32_t Ls[4], const int64_t st[4],
+                                       cplx<R> acc[12])
+{
+    if constexpr (MU1 - MU0 == 1) {
+        gather_dir<MU0, R>(in, U, V, s, co[MU0], Ls[MU0], st[MU0], acc);
+        gather_dir<MU1, R>(in, U, V, s, co[MU1], Ls[MU1], st[MU1], acc);
+    } else {
         cplx<R> psi[12];
         cplx<R> u[9];
 #pragma unroll 1
-        for (int mu = 0; mu < 4; ++mu) {
-            const int64_t st = a.g.stride[mu];
+        for (int mu = MU0; mu <= MU1; ++mu) {
             const int32_t c = co[mu], Lm = Ls[mu];
-            const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st : s + st;
-            const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st : s - st;
+            const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st[mu] : s + st[mu];
+            const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st[mu] : s - st[mu];
             ld_sp(in, V, fwd, psi);
             ld_link(U, V, mu, s, u);
             switch (mu) {
@@ -192,55 +197,178 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
             default: hop_term<3, false>(psi, u, acc); break;
             }
         }
+    }
+}
+
+template <typename ST, typename GT, int EPI, int TPS, bool REMAP>
+__global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__restrict__ U)
+{
+    using R = typename Planes<ST>::R;
+    constexpr int NP = Planes<ST>::n;
+    constexpr int NC = 12 / TPS;   // complex components owned by one lane
+    unsigned tile, f;
+    tile_of_block<REMAP>(tile, f);
+    if (a.stop != nullptr && a.it >= a.stop[f]) return;   // field already converged
+    const int64_t V = a.g.V;
+    const int64_t s = (int64_t)tile * (256 / TPS) + (TPS == 2 ? (threadIdx.x & 127) : threadIdx.x);
+    const int half = TPS == 2 ? (int)(threadIdx.x >> 7) : 0;
+    const bool valid = s < V;
+    const ST *in = a.in + (int64_t)f * NP * V;
+    double part = 0.0;
+    cplx<R> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+    if (valid) {
+        const int32_t L0 = a.g.L[0], L1 = a.g.L[1], L2 = a.g.L[2], L3 = a.g.L[3];
+        const int32_t si = (int32_t)s;
+        int32_t co[4];
+        co[0] = si % L0;
+        int32_t rem = si / L0;
+        co[1] = rem % L1;
+        rem /= L1;
+        co[2] = rem % L2;
+        co[3] = rem / L2;
+        const int32_t Ls[4] = {L0, L1, L2, L3};
+        const int64_t st[4] = {a.g.stride[0], a.g.stride[1], a.g.stride[2], a.g.stride[3]};
+        if constexpr (TPS == 1) {
+            gather<0, 3, R>(in, U, V, s, co, Ls, st, acc);
+        } else {
+            if (half == 0)
+                gather<0, 1, R>(in, U, V, s, co, Ls, st, acc);
+            else
+                gather<2, 3, R>(in, U, V, s, co, Ls, st, acc);
+        }
+    }
+    if constexpr (TPS == 2) {
+        // half h keeps components [6h, 6h+6) and receives the partner's
+        __shared__ cplx<R> xch[2][6][128];
+        const int lane = threadIdx.x & 127;
+        const bool hi = half != 0;   // wave-uniform
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            xch[half][c][lane].re = hi ? acc[c].re : acc[6 + c].re;
+            xch[half][c][lane].im = hi ? acc[c].im : acc[6 + c].im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const R mr = hi ? acc[6 + c].re : acc[c].re;
+            const R mi = hi ? acc[6 + c].im : acc[c].im;
+            const cplx<R> o = xch[1 - half][c][lane];
+            acc[c] = {mr + o.re, mi + o.im};   // own half now in acc[0..6)
+        }
+    }
+    if (valid) {
+        cplx<R> o[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) o[c] = acc[c];
         ST *out = a.out + (int64_t)f * NP * V;
         if constexpr (EPI == EPI_HOP) {
-            st_sp(out, V, s, acc);
+            if constexpr (TPS == 1) st_sp(out, V, s, o); else st_sp_half(out, V, s, half, o);
         } else {
             // D_W psi = (4 - rho) psi - H psi / 2, then gamma_5 (negate spins 2, 3)
-            ld_sp(in, V, s, psi);
-            const R m = (R)a.diag, h = (R)0.5;
+            cplx<R> x[NC];
+            if constexpr (TPS == 1) ld_sp(in, V, s, x); else ld_sp_half(in, V, s, half, x);
+            const R m = (R)a.diag, hh = (R)0.5;
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                cplx<R> d = m * psi[c] - h * acc[c];
-                acc[c] = (c < 6) ? d : -d;
+            for (int c = 0; c < NC; ++c) {
+                const int cg = TPS == 1 ? c : 6 * half + c;
+                const cplx<R> d = m * x[c] - hh * o[c];
+                o[c] = (cg < 6) ? d : -d;
             }
-            if constexpr (EPI == EPI_K2DOT) {
-                // w = K t + sigma p ; partial (p, w)
-                ld_sp(a.aux + (int64_t)f * NP * V, V, s, psi);
-                const R sg = (R)a.sigma;
-                double d = 0.0;
+            if constexpr (EPI == EPI_K2DOT || EPI == EPI_KPLUS) {
+                const ST *aux = a.aux + (int64_t)f * NP * V;
+                if constexpr (TPS == 1) ld_sp(aux, V, s, x); else ld_sp_half(aux, V, s, half, x);
+                if constexpr (EPI == EPI_K2DOT) {
+                    // w = K t + sigma p ; partial (p, w)
+                    const R sg = (R)a.sigma;
+                    double d = 0.0;
 #pragma unroll
-                for (int c = 0; c < 12; ++c) {
-                    acc[c] = acc[c] + sg * psi[c];
-                    d += (double)psi[c].re * (double)acc[c].re + (double)psi[c].im * (double)acc[c].im;
+                    for (int c = 0; c < NC; ++c) {
+                        o[c] = o[c] + sg * x[c];
+                        d += (double)x[c].re * (double)o[c].re + (double)x[c].im * (double)o[c].im;
+                    }
+                    part = d;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) o[c] = o[c] + x[c];
                 }
-                part = d;
-            } else if constexpr (EPI == EPI_KPLUS) {
-                ld_sp(a.aux + (int64_t)f * NP * V, V, s, psi);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) acc[c] = acc[c] + psi[c];
             }
-            st_sp(out, V, s, acc);
+            if constexpr (TPS == 1) st_sp(out, V, s, o); else st_sp_half(out, V, s, half, o);
         }
     }
     if constexpr (EPI == EPI_K2DOT) {
         __shared__ double lds[4];
         const double t = block_sum<256>(part, lds);
-        if (threadIdx.x == 0) a.partial[(int64_t)f * gridDim.x + blockIdx.x] = t;
+        if (threadIdx.x == 0) a.partial[(int64_t)f * gridDim.x + tile] = t;
     }
+}
+
+// Launch shape chosen per (precision, epilogue, nf) by timing the variants on
+// the context's lattice the first time that shape is used (autotuning).
+template <typename ST, typename GT, int EPI, int TPS, bool REMAP>
+static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf)
+{
+    dim3 grid((unsigned)((c.g.V * TPS + 255) / 256), nf);
+    k_stencil<ST, GT, EPI, TPS, REMAP><<<grid, 256, 0, c.stream>>>(a, U);
+}
+
+template <typename ST, typename GT, int EPI>
+static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT *U, int nf)
+{
+    switch (id) {
+    case 0: launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf); break;
+    case 1: launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf); break;
+    case 2: launch_variant<ST, GT, EPI, 2, false>(c, a, U, nf); break;
+    default: launch_variant<ST, GT, EPI, 2, true>(c, a, U, nf); break;
+    }
+}
+
+static constexpr int N_VARIANTS = 4;
+
+template <typename ST, typename GT, int EPI>
+static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, int prec)
+{
+    const int key = (prec * 8 + EPI) * 64 + (nf < 63 ? nf : 63);
+    auto it = c.tuned.find(key);
+    if (it != c.tuned.end()) return it->second;
+    if (c.autotune == 0) return c.tuned[key] = 1;
+    // time every variant on scratch output
+    StencilArgs<ST> t = a;
+    t.stop = nullptr;
+    t.out = (ST *)c.buf("tune_out", field_bytes(c.g, prec) * nf);
+    t.partial = (double *)c.buf("tune_part", sizeof(double) * (size_t)nf * (c.g.V * 2 / 256 + 1));
+    hipEvent_t e0 = c.event(), e1 = c.event();
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int v = 0; v < N_VARIANTS; ++v) {
+        launch_by_id<ST, GT, EPI>(c, v, t, U, nf);   // warm-up
+        OVL_HIP(hipEventRecord(e0, c.stream));
+        for (int r = 0; r < 5; ++r) launch_by_id<ST, GT, EPI>(c, v, t, U, nf);
+        OVL_HIP(hipEventRecord(e1, c.stream));
+        OVL_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        OVL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    OVL_HIP(hipGetLastError());
+    return c.tuned[key] = best;
 }
 
 template <typename ST, typename GT, int EPI>
 static void launch_stencil_t(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, int prec,
                              bool profile)
 {
-    dim3 grid(site_blocks(c.g), nf);
+    const int v = tuned_variant<ST, GT, EPI>(c, a, U, nf, prec);
     PendingEvent pe;
     const double bytes = stencil_bytes(c.g, prec, EPI) * nf;
-    if (profile) c.prof_begin(pe, KERN_STENCIL, prec, bytes);
-    k_stencil<ST, GT, EPI><<<grid, 256, 0, c.stream>>>(a, U);
+    if (profile && c.prof) c.prof_begin(pe, KERN_STENCIL, prec, bytes);
+    launch_by_id<ST, GT, EPI>(c, v, a, U, nf);
     OVL_HIP(hipGetLastError());
-    if (profile) c.prof_end(pe);
+    if (profile && c.prof) c.prof_end(pe);
 }
 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
@@ -268,6 +396,17 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
     } else {
         throw Error{OVL_ERR_UNSUPPORTED, "stencil: precision"};
     }
+}
+
+// w = K t + s0 p with (p, w) partials per tile; returns the number of tiles.
+int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double rho, double s0, const void *p,
+                   double *partial, const int *stop, int it)
+{
+    stencil(c, EPI_K2DOT, prec, t, w, nf, rho, s0, p, partial, stop, it);
+    const int key = (prec * 8 + EPI_K2DOT) * 64 + (nf < 63 ? nf : 63);
+    const int v = c.tuned.count(key) ? c.tuned[key] : 1;
+    const int tps = v >= 2 ? 2 : 1;
+    return (int)((c.g.V * tps + 255) / 256);
 }
 
 void launch_hop(Context &c, const void *in, void *out, int nf, int prec)

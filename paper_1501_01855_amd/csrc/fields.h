@@ -53,6 +53,40 @@ __device__ __forceinline__ void st_sp(float4 *__restrict__ p, int64_t V, int64_t
         p[k * V + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
 }
 
+// Half of a spinor: spins 2h, 2h+1 (complex components 6h .. 6h+5).
+__device__ __forceinline__ void ld_sp_half(const double2 *__restrict__ p, int64_t V, int64_t s, int h,
+                                           cplx<double> v[6])
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double2 t = p[(6 * h + c) * V + s];
+        v[c] = {t.x, t.y};
+    }
+}
+__device__ __forceinline__ void st_sp_half(double2 *__restrict__ p, int64_t V, int64_t s, int h,
+                                           const cplx<double> v[6])
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) p[(6 * h + c) * V + s] = make_double2(v[c].re, v[c].im);
+}
+__device__ __forceinline__ void ld_sp_half(const float4 *__restrict__ p, int64_t V, int64_t s, int h,
+                                           cplx<float> v[6])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float4 t = p[(3 * h + k) * V + s];
+        v[2 * k] = {t.x, t.y};
+        v[2 * k + 1] = {t.z, t.w};
+    }
+}
+__device__ __forceinline__ void st_sp_half(float4 *__restrict__ p, int64_t V, int64_t s, int h,
+                                           const cplx<float> v[6])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        p[(3 * h + k) * V + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+}
+
 // Number of storage elements of one field per site (planes).
 template <typename ST> struct Planes;
 template <> struct Planes<double2> { static constexpr int n = 12; using R = double; };
@@ -161,6 +195,26 @@ __device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[
             }
         }
     }
+}
+
+// ------------------------------------------------------------------ block -> tile mapping
+// Work-groups are handed to the eight XCDs round-robin by linear id.  With
+// REMAP, each XCD receives a contiguous range of logical ids, so neighbouring
+// site tiles (and the fields of one tile, which share its links) run on the
+// same XCD and meet in its L2.  Logical id -> (site tile, field), field
+// fastest.
+template <bool REMAP>
+__device__ __forceinline__ void tile_of_block(unsigned &tile, unsigned &field)
+{
+    const unsigned X = gridDim.x, Y = gridDim.y, B = X * Y;
+    const unsigned lin = blockIdx.y * X + blockIdx.x;
+    unsigned lid = lin;
+    if constexpr (REMAP) {
+        const unsigned q = B / 8, r = B % 8, x = lin % 8, k = lin / 8;
+        lid = x * q + (x < r ? x : r) + k;
+    }
+    tile = lid / Y;
+    field = lid % Y;
 }
 
 // ------------------------------------------------------------------ reductions

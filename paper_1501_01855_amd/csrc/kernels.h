@@ -24,6 +24,12 @@ struct StencilArgs {
     int it;
 };
 
+// w = K t + s0 p with the (p, w) partial of every tile in partial[f][tile];
+// returns the number of tiles of the launch (the variant may use two lanes
+// per site).
+int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double rho, double s0, const void *p,
+                   double *partial, const int *stop, int it);
+
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
              double sigma, const void *aux, double *partial, const int *stop = nullptr, int it = 0);
 double stencil_bytes(const Geom &g, int prec, int epi);

@@ -2,63 +2,46 @@
 // lowest kernel eigenvectors treated exactly (Sec. 1 after eq. 4), the
 // shifted inversions of K^2 + sigma_l done by one multi-shift CG.
 //
-// One CG iteration is six launches on the context's stream, with all of the
-// recurrence scalars (alpha, beta, zeta_l, ...) kept in device memory so that
-// the host never waits inside the loop:
+// One CG iteration is four launches on the context's stream; the recurrence
+// scalars live in device memory (mscg_state.h) so the host never waits inside
+// the loop:
 //   1. t = K p                                  (stencil)
-//   2. w = K t + s0 p, partial (p, w)           (stencil + fused dot)
-//   3. alpha, zeta_l', alpha_l                  (one block per field)
-//   4. r' = r - alpha w, partial ||r'||^2       (fused update + norm)
-//   5. beta, beta_l, freezing                   (one block per field)
-//   6. y += sum_l omega_l alpha_l p_l,          (one pass over the active
-//      p_l = zeta_l' r' + beta_l p_l                shift vectors)
+//   2. w = K t + s0 p, (p, w) per tile          (stencil + fused dot)
+//   3. alpha = rr/(p, w); r' = r - alpha w;     (every block reduces the
+//      ||r'||^2 per block                        tile partials itself)
+//   4. beta, zeta_l', alpha_l, beta_l;          (one pass over the active
+//      y += sum_l omega_l alpha_l p_l,              shift vectors; block 0
+//      p_l = zeta_l' r' + beta_l p_l                writes the next state)
 // Only y = sum_l omega_l x_l is stored, never the x_l themselves.  A shift is
 // frozen once omega_l |zeta_l| ||r|| / (2 sqrt(sigma_l)) <= eta ||b|| / N_Z,
 // which bounds the error of the rational function by eta ||b||.  The host
 // polls a per-field stop iteration every few iterations.
+#include <algorithm>
 #include <cmath>
 
 #include "context.h"
 #include "fields.h"
 #include "kernels.h"
+#include "mscg_state.h"
 #include "ops.h"
 
 namespace ovl {
 
-constexpr int NZMAX = OVL_MAX_NZ;
+static constexpr int UPD_BLOCKS = 1024;   // grid of the update kernels (grid-stride over sites)
 
-struct MscgScal {
-    double rr, alpha, beta, alpha_old, beta_old, b2;
-    int iters, breakdown, act_total, pad1;
-    double zeta[NZMAX], zeta_old[NZMAX], zn[NZMAX], coef_y[NZMAX], bl[NZMAX];
-    int act[NZMAX], act_next[NZMAX];
+struct MscgFinal {
+    int iters, breakdown, act_total, pad;
 };
-
-struct MscgConst {
-    int nz, base, maxiter, pad;
-    double s0;
-    double sigma[NZMAX], omega[NZMAX], tol2[NZMAX];
-};
-
-// --------------------------------------------------------------- scalar kernels
-__device__ double reduce_partials(const double *p, int n, double *lds)
-{
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
-    return block_sum<256>(v, lds);
-}
 
 __global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int nblk, MscgConst k)
 {
     __shared__ double lds[4];
     const int f = blockIdx.x;
-    const double b2 = reduce_partials(partial + (int64_t)f * nblk, nblk, lds);
+    const double b2 = block_allsum(partial + (int64_t)f * nblk, nblk, lds);
     if (threadIdx.x != 0) return;
-    MscgScal &s = S[f];
+    MscgScal &s = S[f];   // parity 0
     s.rr = b2;
     s.b2 = b2;
-    s.alpha = 0.0;
-    s.beta = 0.0;
     s.alpha_old = 1.0;
     s.beta_old = 0.0;
     s.iters = 0;
@@ -67,84 +50,11 @@ __global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int n
     for (int l = 0; l < k.nz; ++l) {
         s.zeta[l] = 1.0;
         s.zeta_old[l] = 1.0;
-        s.zn[l] = 1.0;
-        s.coef_y[l] = 0.0;
-        s.bl[l] = 0.0;
-        s.act[l] = 1;
-        s.act_next[l] = b2 > 0.0 ? 1 : 0;
+        s.act[l] = b2 > 0.0 ? 1 : 0;
     }
     stop[f] = b2 > 0.0 ? 0x7fffffff : 0;
 }
 
-__global__ void k_mscg_alpha(MscgScal *S, const int *stop, const double *partial, int nblk, int it,
-                             MscgConst k)
-{
-    __shared__ double lds[4];
-    const int f = blockIdx.x;
-    if (it >= stop[f]) return;
-    const double pw = reduce_partials(partial + (int64_t)f * nblk, nblk, lds);
-    if (threadIdx.x != 0) return;
-    MscgScal &s = S[f];
-    int na = 0;
-    for (int l = 0; l < k.nz; ++l) {
-        s.act[l] = s.act_next[l];
-        na += s.act[l];
-    }
-    s.act_total += na;
-    const double alpha = s.rr / pw;
-    if (!(pw > 0.0) || !isfinite(alpha)) {
-        s.breakdown = 1;
-        s.alpha = 0.0;
-        for (int l = 0; l < k.nz; ++l) s.coef_y[l] = 0.0;
-        return;
-    }
-    s.alpha = alpha;
-    for (int l = 0; l < k.nz; ++l) {
-        if (!s.act[l]) continue;
-        const double z = s.zeta[l], zo = s.zeta_old[l];
-        const double zn = (z * zo * s.alpha_old) /
-                          (alpha * s.beta_old * (zo - z) + zo * s.alpha_old * (1.0 + (k.sigma[l] - k.s0) * alpha));
-        s.zn[l] = zn;
-        s.coef_y[l] = k.omega[l] * (alpha * zn / z);
-    }
-}
-
-__global__ void k_mscg_beta(MscgScal *S, int *stop, const double *partial, int nblk, int it, MscgConst k)
-{
-    __shared__ double lds[4];
-    const int f = blockIdx.x;
-    if (it >= stop[f]) return;
-    const double rr_new = reduce_partials(partial + (int64_t)f * nblk, nblk, lds);
-    if (threadIdx.x != 0) return;
-    MscgScal &s = S[f];
-    const double beta = rr_new / s.rr;
-    int any = 0;
-    for (int l = 0; l < k.nz; ++l) {
-        if (!s.act[l]) {
-            s.act_next[l] = 0;
-            continue;
-        }
-        const double q = s.zn[l] / s.zeta[l];
-        s.bl[l] = beta * q * q;
-        s.zeta_old[l] = s.zeta[l];
-        s.zeta[l] = s.zn[l];
-        const int keep = !(s.zeta[l] * s.zeta[l] * rr_new <= k.tol2[l] * s.b2);
-        s.act_next[l] = keep;
-        any |= keep;
-    }
-    s.alpha_old = s.alpha;
-    s.beta_old = beta;
-    s.beta = beta;
-    s.rr = rr_new;
-    s.iters += 1;
-    if (s.breakdown || !isfinite(rr_new)) {
-        s.breakdown = 1;
-        any = 0;
-    }
-    if (!any || s.iters >= k.maxiter) stop[f] = it + 1;
-}
-
-// --------------------------------------------------------------- vector kernels
 template <typename ST>
 __global__ __launch_bounds__(256) void k_norm2(const ST *__restrict__ x, int64_t V, double *partial)
 {
@@ -164,74 +74,137 @@ __global__ __launch_bounds__(256) void k_norm2(const ST *__restrict__ x, int64_t
     if (threadIdx.x == 0) partial[(int64_t)f * gridDim.x + blockIdx.x] = t;
 }
 
-// r' = r - alpha w (r = src on the first iteration); partial ||r'||^2
+// r' = r - alpha w (r = src on the first iteration), alpha = rr/(p, w) from the
+// stencil's tile partials; ||r'||^2 per block.
 template <typename ST>
 __global__ __launch_bounds__(256) void k_mscg_rupdate(const ST *__restrict__ rin, ST *__restrict__ r,
                                                       const ST *__restrict__ w, const MscgScal *S,
-                                                      const int *stop, int it, int64_t V, double *partial)
+                                                      const int *stop, int it, int64_t V,
+                                                      const double *pw_part, int pw_n, double *rr_part)
 {
     using R = typename Planes<ST>::R;
     constexpr int NP = Planes<ST>::n;
     const int f = blockIdx.y;
     if (it >= stop[f]) return;
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    __shared__ double lds[4];
+    const int nf = gridDim.y;
+    const MscgScal &sc = S[(it & 1) * nf + f];
+    const double pw = block_allsum(pw_part + (int64_t)f * pw_n, pw_n, lds);
+    const double alpha_d = sc.rr / pw;
+    const R alpha = (pw > 0.0 && isfinite(alpha_d)) ? (R)alpha_d : R(0);
     double d = 0.0;
-    if (s < V) {
-        const R alpha = (R)S[f].alpha;
+    const int64_t o = (int64_t)f * NP * V;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
         cplx<R> a[12], b[12];
-        ld_sp(rin + (int64_t)f * NP * V, V, s, a);
-        ld_sp(w + (int64_t)f * NP * V, V, s, b);
+        ld_sp(rin + o, V, s, a);
+        ld_sp(w + o, V, s, b);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             a[c] = a[c] - alpha * b[c];
             d += (double)a[c].re * (double)a[c].re + (double)a[c].im * (double)a[c].im;
         }
-        st_sp(r + (int64_t)f * NP * V, V, s, a);
+        st_sp(r + o, V, s, a);
     }
-    __shared__ double lds[4];
     const double t = block_sum<256>(d, lds);
-    if (threadIdx.x == 0) partial[(int64_t)f * gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0) rr_part[(int64_t)f * gridDim.x + blockIdx.x] = t;
 }
 
-// y += sum_l omega_l alpha_l p_l ; p_l = zeta_l' r + beta_l p_l (active shifts).
-// On the first iteration every p_l is the source and y starts at zero.
+// y += sum_l omega_l alpha_l p_l ; p_l = zeta_l' r + beta_l p_l over the active
+// shifts (on the first iteration every p_l is the source and y starts at zero).
+// Every block derives the iteration's scalars; block 0 stores the next state.
 template <typename ST>
 __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, const ST *__restrict__ r,
-                                                    ST *__restrict__ y, ST *__restrict__ p, int nz,
-                                                    const MscgScal *S, const int *stop, int it, int64_t V)
+                                                    ST *__restrict__ y, ST *__restrict__ p, MscgScal *S,
+                                                    const MscgConst *kc, int *stop, MscgFinal *fin, int it,
+                                                    int64_t V, const double *pw_part, int pw_n,
+                                                    const double *rr_part, int rr_n)
 {
     using R = typename Planes<ST>::R;
     constexpr int NP = Planes<ST>::n;
     const int f = blockIdx.y;
     if (it >= stop[f]) return;
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= V) return;
-    const MscgScal &sc = S[f];
-    const int64_t fo = (int64_t)f * NP * V;
-    const int64_t pstride = (int64_t)gridDim.y * NP * V;   // shift-major: p[l][f]
-    cplx<R> rv[12], yv[12], pv[12];
-    ld_sp(r + fo, V, s, rv);
-    if (it == 0) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) yv[c] = {R(0), R(0)};
-        ld_sp(src + fo, V, s, pv);
-    } else {
-        ld_sp(y + fo, V, s, yv);
-    }
-    for (int l = 0; l < nz; ++l) {
-        if (!sc.act[l]) continue;
-        ST *pl = p + l * pstride + fo;
-        if (it != 0) ld_sp(pl, V, s, pv);
-        const R cy = (R)sc.coef_y[l], zn = (R)sc.zn[l], bl = (R)sc.bl[l];
-        cplx<R> nv[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            yv[c] = yv[c] + cy * pv[c];
-            nv[c] = zn * rv[c] + bl * pv[c];
+    const int nf = gridDim.y;
+    __shared__ double lds[4];
+    __shared__ double s_cy[NZMAX], s_zn[NZMAX], s_bl[NZMAX];
+    __shared__ int s_act[NZMAX];
+    __shared__ int s_keep_any;
+    const MscgScal &sc = S[(it & 1) * nf + f];
+    const double pw = block_allsum(pw_part + (int64_t)f * pw_n, pw_n, lds);
+    const double rr_new = block_allsum(rr_part + (int64_t)f * rr_n, rr_n, lds);
+    const double alpha = sc.rr / pw;
+    const bool ok = pw > 0.0 && isfinite(alpha) && isfinite(rr_new);
+    const double beta = rr_new / sc.rr;
+    const int nz = kc->nz;
+    if (threadIdx.x == 0) s_keep_any = 0;
+    __syncthreads();
+    if ((int)threadIdx.x < nz) {
+        const int l = threadIdx.x;
+        const int act = sc.act[l] && ok;
+        s_act[l] = act;
+        double zn = sc.zeta[l], cy = 0.0, bl = 0.0;
+        if (act) {
+            const double z = sc.zeta[l], zo = sc.zeta_old[l];
+            zn = (z * zo * sc.alpha_old) /
+                 (alpha * sc.beta_old * (zo - z) + zo * sc.alpha_old * (1.0 + (kc->sigma[l] - kc->s0) * alpha));
+            cy = kc->omega[l] * (alpha * zn / z);
+            const double q = zn / z;
+            bl = beta * q * q;
         }
-        st_sp(pl, V, s, nv);
+        s_zn[l] = zn;
+        s_cy[l] = cy;
+        s_bl[l] = bl;
+        if (blockIdx.x == 0) {
+            MscgScal &nx = S[((it + 1) & 1) * nf + f];
+            nx.zeta_old[l] = act ? sc.zeta[l] : sc.zeta_old[l];
+            nx.zeta[l] = zn;
+            const int keep = act && !(zn * zn * rr_new <= kc->tol2[l] * sc.b2);
+            nx.act[l] = keep;
+            if (keep) atomicOr(&s_keep_any, 1);
+        }
     }
-    st_sp(y + fo, V, s, yv);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        MscgScal &nx = S[((it + 1) & 1) * nf + f];
+        int na = 0;
+        for (int l = 0; l < nz; ++l) na += s_act[l];
+        nx.rr = rr_new;
+        nx.b2 = sc.b2;
+        nx.alpha_old = alpha;
+        nx.beta_old = beta;
+        nx.iters = sc.iters + 1;
+        nx.breakdown = sc.breakdown || !ok;
+        nx.act_total = sc.act_total + na;
+        fin[f] = MscgFinal{nx.iters, nx.breakdown, nx.act_total, 0};
+        if (!s_keep_any || nx.breakdown || nx.iters >= kc->maxiter) stop[f] = it + 1;
+    }
+    if (!ok) return;
+    const int64_t fo = (int64_t)f * NP * V;
+    const int64_t pstride = (int64_t)nf * NP * V;   // shift-major: p[l][f]
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
+        cplx<R> rv[12], yv[12], pv[12];
+        ld_sp(r + fo, V, s, rv);
+        if (it == 0) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) yv[c] = {R(0), R(0)};
+            ld_sp(src + fo, V, s, pv);
+        } else {
+            ld_sp(y + fo, V, s, yv);
+        }
+        for (int l = 0; l < nz; ++l) {
+            if (!s_act[l]) continue;
+            ST *pl = p + l * pstride + fo;
+            if (it != 0) ld_sp(pl, V, s, pv);
+            const R cy = (R)s_cy[l], zn = (R)s_zn[l], bl = (R)s_bl[l];
+            cplx<R> nv[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                yv[c] = yv[c] + cy * pv[c];
+                nv[c] = zn * rv[c] + bl * pv[c];
+            }
+            st_sp(pl, V, s, nv);
+        }
+        st_sp(y + fo, V, s, yv);
+    }
 }
 
 // ---- low-mode projection (basis FP64 packed [n][12][V], fields in ST)
@@ -270,7 +243,7 @@ __global__ __launch_bounds__(256) void k_low_dots(const double2 *__restrict__ ba
 __global__ void k_reduce_rows(const double *partial, int nblk, double *out)
 {
     __shared__ double lds[4];
-    const double v = reduce_partials(partial + (int64_t)blockIdx.x * nblk, nblk, lds);
+    const double v = block_allsum(partial + (int64_t)blockIdx.x * nblk, nblk, lds);
     if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
@@ -325,7 +298,10 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     const int64_t V = g.V;
     const size_t FB = field_bytes(g, prec);
     const unsigned nblk = site_blocks(g);
+    const unsigned nblk_max = site_blocks(g, 128);   // two lanes per site
     const dim3 grid(nblk, nf);
+    const unsigned nupd = std::min<unsigned>(UPD_BLOCKS, nblk);
+    const dim3 ugrid(nupd, nf);
     const int nz = z.n_z;
     OVL_REQUIRE(nz >= 1 && nz <= NZMAX, OVL_ERR_ARG, "n_z out of range");
     OVL_REQUIRE(eta > 0.0, OVL_ERR_ARG, "eta must be positive");
@@ -339,11 +315,15 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     ST *w = (ST *)c.buf("ms_w", FB * nf);
     ST *y = (ST *)c.buf("ms_y", FB * nf);
     ST *p = (ST *)c.buf("ms_p", FB * nf * nz);
-    double *part = (double *)c.buf("ms_part", sizeof(double) * (size_t)nblk * nf * 2 * (c.n_low > 0 ? c.n_low : 1));
-    double *coef = (double *)c.buf("ms_coef", sizeof(double) * (size_t)nf * 2 * (c.n_low > 0 ? c.n_low : 1));
-    double *sgn = (double *)c.buf("ms_sgn", sizeof(double) * (c.n_low > 0 ? c.n_low : 1));
-    MscgScal *S = (MscgScal *)c.buf("ms_scal", sizeof(MscgScal) * nf);
+    const int nl = c.n_low > 0 ? c.n_low : 1;
+    double *part = (double *)c.buf("ms_part", sizeof(double) * (size_t)std::max(nblk_max, nblk * 2 * nl) * nf);
+    double *rr_part = (double *)c.buf("ms_part2", sizeof(double) * (size_t)nupd * nf);
+    double *coef = (double *)c.buf("ms_coef", sizeof(double) * (size_t)nf * 2 * nl);
+    double *sgn = (double *)c.buf("ms_sgn", sizeof(double) * nl);
+    MscgScal *S = (MscgScal *)c.buf("ms_scal", sizeof(MscgScal) * 2 * nf);
+    MscgFinal *fin = (MscgFinal *)c.buf("ms_fin", sizeof(MscgFinal) * nf);
     int *stop = (int *)c.buf("ms_stop", sizeof(int) * nf);
+    MscgConst *kdev = (MscgConst *)c.buf("ms_const", sizeof(MscgConst));
 
     // 1. low-mode split: src = (1 - P) in, ex = sum sign(lambda) P in
     const bool low = c.n_low > 0;
@@ -359,7 +339,7 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     }
     OVL_HIP(hipGetLastError());
 
-    // 2. constants
+    // 2. constants and initial state
     MscgConst k{};
     k.nz = nz;
     k.maxiter = maxiter;
@@ -374,6 +354,7 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
         const double tl = eta * 2.0 * std::sqrt(z.sigma[l]) / (nz * z.omega[l]);
         k.tol2[l] = tl * tl;
     }
+    OVL_HIP(hipMemcpyAsync(kdev, &k, sizeof(MscgConst), hipMemcpyHostToDevice, c.stream));
     zero_fields(c, y, nf, prec);   // y stays zero for a zero source
     k_norm2<ST><<<grid, 256, 0, c.stream>>>(src, V, part);
     k_mscg_init<<<nf, 256, 0, c.stream>>>(S, stop, part, nblk, k);
@@ -386,19 +367,19 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     const size_t pst = FB * nf;   // bytes between shift vectors
     ST *pbase = (ST *)((char *)p + pst * base);
     int it = 0;
-    int pending = -1;   // slot of the chunk awaiting a check
+    int pending = -1;
     bool finished = false;
     while (!finished) {
         for (int j = 0; j < CHUNK; ++j, ++it) {
             const ST *pin = it == 0 ? src : pbase;
             stencil(c, EPI_K, prec, pin, t, nf, rho, 0.0, nullptr, nullptr, stop, it);
-            stencil(c, EPI_K2DOT, prec, t, w, nf, rho, k.s0, pin, part, stop, it);
-            k_mscg_alpha<<<nf, 256, 0, c.stream>>>(S, stop, part, nblk, it, k);
-            k_mscg_rupdate<ST><<<grid, 256, 0, c.stream>>>(it == 0 ? src : r, r, w, S, stop, it, V, part);
-            k_mscg_beta<<<nf, 256, 0, c.stream>>>(S, stop, part, nblk, it, k);
+            const int ntile = stencil_k2_dot(c, prec, t, w, nf, rho, k.s0, pin, part, stop, it);
+            k_mscg_rupdate<ST><<<ugrid, 256, 0, c.stream>>>(it == 0 ? src : r, r, w, S, stop, it, V, part, ntile,
+                                                           rr_part);
             PendingEvent pe;
             if (c.prof) c.prof_begin(pe, KERN_SHIFT, prec, 0.0);
-            k_mscg_shift<ST><<<grid, 256, 0, c.stream>>>(src, r, y, p, nz, S, stop, it, V);
+            k_mscg_shift<ST><<<ugrid, 256, 0, c.stream>>>(src, r, y, p, S, kdev, stop, fin, it, V, part, ntile,
+                                                         rr_part, nupd);
             if (c.prof) c.prof_end(pe);
             OVL_HIP(hipGetLastError());
         }
@@ -414,7 +395,6 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
         pending = slot;
         if (it >= maxiter + 2 * CHUNK) finished = true;
     }
-    OVL_HIP(hipStreamSynchronize(c.stream));
 
     // 4. s = K y + ex
     if (low) {
@@ -424,13 +404,16 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     }
     OVL_HIP(hipGetLastError());
 
-    std::vector<MscgScal> hs(nf);
-    OVL_HIP(hipMemcpyAsync(hs.data(), S, sizeof(MscgScal) * nf, hipMemcpyDeviceToHost, c.stream));
+    std::vector<MscgFinal> hs(nf);
+    std::vector<int> hstop_final(nf);
+    OVL_HIP(hipMemcpyAsync(hs.data(), fin, sizeof(MscgFinal) * nf, hipMemcpyDeviceToHost, c.stream));
+    OVL_HIP(hipMemcpyAsync(hstop_final.data(), stop, sizeof(int) * nf, hipMemcpyDeviceToHost, c.stream));
     OVL_HIP(hipStreamSynchronize(c.stream));
     c.prof_collect();
     int64_t iters = 0, act_total = 0;
     bool brk = false, capped = false;
     for (int f = 0; f < nf; ++f) {
+        if (hstop_final[f] == 0) continue;   // zero source: no iteration ran
         iters += hs[f].iters;
         act_total += hs[f].act_total;
         brk = brk || hs[f].breakdown;
