@@ -1,0 +1,185 @@
+"""Oracle: deflation of the middle solve (Sec. 4) and eigSUMR (Sec. 5,
+Algs. 5 and 6, the relaxation bound of Sec. 5.1).
+
+TEST INFRASTRUCTURE ONLY.
+
+Readings where the paper is silent or garbled (also listed in the design notes):
+* Alg. 6 writes the update as (V U^T v); it is read as the Rayleigh-Ritz
+  vectors  v_new = V R^{-1} Y[:, :n]  (same for v^D), with E = V^H V = R^H R
+  (Cholesky, R upper) and Y the ascending eigenvectors of R^{-H} M R^{-1}.
+* The eigenvector residual of Alg. 6 is taken as
+  r_i = gamma_5 v^D_i - v_i (v_i, gamma_5 v^D_i)  (Sec. 5.1 definition).
+* The pair-splitting constant delta (Sec. 5) is not given: delta = 0.1.
+* Eq. (bound): chi multiplies the whole numerator,
+  ||delta^D|| < chi (sqrt(eps^2 + r0^2) - r0) / (sqrt((m - n) k) <max|UV|>),
+  chi = 1 for the first two diagonalisations and sqrt(n) after; max|UV| is
+  taken over new eigenvectors i < n and new Krylov vectors n <= j < m of the
+  rotation R^{-1} Y, averaged over the last ten diagonalisations (1 before
+  any); the sign accuracy follows as eta = 2 ||delta^D|| / (1 - mu).
+* When both the inversion and the eigenvector bound apply, the stricter
+  (smaller) sign accuracy is used (Sec. 5.1, third strategy).
+* The subspace size m is not given for the inversions: m = n + 40 unless
+  set; v^D is recomputed accurately every k diagonalisations and when the
+  eigenvector phase ends.
+"""
+import numpy as np
+
+from .lattice import dot, g5, norm
+
+
+def _mat(vs):
+    return np.stack([v.reshape(-1) for v in vs], axis=1)
+
+
+class Deflation:
+    """Sec. 4: rotate psi' = psi Y so that (psi'_i, gamma_5 D psi'_j) is
+    diagonal, then x0 = sum_j alpha_j psi'_j with
+    alpha_j = (D psi'_j, b) / (D psi'_j, D psi'_j); D x0 = sum_j alpha_j D psi'_j."""
+
+    def __init__(self, vecs, dvecs):
+        P = _mat(vecs)
+        DP = _mat(dvecs)
+        shape = vecs[0].shape
+        H = P.conj().T @ g5(DP.T.reshape((-1,) + shape)).reshape(len(vecs), -1).T
+        H = 0.5 * (H + H.conj().T)
+        h, Y = np.linalg.eigh(H)
+        self.h = h
+        self.P = P @ Y
+        self.DP = DP @ Y
+        self.shape = shape
+
+    def x0(self, b):
+        bb = b.reshape(-1)
+        num = self.DP.conj().T @ bb
+        den = np.einsum("ij,ij->j", self.DP.conj(), self.DP).real
+        alpha = num / den
+        return (self.P @ alpha).reshape(self.shape)
+
+    def project(self, b):
+        """(x0, D x0)."""
+        bb = b.reshape(-1)
+        alpha = (self.DP.conj().T @ bb) / np.einsum("ij,ij->j", self.DP.conj(), self.DP).real
+        return (self.P @ alpha).reshape(self.shape), (self.DP @ alpha).reshape(self.shape)
+
+
+def rayleigh_ritz(V, VD, n, mu, delta):
+    """Alg. 6 on the columns of V (basis) and VD (their images under D):
+    returns (v, vD, theta, C) with v = V C, vD = VD C, C = R^{-1} Y[:, :n]."""
+    E = V.conj().T @ V
+    E = 0.5 * (E + E.conj().T)
+    L = np.linalg.cholesky(E)            # E = L L^H, R = L^H
+    R = L.conj().T
+    N = V.shape[0]
+    # gamma_5 in canonical layout: spins 2, 3 negated
+    G5VD = (g5(VD.T.reshape((VD.shape[1], N // 12, 4, 3))).reshape(VD.shape[1], -1)).T
+    M = VD.conj().T @ VD + 2.0 * mu * delta * (V.conj().T @ G5VD)
+    M = 0.5 * (M + M.conj().T)
+    Rinv = np.linalg.inv(R)
+    G = Rinv.conj().T @ M @ Rinv
+    G = 0.5 * (G + G.conj().T)
+    theta, Y = np.linalg.eigh(G)
+    C = Rinv @ Y[:, :n]
+    return V @ C, VD @ C, theta[:n], C
+
+
+class EigSUMR:
+    """Alg. 5 inside the SUMR iteration plus Alg. 6 at k = m.
+
+    collect(q, u): v_k = q, v^D_k = (1 - mu)/2 u + (1 + mu)/2 q, u = U q."""
+
+    def __init__(self, n, m, mu, delta=0.1, eps=1e-4, krecalc=25):
+        assert m > n
+        self.n, self.m, self.mu, self.delta = n, m, float(mu), float(delta)
+        self.eps, self.krecalc = eps, krecalc
+        self.V, self.VD = [], []
+        self.ndiag = 0
+        self.uv_hist = []
+        self.theta = None
+        self.shape = None
+
+    def collect(self, q, u):
+        self.shape = q.shape
+        self.V.append(q.copy())
+        self.VD.append(0.5 * (1.0 - self.mu) * u + 0.5 * (1.0 + self.mu) * q)
+        if len(self.V) == self.m:
+            self.diagonalise()
+
+    def diagonalise(self):
+        if len(self.V) <= self.n:
+            return
+        nprev = self.n if self.ndiag > 0 else 0
+        v, vD, theta, C = rayleigh_ritz(_mat(self.V), _mat(self.VD), self.n, self.mu, self.delta)
+        self.V = [v[:, i].reshape(self.shape) for i in range(self.n)]
+        self.VD = [vD[:, i].reshape(self.shape) for i in range(self.n)]
+        self.theta = theta
+        self.ndiag += 1
+        if C.shape[0] > nprev:
+            self.uv_hist.append(float(np.abs(C[nprev:, :]).max()))
+        self.uv_hist = self.uv_hist[-10:]
+
+    def ritz(self):
+        """Ritz values (v_i, gamma_5 v^D_i) and residual norms of Alg. 6."""
+        vals, res = [], []
+        for v, vD in zip(self.V[: self.n], self.VD[: self.n]):
+            g = g5(vD)
+            h = dot(v, g).real
+            vals.append(h)
+            res.append(norm(g - h * v))
+        return np.array(vals), np.array(res)
+
+    def recompute(self, apply_D, eta=1e-13):
+        """v^D = D v to high accuracy (after the eigenvector phase / every k)."""
+        self.VD = [apply_D(v, eta) for v in self.V]
+
+    def sign_accuracy(self):
+        """Eq. (bound) of Sec. 5.1 as a sign accuracy (module notes)."""
+        if len(self.V) < self.n or self.theta is None:
+            r0 = 0.0
+        else:
+            r0 = float(self.ritz()[1].min())
+        chi = 1.0 if self.ndiag < 2 else np.sqrt(self.n)
+        uv = np.mean(self.uv_hist) if self.uv_hist else 1.0
+        dd = chi * (np.sqrt(self.eps ** 2 + r0 ** 2) - r0) / (np.sqrt((self.m - self.n) * self.krecalc) * uv)
+        return 2.0 * dd / (1.0 - self.mu)
+
+    def deflation(self):
+        return Deflation(self.V[: self.n], self.VD[: self.n])
+
+
+def gmresr_eigsumr(overlap, b, eps, eta_tilde, eig, calc=True, floor=1e-2, maxiter=10000):
+    """GMRESR(relSUMR) with eigSUMR (Secs. 3-5): every middle solve starts from
+    the deflation projection of the current eigenvector set; while calc is
+    true its Krylov vectors are collected (Alg. 5) at the stricter of the
+    inversion and eigenvector sign accuracies, and Alg. 6 runs whenever m
+    vectors are held and at the end of each middle solve."""
+    from . import krylov
+    mu = overlap.mu
+    bnorm = norm(b)
+    rho = (1.0 - mu) / (1.0 + mu)
+
+    def apply_A(u):
+        e = min(1e-2, eps * bnorm / (2.0 * (1.0 - mu) * norm(u)))
+        return overlap(u, e)
+
+    def middle(r):
+        x0 = None
+        if len(eig.V) >= eig.n and eig.theta is not None:
+            x0 = eig.deflation().x0(r)
+        bp = (2.0 / (1.0 + mu)) * r
+        bpn = norm(bp)
+
+        def eta_fn(j, res):
+            e = eta_tilde if (res is None or res <= 0) else min(floor, eta_tilde * bpn / res)
+            if calc:
+                e = min(e, eig.sign_accuracy())
+            return e
+
+        res = krylov.sumr(overlap.U, rho, bp, eta_tilde, x0=x0, maxiter=maxiter, eta_fn=eta_fn,
+                          on_step=(eig.collect if calc else None))
+        if calc:
+            eig.diagonalise()
+            if eig.ndiag and eig.ndiag % eig.krecalc == 0:
+                eig.recompute(overlap)
+        return res.x, res.iters
+
+    return krylov.gmresr(apply_A, middle, b, 0.5 * eps)
