@@ -100,9 +100,14 @@ typedef struct {
     int32_t max_outer;     /* GMRESR steps                                          */
     int32_t max_middle;    /* SUMR iterations per middle solve                      */
     int32_t max_mscg;      /* multi-shift CG iterations per sign call               */
-    int32_t use_deflation; /* 1: start middle solves from the eigenspace projection  */
+    int32_t use_deflation; /* 1: start middle solves from the eigenspace projection (Sec. 4) */
     int32_t eig_calc;      /* 1: collect eigSUMR vectors during this solve (Alg. 5)  */
+    int32_t n_eig;         /* eigSUMR: eigenvectors kept (n)                         */
+    int32_t m_eig;         /* eigSUMR: basis size at which Alg. 6 runs (m > n)       */
+    int32_t k_recalc;      /* eigSUMR: recompute v^D = D v every k diagonalisations   */
     int32_t verbose;
+    double eig_eps;        /* eigSUMR: target eigenvector accuracy (Sec. 6: 1e-4)    */
+    double delta_split;    /* eigSUMR: pair splitting in M (Sec. 5), 0 < delta < 1/2 */
 } ovl_solver_params;
 
 typedef struct ovl_context ovl_context;
@@ -188,6 +193,30 @@ ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_
 ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo,
                                  const ovl_solver_params *params, const double *b_dev,
                                  double *x_dev, int32_t nrhs, ovl_stats *stats_host);
+
+/* ---- eigenspace (eigSUMR basis; Secs. 4-5) ------------------------------ */
+
+/* Number of vectors held (n after a diagonalisation), their Ritz values
+ * (v, gamma_5 v^D) and residuals ||gamma_5 v^D - h v|| (host arrays of
+ * capacity cap, may be null), and the number of diagonalisations so far. */
+ovl_status ovl_eigspace_info(ovl_context *ctx, int32_t *n_held, int32_t cap, double *ritz_host,
+                             double *resid_host, int32_t *n_diag);
+/* Copy the held vectors v and v^D out (canonical, device, n_held fields each). */
+ovl_status ovl_eigspace_get(ovl_context *ctx, double *v_dev, double *vD_dev);
+/* Install k vectors v and their images v^D = D v (canonical, device) as the
+ * eigSUMR basis for n wanted eigenvectors and mass mu (k <= m); clears the
+ * diagonalisation history.  k = 0 empties the space. */
+ovl_status ovl_eigspace_set(ovl_context *ctx, int32_t n, int32_t m, double mu, double delta, int32_t k,
+                            const double *v_dev, const double *vD_dev);
+/* Run Alg. 6 on the held vectors now. */
+ovl_status ovl_eigspace_diagonalise(ovl_context *ctx);
+/* Recompute v^D = D v for the held vectors with FP64 sign accuracy eta. */
+ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *zolo, double eta);
+/* Sec. 4 deflated start: x0 = sum_j alpha_j psi'_j and D x0 = sum_j alpha_j D psi'_j,
+ * alpha_j = (D psi'_j, b)/(D psi'_j, D psi'_j), over the held vectors rotated
+ * so that (psi'_i, gamma_5 D psi'_j) is diagonal; nrhs fields (canonical). */
+ovl_status ovl_deflate_project(ovl_context *ctx, const double *b_dev, double *x0_dev, double *Dx0_dev,
+                               int32_t nrhs);
 
 /* Per-kernel timing of the context (HIP events around each launch on the
  * context's stream), for roofline reporting.  kernel: 0 = hopping stencil

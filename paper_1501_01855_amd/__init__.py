@@ -66,14 +66,18 @@ class SolverParams(ctypes.Structure):
                 ("norm_restart", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("max_middle", ctypes.c_int32), ("max_mscg", ctypes.c_int32),
                 ("use_deflation", ctypes.c_int32), ("eig_calc", ctypes.c_int32),
-                ("verbose", ctypes.c_int32)]
+                ("n_eig", ctypes.c_int32), ("m_eig", ctypes.c_int32), ("k_recalc", ctypes.c_int32),
+                ("verbose", ctypes.c_int32), ("eig_eps", ctypes.c_double),
+                ("delta_split", ctypes.c_double)]
 
 
 EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults", "ovl_device_bytes",
            "ovl_gauge_load", "ovl_gauge_generate", "ovl_source_generate", "ovl_wilson_dslash",
            "ovl_kernel_K_apply", "ovl_zolotarev_coeffs", "ovl_lowmodes_compute", "ovl_lowmodes_set",
            "ovl_lowmodes_get", "ovl_sign_zolotarev_mscg", "ovl_overlap_apply",
-           "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read"]
+           "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
+           "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
+           "ovl_deflate_project"]
 
 _lib = None
 
@@ -107,6 +111,12 @@ def lib():
         "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
         "ovl_profile_enable": ([P, I32], I32),
         "ovl_profile_read": ([P, I32, I32, P, P, P], I32),
+        "ovl_eigspace_info": ([P, P, I32, P, P, P], I32),
+        "ovl_eigspace_get": ([P, P, P], I32),
+        "ovl_eigspace_set": ([P, I32, I32, D, D, I32, P, P], I32),
+        "ovl_eigspace_diagonalise": ([P], I32),
+        "ovl_eigspace_recompute": ([P, D, P, D], I32),
+        "ovl_deflate_project": ([P, P, P, P, I32], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -267,6 +277,44 @@ class Context:
                                                   _dev(b, (self.V, 4, 3), "b"),
                                                   _dev(x, (self.V, 4, 3), "x"), nrhs, st), allow)
         return x, list(st), code
+
+    # -- eigenspace (eigSUMR, deflation)
+    def eigspace_info(self, cap=512):
+        n = ctypes.c_int32()
+        nd = ctypes.c_int32()
+        ritz = (ctypes.c_double * cap)()
+        res = (ctypes.c_double * cap)()
+        _check(lib().ovl_eigspace_info(self._h, ctypes.byref(n), cap, ritz, res, ctypes.byref(nd)))
+        k = min(n.value, cap)
+        return {"held": n.value, "ndiag": nd.value, "ritz": list(ritz)[:k], "resid": list(res)[:k]}
+
+    def eigspace_get(self):
+        k = self.eigspace_info()["held"]
+        v = torch.empty((k, self.V, 4, 3), dtype=torch.complex128, device="cuda")
+        vd = torch.empty_like(v)
+        if k:
+            _check(lib().ovl_eigspace_get(self._h, _dev(v, (self.V, 4, 3), "v"),
+                                          _dev(vd, (self.V, 4, 3), "vD")))
+        return v, vd
+
+    def eigspace_set(self, n, m, mu, v=None, vD=None, delta=0.1):
+        k = 0 if v is None else int(v.shape[0])
+        pv = _dev(v, (self.V, 4, 3), "v") if k else None
+        pd = _dev(vD, (self.V, 4, 3), "vD") if k else None
+        _check(lib().ovl_eigspace_set(self._h, int(n), int(m), float(mu), float(delta), k, pv, pd))
+
+    def eigspace_diagonalise(self):
+        _check(lib().ovl_eigspace_diagonalise(self._h))
+
+    def eigspace_recompute(self, rho, zolo, eta=1e-12):
+        _check(lib().ovl_eigspace_recompute(self._h, float(rho), ctypes.byref(zolo), float(eta)))
+
+    def deflate_project(self, b):
+        x0 = torch.empty_like(b)
+        dx0 = torch.empty_like(b)
+        _check(lib().ovl_deflate_project(self._h, _dev(b, (self.V, 4, 3), "b"), _dev(x0, (self.V, 4, 3), "x0"),
+                                         _dev(dx0, (self.V, 4, 3), "Dx0"), self._nrhs(b)))
+        return x0, dx0
 
     # -- profiling
     def profile(self, on=True):

@@ -76,7 +76,12 @@ void ovl_solver_defaults(ovl_solver_params *p)
     p->max_mscg = 20000;
     p->use_deflation = 0;
     p->eig_calc = 0;
+    p->n_eig = 20;
+    p->m_eig = 60;
+    p->k_recalc = 25;
     p->verbose = 0;
+    p->eig_eps = 1e-4;
+    p->delta_split = 0.1;
 }
 
 ovl_status ovl_create(const int32_t dims[4], void *hip_stream, ovl_context **out)
@@ -311,6 +316,99 @@ ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo, const o
         if (worst != OVL_OK) set_error("solver: iteration limit reached");
     });
     return st != OVL_OK ? st : worst;
+}
+
+ovl_status ovl_eigspace_info(ovl_context *ctx, int32_t *n_held, int32_t cap, double *ritz_host,
+                             double *resid_host, int32_t *n_diag)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        const EigSpace &e = ctx->eig;
+        if (n_held) *n_held = e.k;
+        if (n_diag) *n_diag = e.ndiag;
+        for (int i = 0; i < cap && i < (int)e.ritz.size(); ++i) {
+            if (ritz_host) ritz_host[i] = e.ritz[i];
+            if (resid_host) resid_host[i] = e.resid[i];
+        }
+    });
+}
+
+ovl_status ovl_eigspace_get(ovl_context *ctx, double *v_dev, double *vD_dev)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        const EigSpace &e = ctx->eig;
+        if (e.k > 0) {
+            if (v_dev) unpack_spinor(*ctx, e.V, v_dev, e.k, OVL_F64);
+            if (vD_dev) unpack_spinor(*ctx, e.VD, vD_dev, e.k, OVL_F64);
+        }
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_eigspace_set(ovl_context *ctx, int32_t n, int32_t m, double mu, double delta, int32_t k,
+                            const double *v_dev, const double *vD_dev)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(mu >= 0.0 && mu < 1.0 && delta > 0.0 && delta < 0.5, OVL_ERR_ARG, "need 0 <= mu < 1, 0 < delta < 1/2");
+        OVL_REQUIRE(k >= 0 && k <= m, OVL_ERR_ARG, "need 0 <= k <= m");
+        if (k > 0) OVL_REQUIRE(v_dev && vD_dev, OVL_ERR_ARG, "null eigenspace data");
+        EigSpace &e = ctx->eig;
+        e.mu = -1.0;   // force a fresh configuration
+        eig_configure(*ctx, n, m, mu, delta, e.eps, e.krecalc);
+        if (k > 0) {
+            pack_spinor(*ctx, v_dev, e.V, k, OVL_F64);
+            pack_spinor(*ctx, vD_dev, e.VD, k, OVL_F64);
+        }
+        e.k = k;
+        e.ndiag = k > 0 ? 1 : 0;   // treat installed vectors as eigenvector estimates
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_eigspace_diagonalise(ovl_context *ctx)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(ctx->eig.m > 0, OVL_ERR_STATE, "eigenspace not configured");
+        eig_diagonalise(*ctx);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *zolo, double eta)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        check_zolo(zolo);
+        OVL_REQUIRE(eta > 0.0, OVL_ERR_ARG, "eta must be positive");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        eig_recompute(*ctx, rho, *zolo, eta, nullptr);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->prof_collect();
+    });
+}
+
+ovl_status ovl_deflate_project(ovl_context *ctx, const double *b_dev, double *x0_dev, double *Dx0_dev, int32_t nrhs)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(b_dev && x0_dev && Dx0_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(ctx->eig.k >= 1, OVL_ERR_STATE, "the eigenspace is empty");
+        const size_t FB = field_bytes(ctx->g, OVL_F64);
+        double2 *b = (double2 *)ctx->buf("api_b64", FB);
+        double2 *x = (double2 *)ctx->buf("api_x64", FB);
+        double2 *d = (double2 *)ctx->buf("api_d64", FB);
+        for (int f = 0; f < nrhs; ++f) {
+            const size_t o = (size_t)f * ctx->g.V * 24;
+            pack_spinor(*ctx, b_dev + o, b, 1, OVL_F64);
+            eig_project(*ctx, b, x, d);
+            unpack_spinor(*ctx, x, x0_dev + o, 1, OVL_F64);
+            unpack_spinor(*ctx, d, Dx0_dev + o, 1, OVL_F64);
+        }
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+    });
 }
 
 ovl_status ovl_profile_enable(ovl_context *ctx, int32_t on)

@@ -15,6 +15,20 @@ struct PendingEvent {
     hipEvent_t a, b;
 };
 
+// eigSUMR basis and the deflation data derived from it (eigspace.hip).
+struct EigSpace {
+    int n = 0, m = 0, k = 0;        // wanted, capacity, held
+    double mu = -1.0, delta = 0.1, eps = 1e-4;
+    int krecalc = 25;
+    double2 *V = nullptr, *VD = nullptr;   // [m] packed FP64 fields each
+    int ndiag = 0;
+    std::vector<double> uv_hist, ritz, resid;
+    bool defl_ready = false;
+    int ndefl = 0;
+    double2 *P = nullptr, *DP = nullptr;
+    std::vector<double> dn2;
+};
+
 struct Context {
     Geom g{};
     hipStream_t stream = nullptr;
@@ -51,6 +65,8 @@ struct Context {
     // stencil launch variant per (precision, epilogue, nf), chosen by timing
     std::map<int, int> tuned;
     int autotune = 1;
+
+    EigSpace eig;
 
     void *buf(const std::string &name, size_t bytes);
     void *counters();

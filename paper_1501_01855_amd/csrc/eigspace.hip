@@ -1,0 +1,212 @@
+// eigSUMR (paper Sec. 5, Algs. 5 and 6, the relaxation bound of Sec. 5.1)
+// and the deflated start of the middle solve (Sec. 4).
+//
+// The context keeps up to m basis vectors v_k (SUMR's Krylov vectors q_j and,
+// after a diagonalisation, the n current eigenvector estimates) with their
+// images v^D_k = D v_k, in packed FP64.  Alg. 6 needs three m x m Gram
+// matrices (V^H V, V_D^H V_D, V^H gamma_5 V_D), built by the tall-skinny
+// block-product kernel in one pass over the basis, then an m x m Cholesky and
+// Hermitian eigenproblem on the host, then one rotation pass over the basis.
+// Ritz values and eigenvector residuals follow from the same Gram matrices.
+//
+// Readings (the paper is silent or garbled here): the update of Alg. 6 is the
+// Rayleigh-Ritz rotation V R^{-1} Y[:, :n] with E = R^H R; the residual is
+// gamma_5 v^D - v (v, gamma_5 v^D); the pair-splitting delta is a parameter
+// (default 0.1); in eq. (bound) chi scales the whole numerator (1 for the
+// first two diagonalisations, sqrt(n) after) and max|UV| is over new
+// eigenvectors and new Krylov vectors, averaged over the last ten
+// diagonalisations.
+#include <algorithm>
+#include <cmath>
+
+#include "context.h"
+#include "dense.h"
+#include "kernels.h"
+#include "ops.h"
+
+namespace ovl {
+
+using dense::zc;
+
+static std::vector<zc> to_z(const std::vector<cplx<double>> &a)
+{
+    std::vector<zc> z(a.size());
+    for (size_t i = 0; i < a.size(); ++i) z[i] = zc(a[i].re, a[i].im);
+    return z;
+}
+
+static std::vector<cplx<double>> from_z(const std::vector<zc> &a)
+{
+    std::vector<cplx<double>> z(a.size());
+    for (size_t i = 0; i < a.size(); ++i) z[i] = {a[i].real(), a[i].imag()};
+    return z;
+}
+
+void eig_configure(Context &c, int n, int m, double mu, double delta, double eps, int krecalc)
+{
+    EigSpace &e = c.eig;
+    OVL_REQUIRE(n >= 1 && m > n && m <= 512, OVL_ERR_ARG, "eigSUMR needs 1 <= n < m <= 512");
+    const size_t FB = field_bytes(c.g, OVL_F64);
+    if (e.n != n || e.m != m || e.mu != mu) {
+        e.V = (double2 *)c.buf("eig_V", FB * (size_t)m);
+        e.VD = (double2 *)c.buf("eig_VD", FB * (size_t)m);
+        e.k = 0;
+        e.ndiag = 0;
+        e.uv_hist.clear();
+        e.ritz.clear();
+        e.resid.clear();
+        e.defl_ready = false;
+    }
+    e.n = n;
+    e.m = m;
+    e.mu = mu;
+    e.delta = delta;
+    e.eps = eps;
+    e.krecalc = krecalc;
+}
+
+// Alg. 5: v_k = q, v^D_k = (1 - mu)/2 u + (1 + mu)/2 q, with u = U q.
+void eig_collect(Context &c, const double2 *q, const double2 *u)
+{
+    EigSpace &e = c.eig;
+    if (e.m == 0) return;
+    const size_t off = (size_t)e.k * 12 * c.g.V;
+    copy_fields(c, q, e.V + off, 1, OVL_F64);
+    lincomb3_f64(c, 0.5 * (1.0 - e.mu), u, 0.5 * (1.0 + e.mu), q, 0.0, nullptr, e.VD + off, 1);
+    e.k += 1;
+    if (e.k == e.m) eig_diagonalise(c);
+}
+
+// Alg. 6 on the k held vectors; keeps the n lowest Ritz pairs.
+void eig_diagonalise(Context &c)
+{
+    EigSpace &e = c.eig;
+    const int k = e.k, n = e.n;
+    if (k <= n) return;
+    const size_t FB = field_bytes(c.g, OVL_F64);
+    std::vector<cplx<double>> g;
+    gram_f64(c, e.V, k, e.V, k, false, g);
+    const std::vector<zc> E = to_z(g);
+    gram_f64(c, e.VD, k, e.VD, k, false, g);
+    const std::vector<zc> MD = to_z(g);
+    gram_f64(c, e.V, k, e.VD, k, true, g);
+    const std::vector<zc> G5M = to_z(g);
+    std::vector<zc> R;
+    OVL_REQUIRE(dense::cholesky_upper(k, E, R), OVL_ERR_BREAKDOWN,
+                "eigSUMR: basis lost linear independence (Cholesky of V^H V failed)");
+    const std::vector<zc> Rinv = dense::inv_upper(k, R);
+    std::vector<zc> M(k * k);
+    const double s = 2.0 * e.mu * e.delta;
+    for (int i = 0; i < k * k; ++i) M[i] = MD[i] + s * G5M[i];
+    // G = R^{-H} M R^{-1}
+    const std::vector<zc> MR = dense::matmul(k, k, k, M, Rinv);
+    const std::vector<zc> G = dense::matmul_ah(k, k, k, Rinv, MR);
+    std::vector<double> th;
+    std::vector<zc> Y;
+    dense::eigh(k, G, th, Y);
+    // C = R^{-1} Y[:, :n]  (k x n)
+    std::vector<zc> Yn((size_t)k * n);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < n; ++j) Yn[(size_t)i * n + j] = Y[(size_t)i * k + j];
+    const std::vector<zc> C = dense::matmul(k, k, n, Rinv, Yn);
+    // rotation magnitude of the new Krylov vectors into the eigenvectors
+    const int nprev = e.ndiag > 0 ? n : 0;
+    double uv = 0.0;
+    for (int i = nprev; i < k; ++i)
+        for (int j = 0; j < n; ++j) uv = std::max(uv, std::abs(C[(size_t)i * n + j]));
+    if (k > nprev) e.uv_hist.push_back(uv);
+    if (e.uv_hist.size() > 10) e.uv_hist.erase(e.uv_hist.begin());
+    // Ritz values h_i = (v_i, g5 vD_i), residuals ||g5 vD_i - h_i v_i|| (with ||v_i|| = 1)
+    const std::vector<zc> A1 = dense::matmul_ah(k, n, n, C, dense::matmul(k, k, n, G5M, C));
+    const std::vector<zc> A2 = dense::matmul_ah(k, n, n, C, dense::matmul(k, k, n, MD, C));
+    e.ritz.assign(n, 0.0);
+    e.resid.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        const double h = A1[(size_t)i * n + i].real();
+        e.ritz[i] = h;
+        e.resid[i] = std::sqrt(std::max(0.0, A2[(size_t)i * n + i].real() - h * h));
+    }
+    // rotate both bases (through scratch; the rotation cannot work in place)
+    double2 *tv = (double2 *)c.buf("eig_tmpV", FB * n);
+    double2 *td = (double2 *)c.buf("eig_tmpD", FB * n);
+    const std::vector<cplx<double>> Cc = from_z(C);
+    rotate_f64(c, e.V, k, Cc, n, tv, 0.0);
+    rotate_f64(c, e.VD, k, Cc, n, td, 0.0);
+    copy_fields(c, tv, e.V, n, OVL_F64);
+    copy_fields(c, td, e.VD, n, OVL_F64);
+    e.k = n;
+    e.ndiag += 1;
+    e.defl_ready = false;
+}
+
+// Eq. (bound) of Sec. 5.1 as a sign-function accuracy.
+double eig_sign_accuracy(const Context &c)
+{
+    const EigSpace &e = c.eig;
+    double r0 = 0.0;
+    if (!e.resid.empty()) r0 = *std::min_element(e.resid.begin(), e.resid.end());
+    const double chi = e.ndiag < 2 ? 1.0 : std::sqrt((double)e.n);
+    double uv = 1.0;
+    if (!e.uv_hist.empty()) {
+        uv = 0.0;
+        for (double x : e.uv_hist) uv += x;
+        uv /= (double)e.uv_hist.size();
+    }
+    const double dd = chi * (std::sqrt(e.eps * e.eps + r0 * r0) - r0) /
+                      (std::sqrt((double)(e.m - e.n) * e.krecalc) * std::max(uv, 1e-300));
+    return 2.0 * dd / (1.0 - e.mu);
+}
+
+// v^D = D v for the held vectors, to sign accuracy eta in FP64.
+void eig_recompute(Context &c, double rho, const ovl_zolo &z, double eta, ovl_stats *st)
+{
+    EigSpace &e = c.eig;
+    for (int i = 0; i < e.k; ++i) {
+        const size_t off = (size_t)i * 12 * c.g.V;
+        overlap_f64(c, rho, e.mu, z, e.V + off, e.VD + off, 1, eta, OVL_F64, 100000, st);
+    }
+    e.defl_ready = false;
+}
+
+// Sec. 4: rotate so that (psi'_i, gamma_5 D psi'_j) is diagonal.
+static void deflation_prepare(Context &c)
+{
+    EigSpace &e = c.eig;
+    const int n = std::min(e.n, e.k);
+    const size_t FB = field_bytes(c.g, OVL_F64);
+    std::vector<cplx<double>> g;
+    gram_f64(c, e.V, n, e.VD, n, true, g);
+    std::vector<double> h;
+    std::vector<zc> Y;
+    dense::eigh(n, to_z(g), h, Y);
+    e.P = (double2 *)c.buf("eig_P", FB * n);
+    e.DP = (double2 *)c.buf("eig_DP", FB * n);
+    const std::vector<cplx<double>> Yc = from_z(Y);
+    rotate_f64(c, e.V, n, Yc, n, e.P, 0.0);
+    rotate_f64(c, e.VD, n, Yc, n, e.DP, 0.0);
+    gram_f64(c, e.DP, n, e.DP, n, false, g);
+    e.dn2.assign(n, 0.0);
+    for (int j = 0; j < n; ++j) e.dn2[j] = g[(size_t)j * n + j].re;
+    e.ndefl = n;
+    e.defl_ready = true;
+}
+
+// x0 = sum_j alpha_j psi'_j, D x0 = sum_j alpha_j D psi'_j,
+// alpha_j = (D psi'_j, b) / (D psi'_j, D psi'_j)   (one field b).
+void eig_project(Context &c, const double2 *b, double2 *x0, double2 *Dx0)
+{
+    EigSpace &e = c.eig;
+    OVL_REQUIRE(e.k >= 1, OVL_ERR_STATE, "deflation: the eigenspace is empty");
+    if (!e.defl_ready) deflation_prepare(c);
+    const int n = e.ndefl;
+    std::vector<cplx<double>> a;
+    gram_f64(c, e.DP, n, b, 1, false, a);
+    for (int j = 0; j < n; ++j) {
+        const double d = e.dn2[j] > 0.0 ? e.dn2[j] : 1.0;
+        a[j] = {a[j].re / d, a[j].im / d};
+    }
+    rotate_f64(c, e.P, n, a, 1, x0, 0.0);
+    rotate_f64(c, e.DP, n, a, 1, Dx0, 0.0);
+}
+
+}  // namespace ovl

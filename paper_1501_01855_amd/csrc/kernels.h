@@ -58,4 +58,12 @@ void multidot_f64(Context &c, const double2 *Vb, int nv, const double2 *x, int n
 // x_f += sum_j coef[f][j] V_j
 void multiaxpy_f64(Context &c, const double2 *Vb, int nv, const cplx<double> *coef, double2 *x, int nf);
 
+// Tall-skinny block products on whole FP64 fields:
+// G[i][j] = (X_i, g5^s Y_j) (nx x ny, row-major, host), s = g5 ? 1 : 0
+void gram_f64(Context &c, const double2 *X, int nx, const double2 *Y, int ny, bool g5,
+              std::vector<cplx<double>> &G);
+// Z_k = beta Z_k + sum_j W[j][k] Y_j, W is ny x nz row-major (host); Z may not alias Y
+void rotate_f64(Context &c, const double2 *Y, int ny, const std::vector<cplx<double>> &W, int nz, double2 *Z,
+                double beta);
+
 }  // namespace ovl

@@ -23,6 +23,14 @@ ovl_status solve_one(Context &c, const ovl_zolo &z, const ovl_solver_params &p, 
 // Kernel low modes (lowmodes.hip).
 void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *evals, double *lmax);
 
+// eigSUMR and deflation (eigspace.hip).
+void eig_configure(Context &c, int n, int m, double mu, double delta, double eps, int krecalc);
+void eig_collect(Context &c, const double2 *q, const double2 *u);
+void eig_diagonalise(Context &c);
+double eig_sign_accuracy(const Context &c);
+void eig_recompute(Context &c, double rho, const ovl_zolo &z, double eta, ovl_stats *st);
+void eig_project(Context &c, const double2 *b, double2 *x0, double2 *Dx0);
+
 // Generators (gen.hip).
 void gauge_generate(Context &c, uint64_t seed, double eps, double *canon_out);
 void source_generate(Context &c, int kind, uint64_t seed, int64_t site, int spin, int colour,

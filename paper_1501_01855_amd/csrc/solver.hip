@@ -149,8 +149,13 @@ static void axpby1(Context &c, zc a, const double2 *x, zc b, double2 *y)
 }
 
 // relSUMR for (1 + rho U) x = bp, starting from x (which holds x0 or zero).
+// Ax0 (nullable) is (1 + rho U) x0 when the caller knows it (the deflated
+// start supplies it from the stored D psi', Sec. 4), which saves a sign call.
+// collect: feed every (q, U q) to eigSUMR (Alg. 5) and use the stricter of the
+// inversion and eigenvector sign accuracies (Sec. 5.1).
 static SumrOut sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, double rhoK, double rho,
-                    const double2 *bp, double2 *x, bool x_is_zero, double tol, double epsA, ovl_stats *st)
+                    const double2 *bp, double2 *x, bool x_is_zero, const double2 *Ax0, double tol, double epsA,
+                    bool collect, ovl_stats *st)
 {
     const size_t FB = field_bytes(c.g, OVL_F64);
     double2 *rt = (double2 *)c.buf("s_rt", FB);
@@ -172,7 +177,11 @@ static SumrOut sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm,
         out.converged = true;
         return out;
     }
-    auto eta_for = [&](double resid) { return std::fmin(prm.relax_floor, epsA * bn / resid); };
+    auto eta_for = [&](double resid) {
+        double e = std::fmin(prm.relax_floor, epsA * bn / resid);
+        if (collect) e = std::fmin(e, eig_sign_accuracy(c));
+        return e;
+    };
     const double zeta = 1.0;
     double resid = bn;
     bool first = true;
@@ -180,6 +189,9 @@ static SumrOut sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm,
         // r~ = b - (1 + rho U) x
         if (first && x_is_zero) {
             copy_fields(c, bp, rt, 1, OVL_F64);
+        } else if (first && Ax0 != nullptr) {
+            copy_fields(c, bp, rt, 1, OVL_F64);
+            axpby1(c, zc(-1.0), Ax0, zc(1.0), rt);
         } else {
             const double eta = eta_for(resid);
             unitary_f64(c, rhoK, z, x, u, 1, eta, prec_for(prm, eta), prm.max_mscg, st);
@@ -224,6 +236,7 @@ static SumrOut sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm,
             const double r_pp = r;
             const double eta_j = eta_for(resid);
             unitary_f64(c, rhoK, z, q, u, 1, eta_j, prec_for(prm, eta_j), prm.max_mscg, st);
+            if (collect) eig_collect(c, q, u);
             gamma = dot1(c, qt, u);
             if (!(std::abs(gamma) < 1.0)) {
                 restart = true;
@@ -297,6 +310,7 @@ ovl_status solve_one(Context &c, const ovl_zolo &z, const ovl_solver_params &prm
 
     zero_fields(c, x, 1, OVL_F64);
     copy_fields(c, b, r, 1, OVL_F64);
+    if (prm.eig_calc) eig_configure(c, prm.n_eig, prm.m_eig, mu, prm.delta_split, prm.eig_eps, prm.k_recalc);
     const double bn = norm_f64(c, b);
     if (bn == 0.0) {
         if (st) st->computed_relres = 0.0;
@@ -315,8 +329,25 @@ ovl_status solve_one(Context &c, const ovl_zolo &z, const ovl_solver_params &prm
             cplx<double> a{2.0 / (1.0 + mu), 0.0}, b0{0.0, 0.0};
             axpby_f64(c, &a, r, &b0, bp, 1);
         }
-        zero_fields(c, uu, 1, OVL_F64);
-        SumrOut so = sumr(c, z, prm, rhoK, rho, bp, uu, true, prm.eta_tilde, prm.eta_tilde, st);
+        // deflated start (Sec. 4): u0 from the eigenspace, (1 + rho U) u0 = 2 D u0/(1 + mu)
+        const bool defl = prm.use_deflation && c.eig.k >= c.eig.n && c.eig.n > 0 && c.eig.ndiag > 0;
+        double2 *Ax0 = nullptr;
+        if (defl) {
+            Ax0 = (double2 *)c.buf("g_Ax0", FB);
+            double2 *Dx0 = (double2 *)c.buf("g_Dx0", FB);
+            eig_project(c, r, uu, Dx0);
+            cplx<double> a{2.0 / (1.0 + mu), 0.0}, b0{0.0, 0.0};
+            axpby_f64(c, &a, Dx0, &b0, Ax0, 1);
+        } else {
+            zero_fields(c, uu, 1, OVL_F64);
+        }
+        const bool collect = prm.eig_calc != 0;
+        SumrOut so = sumr(c, z, prm, rhoK, rho, bp, uu, !defl, Ax0, prm.eta_tilde, prm.eta_tilde, collect, st);
+        if (collect) {
+            eig_diagonalise(c);   // the closing Alg. 6 of Alg. 5
+            if (c.eig.ndiag > 0 && prm.k_recalc > 0 && c.eig.ndiag % prm.k_recalc == 0)
+                eig_recompute(c, rhoK, z, 1e-12, st);
+        }
         (void)so;
         // c = D u, to ||D u - c|| <= eps ||b|| / 4
         const double un = norm_f64(c, uu);
