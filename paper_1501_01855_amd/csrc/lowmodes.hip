@@ -37,21 +37,18 @@ static void applyK(Context &c, double rho, const double2 *X, double2 *Y, int nb)
 static std::vector<zc> gram(Context &c, const double2 *X, int nx, const double2 *Y, int ny)
 {
     std::vector<cplx<double>> d;
-    multidot_f64(c, X, nx, Y, ny, d);   // d[f * nx + j] = (X_j, Y_f)
-    std::vector<zc> G((size_t)nx * ny);
-    for (int f = 0; f < ny; ++f)
-        for (int j = 0; j < nx; ++j) G[(size_t)j * ny + f] = zc(d[(size_t)f * nx + j].re, d[(size_t)f * nx + j].im);
+    gram_f64(c, X, nx, Y, ny, false, d);
+    std::vector<zc> G(d.size());
+    for (size_t i = 0; i < d.size(); ++i) G[i] = zc(d[i].re, d[i].im);
     return G;
 }
 
 // Z_k = sum_j W[j][k] Y_j, W is nY x nZ
 static void rotate(Context &c, const double2 *Y, int nY, const std::vector<zc> &W, double2 *Z, int nZ)
 {
-    zero_fields(c, Z, nZ, OVL_F64);
-    std::vector<cplx<double>> coef((size_t)nZ * nY);
-    for (int k = 0; k < nZ; ++k)
-        for (int j = 0; j < nY; ++j) coef[(size_t)k * nY + j] = {W[(size_t)j * nZ + k].real(), W[(size_t)j * nZ + k].imag()};
-    multiaxpy_f64(c, Y, nY, coef.data(), Z, nZ);
+    std::vector<cplx<double>> w(W.size());
+    for (size_t i = 0; i < W.size(); ++i) w[i] = {W[i].real(), W[i].imag()};
+    rotate_f64(c, Y, nY, w, nZ, Z, 0.0);
 }
 
 // Y <- Y R^{-1} with Y^H Y = R^H R (into Q), twice for orthogonality to rounding.
