@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--half-threshold", type=float, default=3e-3,
+                    help="sign accuracies at or above this use FP16 storage (> 1 disables)")
     ap.add_argument("--no-dslash", action="store_true", help="skip the stand-alone stencil timing")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware counters: one 1 GiB device copy (calibration) "
@@ -62,9 +64,10 @@ def profile_run(torch, ovl):
     print(json.dumps(out))
 
 
-def solve_params(ovl, mixed):
+def solve_params(ovl, mixed, half_threshold=2.0):
     return ovl.solver_defaults(rho=RHO, mu=MU, tol=TOL, eta_tilde=1e-3, relax_floor=1e-2,
-                               f32_threshold=(1e-6 if mixed else 10.0), max_outer=16,
+                               f32_threshold=(1e-6 if mixed else 10.0),
+                               half_threshold=(half_threshold if mixed else 10.0), max_outer=16,
                                max_middle=4000, max_mscg=20000)
 
 
@@ -170,7 +173,8 @@ def main():
     zolo = ovl.zolotarev_coeffs(NZ, a, lmax)
     b = ctx.source(ovl.SRC_GAUSS, seed=102)
 
-    dt_mix, st_mix, prof_mix, x_mix = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, True),
+    dt_mix, st_mix, prof_mix, x_mix = time_solves(torch, ctx, ovl, b, zolo,
+                                                  solve_params(ovl, True, args.half_threshold),
                                                   args.steps, args.warmup)
     dt_64, st_64, prof_64, x_64 = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, False),
                                               max(1, args.steps), 0)

@@ -156,7 +156,7 @@ ovl_status ovl_wilson_dslash(ovl_context *ctx, const double *in_dev, double *out
 {
     return guard([&] {
         check_ctx(ctx);
-        check_prec(prec);
+        check_prec(prec, true);
         OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
         OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
         const size_t FB = field_bytes(ctx->g, prec) * nrhs;
@@ -174,7 +174,7 @@ ovl_status ovl_kernel_K_apply(ovl_context *ctx, double rho, const double *in_dev
 {
     return guard([&] {
         check_ctx(ctx);
-        check_prec(prec);
+        check_prec(prec, true);
         OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
         OVL_REQUIRE(std::isfinite(rho), OVL_ERR_ARG, "rho must be finite");
         OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
@@ -248,7 +248,7 @@ ovl_status ovl_sign_zolotarev_mscg(ovl_context *ctx, double rho, const ovl_zolo 
 {
     return guard([&] {
         check_ctx(ctx);
-        check_prec(prec);
+        check_prec(prec, true);
         check_zolo(zolo);
         OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
         OVL_REQUIRE(eta > 0.0 && std::isfinite(rho), OVL_ERR_ARG, "eta must be positive, rho finite");
@@ -269,7 +269,7 @@ ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_
 {
     return guard([&] {
         check_ctx(ctx);
-        check_prec(prec);
+        check_prec(prec, true);
         check_zolo(zolo);
         OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
         OVL_REQUIRE(eta > 0.0 && std::isfinite(rho) && mu >= 0.0 && mu < 1.0, OVL_ERR_ARG,

@@ -38,6 +38,7 @@ struct Context {
     // gauge field, packed per precision
     double2 *U64 = nullptr;   // [4][9][V]
     float2 *U32 = nullptr;    // [4][9][V]
+    void *U16 = nullptr;      // __half2 [4][9][V]
     bool have_gauge = false;
 
     // kernel low modes: FP64 packed [n][12][V] and eigenvalues

@@ -112,6 +112,7 @@ Context::~Context()
         if (kv.second.p) hipFree(kv.second.p);
     if (U64) hipFree(U64);
     if (U32) hipFree(U32);
+    if (U16) hipFree(U16);
     if (low) hipFree(low);
     if (pinned) hipHostFree(pinned);
     if (grid_counters) hipFree(grid_counters);

@@ -9,6 +9,8 @@
 // 2 x 3 x 3 complex multiply-adds per half spinor.  Neighbour indices are
 // computed arithmetically (no index table).  Spinor and link planes are
 // site-major, so consecutive lanes issue consecutive 16-byte loads.
+#include <type_traits>
+
 #include "context.h"
 #include "fields.h"
 #include "kernels.h"
@@ -66,7 +68,7 @@ __global__ void k_f32_to_f64(const float4 *__restrict__ in, double2 *__restrict_
 }
 
 __global__ void k_pack_gauge(const double2 *__restrict__ canon, double2 *__restrict__ U64,
-                             float2 *__restrict__ U32, int64_t V)
+                             float2 *__restrict__ U32, __half2 *__restrict__ U16, int64_t V)
 {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= V) return;
@@ -76,7 +78,35 @@ __global__ void k_pack_gauge(const double2 *__restrict__ canon, double2 *__restr
             const double2 u = canon[s * 36 + mu * 9 + k];
             U64[(mu * 9 + k) * V + s] = u;
             U32[(mu * 9 + k) * V + s] = make_float2((float)u.x, (float)u.y);
+            U16[(mu * 9 + k) * V + s] = __floats2half2_rn((float)u.x, (float)u.y);
         }
+}
+
+// packed FP64 <-> packed FP16 with per-site scale
+__global__ void k_f64_to_h8(const double2 *__restrict__ in, h8 *__restrict__ out, int64_t V)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    if (s >= V) return;
+    cplx<double> v[12];
+    ld_sp(in + (int64_t)f * 12 * V, V, s, v);
+    cplx<float> w[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[c] = {(float)v[c].re, (float)v[c].im};
+    st_sp(out + f * fstride<h8>(V), V, s, w);
+}
+
+__global__ void k_h8_to_f64(const h8 *__restrict__ in, double2 *__restrict__ out, int64_t V)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    if (s >= V) return;
+    cplx<float> v[12];
+    ld_sp(in + f * fstride<h8>(V), V, s, v);
+    cplx<double> w[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[c] = {(double)v[c].re, (double)v[c].im};
+    st_sp(out + (int64_t)f * 12 * V, V, s, w);
 }
 
 void pack_spinor(Context &c, const double *canon, void *packed, int nf, int prec)
@@ -90,7 +120,9 @@ void pack_spinor(Context &c, const double *canon, void *packed, int nf, int prec
         k_pack_f64<<<grid, 256, 0, c.stream>>>((const double2 *)canon, tmp, g.V);
         k_f64_to_f32<<<grid, 256, 0, c.stream>>>(tmp, (float4 *)packed, g.V);
     } else {
-        throw Error{OVL_ERR_UNSUPPORTED, "pack_spinor: precision"};
+        double2 *tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
+        k_pack_f64<<<grid, 256, 0, c.stream>>>((const double2 *)canon, tmp, g.V);
+        k_f64_to_h8<<<grid, 256, 0, c.stream>>>(tmp, (h8 *)packed, g.V);
     }
     OVL_HIP(hipGetLastError());
 }
@@ -106,7 +138,9 @@ void unpack_spinor(Context &c, const void *packed, double *canon, int nf, int pr
         k_f32_to_f64<<<grid, 256, 0, c.stream>>>((const float4 *)packed, tmp, g.V);
         k_unpack_f64<<<grid, 256, 0, c.stream>>>(tmp, (double2 *)canon, g.V);
     } else {
-        throw Error{OVL_ERR_UNSUPPORTED, "unpack_spinor: precision"};
+        double2 *tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
+        k_h8_to_f64<<<grid, 256, 0, c.stream>>>((const h8 *)packed, tmp, g.V);
+        k_unpack_f64<<<grid, 256, 0, c.stream>>>(tmp, (double2 *)canon, g.V);
     }
     OVL_HIP(hipGetLastError());
 }
@@ -121,6 +155,10 @@ void convert_spinor(Context &c, const void *src, int sprec, void *dst, int dprec
         k_f64_to_f32<<<grid, 256, 0, c.stream>>>((const double2 *)src, (float4 *)dst, g.V);
     } else if (sprec == OVL_F32 && dprec == OVL_F64) {
         k_f32_to_f64<<<grid, 256, 0, c.stream>>>((const float4 *)src, (double2 *)dst, g.V);
+    } else if (sprec == OVL_F64 && dprec == OVL_HALF) {
+        k_f64_to_h8<<<grid, 256, 0, c.stream>>>((const double2 *)src, (h8 *)dst, g.V);
+    } else if (sprec == OVL_HALF && dprec == OVL_F64) {
+        k_h8_to_f64<<<grid, 256, 0, c.stream>>>((const h8 *)src, (double2 *)dst, g.V);
     } else {
         throw Error{OVL_ERR_UNSUPPORTED, "convert_spinor: precision pair"};
     }
@@ -133,9 +171,11 @@ void pack_gauge(Context &c, const double *canon)
     if (!c.U64) {
         OVL_HIP(hipMalloc(&c.U64, (size_t)g.V * 36 * sizeof(double2)));
         OVL_HIP(hipMalloc(&c.U32, (size_t)g.V * 36 * sizeof(float2)));
-        c.bytes_held += (int64_t)g.V * 36 * (16 + 8);
+        OVL_HIP(hipMalloc(&c.U16, (size_t)g.V * 36 * sizeof(__half2)));
+        c.bytes_held += (int64_t)g.V * 36 * (16 + 8 + 4);
     }
-    k_pack_gauge<<<site_blocks(g), 256, 0, c.stream>>>((const double2 *)canon, c.U64, c.U32, g.V);
+    k_pack_gauge<<<site_blocks(g), 256, 0, c.stream>>>((const double2 *)canon, c.U64, c.U32, (__half2 *)c.U16,
+                                                       g.V);
     OVL_HIP(hipGetLastError());
     c.have_gauge = true;
 }
@@ -204,7 +244,6 @@ template <typename ST, typename GT, int EPI, int TPS, bool REMAP>
 __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__restrict__ U)
 {
     using R = typename Planes<ST>::R;
-    constexpr int NP = Planes<ST>::n;
     constexpr int NC = 12 / TPS;   // complex components owned by one lane
     unsigned tile, f;
     tile_of_block<REMAP>(tile, f);
@@ -213,7 +252,7 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
     const int64_t s = (int64_t)tile * (256 / TPS) + (TPS == 2 ? (threadIdx.x & 127) : threadIdx.x);
     const int half = TPS == 2 ? (int)(threadIdx.x >> 7) : 0;
     const bool valid = s < V;
-    const ST *in = a.in + (int64_t)f * NP * V;
+    const ST *in = a.in + f * fstride<ST>(V);
     double part = 0.0;
     cplx<R> acc[12];
 #pragma unroll
@@ -262,7 +301,7 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
         cplx<R> o[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) o[c] = acc[c];
-        ST *out = a.out + (int64_t)f * NP * V;
+        ST *out = a.out + f * fstride<ST>(V);
         if constexpr (EPI == EPI_HOP) {
             if constexpr (TPS == 1) st_sp(out, V, s, o); else st_sp_half(out, V, s, half, o);
         } else {
@@ -277,7 +316,7 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
                 o[c] = (cg < 6) ? d : -d;
             }
             if constexpr (EPI == EPI_K2DOT || EPI == EPI_KPLUS) {
-                const ST *aux = a.aux + (int64_t)f * NP * V;
+                const ST *aux = a.aux + f * fstride<ST>(V);
                 if constexpr (TPS == 1) ld_sp(aux, V, s, x); else ld_sp_half(aux, V, s, half, x);
                 if constexpr (EPI == EPI_K2DOT) {
                     // w = K t + sigma p ; partial (p, w)
@@ -316,11 +355,18 @@ static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, in
 template <typename ST, typename GT, int EPI>
 static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT *U, int nf)
 {
-    switch (id) {
-    case 0: launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf); break;
-    case 1: launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf); break;
-    case 2: launch_variant<ST, GT, EPI, 2, false>(c, a, U, nf); break;
-    default: launch_variant<ST, GT, EPI, 2, true>(c, a, U, nf); break;
+    if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: one thread per site only
+        if (id == 0)
+            launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf);
+        else
+            launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf);
+    } else {
+        switch (id) {
+        case 0: launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf); break;
+        case 1: launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf); break;
+        case 2: launch_variant<ST, GT, EPI, 2, false>(c, a, U, nf); break;
+        default: launch_variant<ST, GT, EPI, 2, true>(c, a, U, nf); break;
+        }
     }
 }
 
@@ -341,7 +387,8 @@ static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int 
     hipEvent_t e0 = c.event(), e1 = c.event();
     int best = 0;
     float best_ms = 1e30f;
-    for (int v = 0; v < N_VARIANTS; ++v) {
+    const int nvar = std::is_same<ST, h8>::value ? 2 : N_VARIANTS;
+    for (int v = 0; v < nvar; ++v) {
         launch_by_id<ST, GT, EPI>(c, v, t, U, nf);   // warm-up
         OVL_HIP(hipEventRecord(e0, c.stream));
         for (int r = 0; r < 5; ++r) launch_by_id<ST, GT, EPI>(c, v, t, U, nf);
@@ -394,7 +441,14 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
         case EPI_KPLUS: launch_stencil_t<float4, float2, EPI_KPLUS>(c, a, c.U32, nf, prec, true); break;
         }
     } else {
-        throw Error{OVL_ERR_UNSUPPORTED, "stencil: precision"};
+        StencilArgs<h8> a{c.g, (const h8 *)in, (h8 *)out, (const h8 *)aux, 4.0 - rho, sigma, partial, stop, it};
+        const __half2 *U = (const __half2 *)c.U16;
+        switch (epi) {
+        case EPI_HOP: launch_stencil_t<h8, __half2, EPI_HOP>(c, a, U, nf, prec, true); break;
+        case EPI_K: launch_stencil_t<h8, __half2, EPI_K>(c, a, U, nf, prec, true); break;
+        case EPI_K2DOT: launch_stencil_t<h8, __half2, EPI_K2DOT>(c, a, U, nf, prec, true); break;
+        case EPI_KPLUS: launch_stencil_t<h8, __half2, EPI_KPLUS>(c, a, U, nf, prec, true); break;
+        }
     }
 }
 

@@ -87,10 +87,68 @@ __device__ __forceinline__ void st_sp_half(float4 *__restrict__ p, int64_t V, in
         p[(3 * h + k) * V + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
 }
 
+// FP16 spinor storage: one h8 = 8 FP16 values = 4 complex numbers.  A field
+// is [3][V] h8 planes followed by one FP32 scale per site (V floats, packed
+// four per h8 slot): the site's 24 reals are stored divided by their largest
+// magnitude (so every stored value is in [-1, 1]).
+struct h8 {
+    uint4 v;
+};
+
 // Number of storage elements of one field per site (planes).
 template <typename ST> struct Planes;
 template <> struct Planes<double2> { static constexpr int n = 12; using R = double; };
 template <> struct Planes<float4> { static constexpr int n = 6; using R = float; };
+template <> struct Planes<h8> { static constexpr int n = 3; using R = float; };
+
+// Elements of ST between consecutive fields.
+template <typename ST> __host__ __device__ __forceinline__ int64_t fstride(int64_t V)
+{
+    return (int64_t)Planes<ST>::n * V;
+}
+template <> __host__ __device__ __forceinline__ int64_t fstride<h8>(int64_t V) { return 3 * V + V / 4; }
+
+__device__ __forceinline__ float2 h2f2(uint32_t w)
+{
+    __half2 h = *reinterpret_cast<__half2 *>(&w);
+    return __half22float2(h);
+}
+__device__ __forceinline__ uint32_t f22h2(float a, float b)
+{
+    __half2 h = __floats2half2_rn(a, b);
+    return *reinterpret_cast<uint32_t *>(&h);
+}
+
+__device__ __forceinline__ void ld_sp(const h8 *__restrict__ p, int64_t V, int64_t s, cplx<float> v[12])
+{
+    const float sc = reinterpret_cast<const float *>(p + 3 * V)[s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint4 t = p[k * V + s].v;
+        const float2 a = h2f2(t.x), b = h2f2(t.y), c = h2f2(t.z), d = h2f2(t.w);
+        v[4 * k] = {a.x * sc, a.y * sc};
+        v[4 * k + 1] = {b.x * sc, b.y * sc};
+        v[4 * k + 2] = {c.x * sc, c.y * sc};
+        v[4 * k + 3] = {d.x * sc, d.y * sc};
+    }
+}
+__device__ __forceinline__ void st_sp(h8 *__restrict__ p, int64_t V, int64_t s, const cplx<float> v[12])
+{
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        uint4 t;
+        t.x = f22h2(v[4 * k].re * inv, v[4 * k].im * inv);
+        t.y = f22h2(v[4 * k + 1].re * inv, v[4 * k + 1].im * inv);
+        t.z = f22h2(v[4 * k + 2].re * inv, v[4 * k + 2].im * inv);
+        t.w = f22h2(v[4 * k + 3].re * inv, v[4 * k + 3].im * inv);
+        p[k * V + s].v = t;
+    }
+    reinterpret_cast<float *>(p + 3 * V)[s] = m;
+}
 
 // ------------------------------------------------------------------ links
 __device__ __forceinline__ void ld_link(const double2 *__restrict__ U, int64_t V, int mu,
@@ -108,6 +166,18 @@ __device__ __forceinline__ void ld_link(const float2 *__restrict__ U, int64_t V,
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         float2 t = U[(mu * 9 + k) * V + s];
+        u[k] = {t.x, t.y};
+    }
+}
+
+// FP16 links: one __half2 per complex entry, [4][9][V] (entries of a unitary
+// matrix have modulus <= 1, so no scale is needed).
+__device__ __forceinline__ void ld_link(const __half2 *__restrict__ U, int64_t V, int mu,
+                                        int64_t s, cplx<float> u[9])
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float2 t = __half22float2(U[(mu * 9 + k) * V + s]);
         u[k] = {t.x, t.y};
     }
 }

@@ -59,13 +59,12 @@ template <typename ST>
 __global__ __launch_bounds__(256) void k_norm2(const ST *__restrict__ x, int64_t V, double *partial)
 {
     using R = typename Planes<ST>::R;
-    constexpr int NP = Planes<ST>::n;
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int f = blockIdx.y;
     double d = 0.0;
     if (s < V) {
         cplx<R> v[12];
-        ld_sp(x + (int64_t)f * NP * V, V, s, v);
+        ld_sp(x + f * fstride<ST>(V), V, s, v);
 #pragma unroll
         for (int c = 0; c < 12; ++c) d += (double)v[c].re * (double)v[c].re + (double)v[c].im * (double)v[c].im;
     }
@@ -83,7 +82,6 @@ __global__ __launch_bounds__(256) void k_mscg_rupdate(const ST *__restrict__ rin
                                                       const double *pw_part, int pw_n, double *rr_part)
 {
     using R = typename Planes<ST>::R;
-    constexpr int NP = Planes<ST>::n;
     const int f = blockIdx.y;
     if (it >= stop[f]) return;
     __shared__ double lds[4];
@@ -93,7 +91,7 @@ __global__ __launch_bounds__(256) void k_mscg_rupdate(const ST *__restrict__ rin
     const double alpha_d = sc.rr / pw;
     const R alpha = (pw > 0.0 && isfinite(alpha_d)) ? (R)alpha_d : R(0);
     double d = 0.0;
-    const int64_t o = (int64_t)f * NP * V;
+    const int64_t o = f * fstride<ST>(V);
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
         cplx<R> a[12], b[12];
         ld_sp(rin + o, V, s, a);
@@ -120,7 +118,6 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
                                                     const double *rr_part, int rr_n)
 {
     using R = typename Planes<ST>::R;
-    constexpr int NP = Planes<ST>::n;
     const int f = blockIdx.y;
     if (it >= stop[f]) return;
     const int nf = gridDim.y;
@@ -178,8 +175,8 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
         if (!s_keep_any || nx.breakdown || nx.iters >= kc->maxiter) stop[f] = it + 1;
     }
     if (!ok) return;
-    const int64_t fo = (int64_t)f * NP * V;
-    const int64_t pstride = (int64_t)nf * NP * V;   // shift-major: p[l][f]
+    const int64_t fo = f * fstride<ST>(V);
+    const int64_t pstride = nf * fstride<ST>(V);   // shift-major: p[l][f]
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
         cplx<R> rv[12], yv[12], pv[12];
         ld_sp(r + fo, V, s, rv);
@@ -213,12 +210,11 @@ __global__ __launch_bounds__(256) void k_low_dots(const double2 *__restrict__ ba
                                                   const ST *__restrict__ x, int64_t V, double *partial)
 {
     using R = typename Planes<ST>::R;
-    constexpr int NP = Planes<ST>::n;
     const int f = blockIdx.y;
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     __shared__ double lds[4];
     cplx<R> xv[12];
-    if (s < V) ld_sp(x + (int64_t)f * NP * V, V, s, xv);
+    if (s < V) ld_sp(x + f * fstride<ST>(V), V, s, xv);
     for (int j = 0; j < n; ++j) {
         double dr = 0.0, di = 0.0;
         if (s < V) {
@@ -255,12 +251,11 @@ __global__ __launch_bounds__(256) void k_low_project(const double2 *__restrict__
                                                      ST *__restrict__ ex, int64_t V)
 {
     using R = typename Planes<ST>::R;
-    constexpr int NP = Planes<ST>::n;
     const int f = blockIdx.y;
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= V) return;
     cplx<R> xv[12];
-    ld_sp(x + (int64_t)f * NP * V, V, s, xv);
+    ld_sp(x + f * fstride<ST>(V), V, s, xv);
     cplx<double> a[12], e[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -285,8 +280,8 @@ __global__ __launch_bounds__(256) void k_low_project(const double2 *__restrict__
         o[c] = {(R)a[c].re, (R)a[c].im};
         oe[c] = {(R)e[c].re, (R)e[c].im};
     }
-    st_sp(xp + (int64_t)f * NP * V, V, s, o);
-    st_sp(ex + (int64_t)f * NP * V, V, s, oe);
+    st_sp(xp + f * fstride<ST>(V), V, s, o);
+    st_sp(ex + f * fstride<ST>(V), V, s, oe);
 }
 
 // --------------------------------------------------------------- host driver
@@ -439,7 +434,7 @@ void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *
     else if (prec == OVL_F32)
         sign_t<float4>(c, rho, z, in, out, nf, eta, prec, maxiter, st);
     else
-        throw Error{OVL_ERR_UNSUPPORTED, "sign: precision"};
+        sign_t<h8>(c, rho, z, in, out, nf, eta, prec, maxiter, st);
 }
 
 }  // namespace ovl

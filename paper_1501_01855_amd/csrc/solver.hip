@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_overlap_combine(const double2 *__restri
 
 static int prec_for(const ovl_solver_params &p, double eta)
 {
+    if (eta >= p.half_threshold) return OVL_HALF;
     if (eta >= p.f32_threshold) return OVL_F32;
     return OVL_F64;
 }

@@ -74,3 +74,19 @@ def test_gamma5_hermiticity_gpu():
     Kb = to_host(ctx.kernel_K_apply(to_dev(b), 1.4))
     lhs, rhs = np.vdot(a, Kb), np.vdot(Ka, b)
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("dims", CASES[:2])
+def test_hop_and_K_half(dims):
+    """FP16 links and FP16 spinors (per-site scale), FP32 arithmetic: errors of
+    a few units of 2^-11 relative to the field's largest component."""
+    ovl = require_gpu()
+    U = synth.gauge_field(dims, 13, 0.4)
+    ora = WilsonKernel(dims, U, 1.4)
+    psi = synth.gaussian_source(dims, 5)
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(U))
+    h = to_host(ctx.wilson_dslash(to_dev(psi), prec=ovl.HALF))
+    k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4, prec=ovl.HALF))
+    assert max_rel_elem(h, ora.hop(psi)) < 5e-3
+    assert rel(k, ora.K(psi)) < 2e-3

@@ -120,3 +120,28 @@ def test_solve_c1(c1, ladder):
     if ladder == "mixed":
         assert s.sign_calls[1] > 0          # single-precision sign calls used
     print("stats", s.as_dict())
+
+
+def test_sign_half_error(c1):
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    psi = synth.gaussian_source(c1.dims, 26)
+    got = to_host(ctx.sign(to_dev(psi), 1.4, zg, 1e-2, prec=ovl.HALF)[0])
+    ref = c1.sign(psi, 1e-14)
+    assert rel(got, ref) < 1e-2
+
+
+def test_solve_c1_half_ladder(c1):
+    """Sign calls with accuracy >= 3e-3 in FP16 storage, >= 1e-6 in FP32, the
+    rest in FP64: still a true residual <= 1e-10."""
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    b = synth.z2_source(c1.dims, 31)
+    p = ovl.solver_defaults(rho=1.4, mu=0.05, tol=1e-10, eta_tilde=1e-3, f32_threshold=1e-6,
+                            half_threshold=3e-3)
+    x, st, code = ctx.solve(to_dev(b), zg, p)
+    assert code == 0
+    D = krylov.Overlap(c1.sign, 0.05)
+    assert norm(b - D(to_host(x), 1e-15)) / norm(b) <= 1e-10
+    assert st[0].sign_calls[2] > 0
+    print("half ladder stats", st[0].as_dict())
