@@ -89,6 +89,7 @@ __global__ __launch_bounds__(256) void k_axpby(AxpbyCoef k, const double2 *__res
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const cplx<double> af = {k.a[f].re, k.a[f].im}, bf = {k.b[f].re, k.b[f].im};
+    if (af.re == 0.0 && af.im == 0.0 && bf.re == 1.0 && bf.im == 0.0) return;   // field left as is
     const double2 xv = x[(int64_t)f * n + i];
     cplx<double> r = af * cplx<double>{xv.x, xv.y};
     if (bf.re != 0.0 || bf.im != 0.0) {   // b = 0: y is not read (it may be uninitialised)

@@ -1,6 +1,7 @@
 // extern "C" entry points (include/ovl.h): argument checks, layout packing
 // between the canonical complex128 layout and the internal planes, error
 // translation.  No exception crosses this boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -301,14 +302,17 @@ ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo, const o
                     OVL_ERR_ARG, "invalid solver parameters");
         OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
         const size_t FB = field_bytes(ctx->g, OVL_F64);
-        double2 *b = (double2 *)ctx->buf("api_b64", FB);
-        double2 *x = (double2 *)ctx->buf("api_x64", FB);
-        for (int f = 0; f < nrhs; ++f) {
-            ovl_stats *s = stats_host ? stats_host + f : nullptr;
-            if (s) std::memset(s, 0, sizeof(*s));
-            pack_spinor(*ctx, b_dev + (size_t)f * ctx->g.V * 24, b, 1, OVL_F64);
-            const ovl_status r = solve_one(*ctx, *zolo, p, b, x, s);
-            unpack_spinor(*ctx, x, x_dev + (size_t)f * ctx->g.V * 24, 1, OVL_F64);
+        if (stats_host) std::memset(stats_host, 0, sizeof(ovl_stats) * nrhs);
+        // calculating (eigSUMR) solves run one right-hand side after another;
+        // otherwise all right-hand sides are solved together
+        const int batch = p.eig_calc ? 1 : nrhs;
+        double2 *b = (double2 *)ctx->buf("api_b64", FB * batch);
+        double2 *x = (double2 *)ctx->buf("api_x64", FB * batch);
+        for (int f0 = 0; f0 < nrhs; f0 += batch) {
+            const int nb = std::min(batch, nrhs - f0);
+            pack_spinor(*ctx, b_dev + (size_t)f0 * ctx->g.V * 24, b, nb, OVL_F64);
+            const ovl_status r = solve_batch(*ctx, *zolo, p, b, x, nb, stats_host ? stats_host + f0 : nullptr);
+            unpack_spinor(*ctx, x, x_dev + (size_t)f0 * ctx->g.V * 24, nb, OVL_F64);
             if (r != OVL_OK && worst == OVL_OK) worst = r;
         }
         OVL_HIP(hipStreamSynchronize(ctx->stream));

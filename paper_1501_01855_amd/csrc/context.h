@@ -60,6 +60,7 @@ struct Context {
     std::vector<hipEvent_t> free_events;
     ProfileSlot slots[KERN_COUNT][3];
     int64_t last_mscg_iters = 0;
+    std::vector<int64_t> last_field_iters;   // per field, last sign call
 
     unsigned *grid_counters = nullptr;   // zero between launches (reset by the last block)
 

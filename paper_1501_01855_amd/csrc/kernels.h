@@ -39,7 +39,7 @@ double stencil_bytes(const Geom &g, int prec, int epi);
 // dots[f] = (x_f, y_f) complex, computed with a fixed reduction order.
 void dot_f64(Context &c, const double2 *x, const double2 *y, int nf, std::vector<cplx<double>> &out);
 void norm2_f64(Context &c, const double2 *x, int nf, std::vector<double> &out);
-// y_f = a_f x_f + b_f y_f (y not read when b_f = 0)
+// y_f = a_f x_f + b_f y_f (y not read when b_f = 0; field untouched when a_f = 0, b_f = 1)
 void axpby_f64(Context &c, const cplx<double> *a, const double2 *x, const cplx<double> *b, double2 *y, int nf);
 // out[row] = sum_i partial[row][i], i < nblk (fixed order)
 void sum_partials(Context &c, const double *partial, int nblk, int rows, double *out);

@@ -33,7 +33,8 @@ struct MscgFinal {
     int iters, breakdown, act_total, pad;
 };
 
-__global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int nblk, MscgConst k)
+__global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int nblk, MscgConst k,
+                            const double *eta2)
 {
     __shared__ double lds[4];
     const int f = blockIdx.x;
@@ -41,7 +42,9 @@ __global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int n
     if (threadIdx.x != 0) return;
     MscgScal &s = S[f];   // parity 0
     s.rr = b2;
-    s.b2 = b2;
+    // the freezing test uses eta_f^2 ||b||^2; eta_f <= 0 marks a field to skip
+    const double e2 = eta2[f];
+    s.b2 = e2 > 0.0 ? e2 * b2 : 0.0;
     s.alpha_old = 1.0;
     s.beta_old = 0.0;
     s.iters = 0;
@@ -52,7 +55,7 @@ __global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int n
         s.zeta_old[l] = 1.0;
         s.act[l] = b2 > 0.0 ? 1 : 0;
     }
-    stop[f] = b2 > 0.0 ? 0x7fffffff : 0;
+    stop[f] = (b2 > 0.0 && e2 > 0.0) ? 0x7fffffff : 0;
 }
 
 template <typename ST>
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(256) void k_low_project(const double2 *__restrict__
 // --------------------------------------------------------------- host driver
 template <typename ST>
 static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
-                   double eta, int prec, int maxiter, ovl_stats *st)
+                   const double *eta, int prec, int maxiter, ovl_stats *st)
 {
     const Geom &g = c.g;
     const int64_t V = g.V;
@@ -299,7 +302,12 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     const dim3 ugrid(nupd, nf);
     const int nz = z.n_z;
     OVL_REQUIRE(nz >= 1 && nz <= NZMAX, OVL_ERR_ARG, "n_z out of range");
-    OVL_REQUIRE(eta > 0.0, OVL_ERR_ARG, "eta must be positive");
+    int nact = 0;
+    std::vector<double> eta2(nf);
+    for (int f = 0; f < nf; ++f) {
+        eta2[f] = eta[f] > 0.0 ? eta[f] * eta[f] : 0.0;
+        nact += eta[f] > 0.0;
+    }
     for (int l = 0; l < nz; ++l)
         OVL_REQUIRE(z.sigma[l] > 0.0 && z.omega[l] > 0.0, OVL_ERR_ARG, "Zolotarev coefficients must be positive");
 
@@ -346,13 +354,15 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     for (int l = 0; l < nz; ++l) {
         k.sigma[l] = z.sigma[l];
         k.omega[l] = z.omega[l];
-        const double tl = eta * 2.0 * std::sqrt(z.sigma[l]) / (nz * z.omega[l]);
+        const double tl = 2.0 * std::sqrt(z.sigma[l]) / (nz * z.omega[l]);
         k.tol2[l] = tl * tl;
     }
     OVL_HIP(hipMemcpyAsync(kdev, &k, sizeof(MscgConst), hipMemcpyHostToDevice, c.stream));
     zero_fields(c, y, nf, prec);   // y stays zero for a zero source
     k_norm2<ST><<<grid, 256, 0, c.stream>>>(src, V, part);
-    k_mscg_init<<<nf, 256, 0, c.stream>>>(S, stop, part, nblk, k);
+    double *eta2d = (double *)c.buf("ms_eta2", sizeof(double) * nf);
+    OVL_HIP(hipMemcpyAsync(eta2d, eta2.data(), sizeof(double) * nf, hipMemcpyHostToDevice, c.stream));
+    k_mscg_init<<<nf, 256, 0, c.stream>>>(S, stop, part, nblk, k, eta2d);
     OVL_HIP(hipGetLastError());
 
     // 3. iterations; poll the stop flags every CHUNK iterations, one chunk behind
@@ -416,10 +426,13 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     }
     if (st) {
         st->mscg_iters += iters;
-        st->dslash_calls[prec] += 2 * iters + nf;
-        st->sign_calls[prec] += nf;
+        st->dslash_calls[prec] += 2 * iters + nact;
+        st->sign_calls[prec] += nact;
     }
     c.last_mscg_iters = iters;
+    c.last_field_iters.assign(nf, 0);
+    for (int f = 0; f < nf; ++f)
+        if (hstop_final[f] != 0) c.last_field_iters[f] = hs[f].iters;
     // algorithmic bytes of the shift kernel: r, y in, y out, 2 per active shift
     if (c.prof) c.slots[KERN_SHIFT][prec].bytes += (double)FB * (3.0 * iters + 2.0 * act_total);
     OVL_REQUIRE(!brk, OVL_ERR_BREAKDOWN, "multi-shift CG breakdown (non-positive curvature or NaN)");
@@ -427,7 +440,7 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
 }
 
 void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
-               double eta, int prec, int maxiter, ovl_stats *st)
+               const double *eta, int prec, int maxiter, ovl_stats *st)
 {
     if (prec == OVL_F64)
         sign_t<double2>(c, rho, z, in, out, nf, eta, prec, maxiter, st);
@@ -435,6 +448,14 @@ void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *
         sign_t<float4>(c, rho, z, in, out, nf, eta, prec, maxiter, st);
     else
         sign_t<h8>(c, rho, z, in, out, nf, eta, prec, maxiter, st);
+}
+
+void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
+               double eta, int prec, int maxiter, ovl_stats *st)
+{
+    OVL_REQUIRE(eta > 0.0, OVL_ERR_ARG, "eta must be positive");
+    std::vector<double> e(nf, eta);
+    sign_mscg(c, rho, z, in, out, nf, e.data(), prec, maxiter, st);
 }
 
 }  // namespace ovl

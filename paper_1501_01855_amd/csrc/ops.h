@@ -7,6 +7,9 @@ namespace ovl {
 // sign(K) in -> out, packed fields of precision prec (mscg.hip).
 void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
                double eta, int prec, int maxiter, ovl_stats *st);
+// per-field accuracies eta[f]; eta[f] <= 0 skips field f (its output is unspecified)
+void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
+               const double *eta, int prec, int maxiter, ovl_stats *st);
 
 // out = D[mu] in, packed FP64 in/out; the sign function in precision prec
 // (conversions at its boundary) (solver.hip).
@@ -16,9 +19,14 @@ void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const dou
 // Zolotarev coefficients (zolo.cpp).
 void zolotarev(int nz, double a, double b, ovl_zolo &out);
 
-// GMRESR(relSUMR) for one right-hand side, packed FP64 b and x (solver.hip).
-ovl_status solve_one(Context &c, const ovl_zolo &z, const ovl_solver_params &p, const double2 *b,
-                     double2 *x, ovl_stats *st);
+// out = D[mu] in with per-field accuracies (eta[f] <= 0 skips field f).
+void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in, double2 *out,
+                 int nf, const double *eta, int prec, int maxiter, ovl_stats *st);
+
+// GMRESR(relSUMR) for nf right-hand sides solved together, packed FP64 b and
+// x (nf contiguous fields); st has nf entries (solver.hip).
+ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p, const double2 *b,
+                       double2 *x, int nf, ovl_stats *st);
 
 // Kernel low modes (lowmodes.hip).
 void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *evals, double *lmax);

@@ -4,11 +4,17 @@
 //            U = gamma_5 sign(K), rho' = (1 - mu)/(1 + mu), b' = 2 b/(1 + mu),
 //            sign accuracy eta_j = min(floor, eps_A ||b'|| / ||r_j||)   (Sec. 3)
 //   GMRESR:  Alg. 3 around relSUMR, outer vectors and residual in FP64.
-// The SUMR and GMRESR vectors are packed FP64 fields on the device; their
-// scalar recurrences (a few complex numbers per iteration) run on the host,
-// which reads back one inner product and one norm per SUMR iteration.  The
-// sign function's precision follows its requested accuracy (Sec. 3: single
-// precision once the accuracy asked for is looser than a threshold).
+//
+// nf right-hand sides are solved together: every vector operation runs on all
+// nf fields in one launch (per-field coefficients passed by value), and every
+// sign-function call applies the multi-shift CG to all active fields at once,
+// so one gauge-link read serves all of them.  Each right-hand side keeps its
+// own scalar recurrences (on the host: a few complex numbers per iteration),
+// its own accuracy and its own convergence; finished fields are masked out.
+// The sign function's precision follows the strictest accuracy asked for
+// among the active fields (Sec. 3: single precision once the accuracy is
+// looser than a threshold; here also an FP16-storage level).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -21,6 +27,7 @@
 namespace ovl {
 
 using zc = std::complex<double>;
+static constexpr int MAXF = 16;
 
 // out = a in + b gamma_5 s   (flat FP64 fields, n = 12 V complex each)
 __global__ __launch_bounds__(256) void k_overlap_combine(const double2 *__restrict__ in,
@@ -43,346 +50,468 @@ static int prec_for(const ovl_solver_params &p, double eta)
     return OVL_F64;
 }
 
-// u = gamma_5 sign(K) q (FP64 packed in/out), sign in precision prec.
-static void unitary_f64(Context &c, double rho, const ovl_zolo &z, const double2 *q, double2 *u, int nf,
-                        double eta, int prec, int maxiter, ovl_stats *st)
+static double min_active(const double *eta, int nf)
 {
-    if (prec == OVL_F64) {
-        sign_mscg(c, rho, z, q, u, nf, eta, prec, maxiter, st);
-    } else {
-        const size_t FB = field_bytes(c.g, prec) * nf;
-        void *a = c.buf("u_lo_in", FB);
-        void *b = c.buf("u_lo_out", FB);
-        convert_spinor(c, q, OVL_F64, a, prec, nf);
-        sign_mscg(c, rho, z, a, b, nf, eta, prec, maxiter, st);
-        convert_spinor(c, b, prec, u, OVL_F64, nf);
-    }
-    gamma5_f64(c, u, nf);
+    double m = 1e300;
+    for (int f = 0; f < nf; ++f)
+        if (eta[f] > 0.0) m = std::min(m, eta[f]);
+    return m;
 }
 
-void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in, double2 *out,
-                 int nf, double eta, int prec, int maxiter, ovl_stats *st)
+// s = sign(K) in (FP64 packed in/out) with the multi-shift CG in precision
+// prec.  Counters: with per_field, st has nf entries and field f's work goes
+// to st[f]; otherwise st is one aggregate.
+static void sign_f64(Context &c, double rho, const ovl_zolo &z, const double2 *in, double2 *s, int nf,
+                     const double *eta, int prec, int maxiter, ovl_stats *st, bool per_field)
 {
-    double2 *s = (double2 *)c.buf("ov_s", field_bytes(c.g, OVL_F64) * nf);
+    ovl_stats *agg = per_field ? nullptr : st;
     if (prec == OVL_F64) {
-        sign_mscg(c, rho, z, in, s, nf, eta, prec, maxiter, st);
+        sign_mscg(c, rho, z, in, s, nf, eta, prec, maxiter, agg);
     } else {
         const size_t FB = field_bytes(c.g, prec) * nf;
         void *a = c.buf("u_lo_in", FB);
         void *b = c.buf("u_lo_out", FB);
         convert_spinor(c, in, OVL_F64, a, prec, nf);
-        sign_mscg(c, rho, z, a, b, nf, eta, prec, maxiter, st);
+        sign_mscg(c, rho, z, a, b, nf, eta, prec, maxiter, agg);
         convert_spinor(c, b, prec, s, OVL_F64, nf);
     }
+    if (per_field && st)
+        for (int f = 0; f < nf; ++f)
+            if (eta[f] > 0.0) {
+                const int64_t it = f < (int)c.last_field_iters.size() ? c.last_field_iters[f] : 0;
+                st[f].mscg_iters += it;
+                st[f].dslash_calls[prec] += 2 * it + 1;
+                st[f].sign_calls[prec] += 1;
+            }
+}
+
+// u = gamma_5 sign(K) q for the fields with eta[f] > 0.
+static void unitary_f64(Context &c, double rho, const ovl_zolo &z, const double2 *q, double2 *u, int nf,
+                        const double *eta, const ovl_solver_params &prm, ovl_stats *st)
+{
+    sign_f64(c, rho, z, q, u, nf, eta, prec_for(prm, min_active(eta, nf)), prm.max_mscg, st, true);
+    gamma5_f64(c, u, nf);
+}
+
+static void overlap_impl(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in, double2 *out,
+                         int nf, const double *eta, int prec, int maxiter, ovl_stats *st, bool per_field)
+{
+    double2 *s = (double2 *)c.buf("ov_s", field_bytes(c.g, OVL_F64) * nf);
+    sign_f64(c, rho, z, in, s, nf, eta, prec, maxiter, st, per_field);
     const int64_t V = c.g.V;
     k_overlap_combine<<<dim3((unsigned)((12 * V + 255) / 256), nf), 256, 0, c.stream>>>(
         in, s, out, 0.5 * (1.0 + mu), 0.5 * (1.0 - mu), V);
     OVL_HIP(hipGetLastError());
 }
 
-// One fused SUMR vector step (the vector statements of Alg. 2, in order):
+void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in, double2 *out, int nf,
+                 const double *eta, int prec, int maxiter, ovl_stats *st)
+{
+    overlap_impl(c, rho, mu, z, in, out, nf, eta, prec, maxiter, st, false);
+}
+
+void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in, double2 *out, int nf,
+                 double eta, int prec, int maxiter, ovl_stats *st)
+{
+    std::vector<double> e(nf, eta);
+    overlap_impl(c, rho, mu, z, in, out, nf, e.data(), prec, maxiter, st, false);
+}
+
+// One fused SUMR vector step per field (the vector statements of Alg. 2, in order):
 //   omega_old = omega; omega = alpha p + kappa (q_old - omega)
 //   p = p + lambda (q_old - omega_old)
 //   x = x + eta (q - omega)
 //   q_old = q; q = (gamma q_t + u)/sigma; q_t = sigma q_t + conj(gamma) q
-// q_new is written over the q_old buffer (the caller swaps the two), and a
-// partial ||q_new||^2 is produced.
+// and ||q_new||^2 per block.  Fields with act[f] = 0 are left untouched.
 struct SumrCoef {
-    double ar, ai, kr, ki, lr, li, er, ei, gr, gi, sigma;
+    double ar[MAXF], ai[MAXF], kr[MAXF], ki[MAXF], lr[MAXF], li[MAXF], er[MAXF], ei[MAXF], gr[MAXF], gi[MAXF],
+        sigma[MAXF];
+    int act[MAXF];
 };
 
 __global__ __launch_bounds__(256) void k_sumr_step(SumrCoef k, double2 *__restrict__ x, double2 *__restrict__ p,
-                                                   double2 *__restrict__ om, double2 *__restrict__ qold_qnew,
-                                                   const double2 *__restrict__ q, double2 *__restrict__ qt,
+                                                   double2 *__restrict__ om, double2 *__restrict__ qold,
+                                                   double2 *__restrict__ q, double2 *__restrict__ qt,
                                                    const double2 *__restrict__ u, int64_t n, double *partial)
 {
+    const int f = blockIdx.y;
     double nn = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double2 pv = p[i], ov = om[i], qo = qold_qnew[i], qv = q[i], tv = qt[i], uv = u[i], xv = x[i];
-        const cplx<double> P{pv.x, pv.y}, O{ov.x, ov.y}, QO{qo.x, qo.y}, Q{qv.x, qv.y}, T{tv.x, tv.y},
-            U{uv.x, uv.y}, X{xv.x, xv.y};
-        const cplx<double> alpha{k.ar, k.ai}, kappa{k.kr, k.ki}, lam{k.lr, k.li}, eta{k.er, k.ei},
-            gam{k.gr, k.gi};
-        const cplx<double> On = alpha * P + kappa * (QO - O);
-        const cplx<double> Pn = P + lam * (QO - O);
-        const cplx<double> Xn = X + eta * (Q - On);
-        const double is = 1.0 / k.sigma;
-        const cplx<double> Qn = is * (gam * T + U);
-        const cplx<double> Tn = k.sigma * T + cmul_conj(gam, Qn);
-        om[i] = make_double2(On.re, On.im);
-        p[i] = make_double2(Pn.re, Pn.im);
-        x[i] = make_double2(Xn.re, Xn.im);
-        qold_qnew[i] = make_double2(Qn.re, Qn.im);
-        qt[i] = make_double2(Tn.re, Tn.im);
-        nn += Qn.re * Qn.re + Qn.im * Qn.im;
+    if (k.act[f]) {
+        const cplx<double> alpha{k.ar[f], k.ai[f]}, kappa{k.kr[f], k.ki[f]}, lam{k.lr[f], k.li[f]},
+            eta{k.er[f], k.ei[f]}, gam{k.gr[f], k.gi[f]};
+        const double sg = k.sigma[f], is = 1.0 / sg;
+        const int64_t o = (int64_t)f * n;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t j = o + i;
+            const double2 pv = p[j], ov = om[j], qo = qold[j], qv = q[j], tv = qt[j], uv = u[j], xv = x[j];
+            const cplx<double> P{pv.x, pv.y}, O{ov.x, ov.y}, QO{qo.x, qo.y}, Q{qv.x, qv.y}, T{tv.x, tv.y},
+                U{uv.x, uv.y}, X{xv.x, xv.y};
+            const cplx<double> On = alpha * P + kappa * (QO - O);
+            const cplx<double> Pn = P + lam * (QO - O);
+            const cplx<double> Xn = X + eta * (Q - On);
+            const cplx<double> Qn = is * (gam * T + U);
+            const cplx<double> Tn = sg * T + cmul_conj(gam, Qn);
+            om[j] = make_double2(On.re, On.im);
+            p[j] = make_double2(Pn.re, Pn.im);
+            x[j] = make_double2(Xn.re, Xn.im);
+            qold[j] = qv;
+            q[j] = make_double2(Qn.re, Qn.im);
+            qt[j] = make_double2(Tn.re, Tn.im);
+            nn += Qn.re * Qn.re + Qn.im * Qn.im;
+        }
     }
     __shared__ double lds[4];
     const double t = block_sum<256>(nn, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    if (threadIdx.x == 0) partial[(int64_t)f * gridDim.x + blockIdx.x] = t;
 }
 
-struct SumrOut {
-    int iters = 0;
-    int restarts = 0;
-    double resid = 0.0;
-    bool converged = false;
-};
-
-static double norm_f64(Context &c, const double2 *x)
+static void norms(Context &c, const double2 *x, int nf, std::vector<double> &out)
 {
-    std::vector<double> n2;
-    norm2_f64(c, x, 1, n2);
-    return std::sqrt(n2[0]);
+    norm2_f64(c, x, nf, out);
+    for (auto &v : out) v = std::sqrt(std::max(0.0, v));
 }
 
-static zc dot1(Context &c, const double2 *x, const double2 *y)
+static void dots(Context &c, const double2 *x, const double2 *y, int nf, std::vector<zc> &out)
 {
     std::vector<cplx<double>> d;
-    dot_f64(c, x, y, 1, d);
-    return zc(d[0].re, d[0].im);
+    dot_f64(c, x, y, nf, d);
+    out.resize(nf);
+    for (int f = 0; f < nf; ++f) out[f] = zc(d[f].re, d[f].im);
 }
 
-// y = a x + b y  (complex scalars, one field)
-static void axpby1(Context &c, zc a, const double2 *x, zc b, double2 *y)
+// y_f = a_f x_f + b_f y_f over nf fields (a_f = 0, b_f = 1 leaves field f as is)
+static void axpby(Context &c, const std::vector<zc> &a, const double2 *x, const std::vector<zc> &b, double2 *y,
+                  int nf)
 {
-    cplx<double> ca{a.real(), a.imag()}, cb{b.real(), b.imag()};
-    axpby_f64(c, &ca, x, &cb, y, 1);
+    std::vector<cplx<double>> ca(nf), cb(nf);
+    for (int f = 0; f < nf; ++f) {
+        ca[f] = {a[f].real(), a[f].imag()};
+        cb[f] = {b[f].real(), b[f].imag()};
+    }
+    axpby_f64(c, ca.data(), x, cb.data(), y, nf);
 }
 
-// relSUMR for (1 + rho U) x = bp, starting from x (which holds x0 or zero).
-// Ax0 (nullable) is (1 + rho U) x0 when the caller knows it (the deflated
-// start supplies it from the stored D psi', Sec. 4), which saves a sign call.
-// collect: feed every (q, U q) to eigSUMR (Alg. 5) and use the stricter of the
-// inversion and eigenvector sign accuracies (Sec. 5.1).
-static SumrOut sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, double rhoK, double rho,
-                    const double2 *bp, double2 *x, bool x_is_zero, const double2 *Ax0, double tol, double epsA,
-                    bool collect, ovl_stats *st)
+struct SumrField {
+    zc phi_hat, tau_hat, phi, s, lam, c_dag, cc;
+    double r = 1.0, delta = 0.0, bn = 0.0, resid = 0.0;
+    int iters = 0, restarts = 0;
+    bool active = false, need_init = true;
+};
+
+// relSUMR for (1 + rho U) x_f = bp_f on the fields with mask[f], x holding x0
+// (zero when x_zero).  Ax0 (nullable) holds (1 + rho U) x0 when the caller
+// knows it (the deflated start supplies it from the stored D psi', Sec. 4),
+// which saves a sign call.  collect (one field only): feed every (q, U q) to
+// eigSUMR (Alg. 5) and use the stricter of the inversion and eigenvector sign
+// accuracies (Sec. 5.1).
+static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, double rhoK, double rho,
+                 const double2 *bp, double2 *x, int nf, const std::vector<int> &mask, bool x_zero,
+                 const double2 *Ax0, double tol, double epsA, bool collect, ovl_stats *st)
 {
     const size_t FB = field_bytes(c.g, OVL_F64);
-    double2 *rt = (double2 *)c.buf("s_rt", FB);
-    double2 *p = (double2 *)c.buf("s_p", FB);
-    double2 *om = (double2 *)c.buf("s_om", FB);
-    double2 *qa = (double2 *)c.buf("s_qa", FB);
-    double2 *qb = (double2 *)c.buf("s_qb", FB);
-    double2 *qt = (double2 *)c.buf("s_qt", FB);
-    double2 *u = (double2 *)c.buf("s_u", FB);
+    double2 *rt = (double2 *)c.buf("s_rt", FB * nf);
+    double2 *p = (double2 *)c.buf("s_p", FB * nf);
+    double2 *om = (double2 *)c.buf("s_om", FB * nf);
+    double2 *q = (double2 *)c.buf("s_q", FB * nf);
+    double2 *qold = (double2 *)c.buf("s_qold", FB * nf);
+    double2 *qt = (double2 *)c.buf("s_qt", FB * nf);
+    double2 *u = (double2 *)c.buf("s_u", FB * nf);
     const int64_t n = 12 * c.g.V;
-    const int nblk = 512;
-    double *part = (double *)c.buf("s_part", sizeof(double) * nblk);
-    double *res = (double *)c.buf("s_res", sizeof(double));
+    const int nblk = 256;
+    double *part = (double *)c.buf("s_part", sizeof(double) * nblk * nf);
+    double *res = (double *)c.buf("s_res", sizeof(double) * nf);
+    const double zeta = 1.0;
 
-    const double bn = norm_f64(c, bp);
-    SumrOut out;
-    if (bn == 0.0) {
-        zero_fields(c, x, 1, OVL_F64);
-        out.converged = true;
-        return out;
+    std::vector<SumrField> F(nf);
+    std::vector<double> bn;
+    norms(c, bp, nf, bn);
+    for (int f = 0; f < nf; ++f) {
+        F[f].bn = bn[f];
+        F[f].active = mask[f] != 0 && bn[f] > 0.0;
+        F[f].resid = bn[f];
     }
-    auto eta_for = [&](double resid) {
-        double e = std::fmin(prm.relax_floor, epsA * bn / resid);
+    bool first = true;
+    auto eta_for = [&](const SumrField &sf) {
+        double e = std::fmin(prm.relax_floor, epsA * sf.bn / sf.resid);
         if (collect) e = std::fmin(e, eig_sign_accuracy(c));
         return e;
     };
-    const double zeta = 1.0;
-    double resid = bn;
-    bool first = true;
+    std::vector<double> eta(nf, 0.0);
     while (true) {
-        // r~ = b - (1 + rho U) x
-        if (first && x_is_zero) {
-            copy_fields(c, bp, rt, 1, OVL_F64);
-        } else if (first && Ax0 != nullptr) {
-            copy_fields(c, bp, rt, 1, OVL_F64);
-            axpby1(c, zc(-1.0), Ax0, zc(1.0), rt);
-        } else {
-            const double eta = eta_for(resid);
-            unitary_f64(c, rhoK, z, x, u, 1, eta, prec_for(prm, eta), prm.max_mscg, st);
-            copy_fields(c, bp, rt, 1, OVL_F64);
-            axpby1(c, zc(-1.0), x, zc(1.0), rt);
-            axpby1(c, zc(-rho), u, zc(1.0), rt);
+        // (re)initialise the fields that need it: r~ = b - (1 + rho U) x
+        bool any_init = false;
+        std::vector<int> init(nf, 0);
+        for (int f = 0; f < nf; ++f) {
+            init[f] = F[f].active && F[f].need_init;
+            any_init = any_init || init[f];
+        }
+        if (any_init) {
+            std::vector<zc> ca(nf, 0.0), cb(nf, 1.0);
+            for (int f = 0; f < nf; ++f)
+                if (init[f]) {
+                    ca[f] = 1.0;
+                    cb[f] = 0.0;
+                }
+            axpby(c, ca, bp, cb, rt, nf);   // rt = bp on the (re)starting fields
+            const bool need_ux = !(first && x_zero) && !(first && Ax0 != nullptr);
+            if (first && !x_zero && Ax0 != nullptr) {
+                std::vector<zc> a2(nf, 0.0), b2(nf, 1.0);
+                for (int f = 0; f < nf; ++f)
+                    if (init[f]) a2[f] = -1.0;
+                axpby(c, a2, Ax0, b2, rt, nf);
+            } else if (need_ux) {
+                for (int f = 0; f < nf; ++f) eta[f] = init[f] ? eta_for(F[f]) : 0.0;
+                unitary_f64(c, rhoK, z, x, u, nf, eta.data(), prm, st);
+                std::vector<zc> a1(nf, 0.0), a2(nf, 0.0), b1(nf, 1.0);
+                for (int f = 0; f < nf; ++f)
+                    if (init[f]) {
+                        a1[f] = -1.0;
+                        a2[f] = -rho;
+                    }
+                axpby(c, a1, x, b1, rt, nf);
+                axpby(c, a2, u, b1, rt, nf);
+            }
+            std::vector<double> dl;
+            norms(c, rt, nf, dl);
+            std::vector<zc> qa(nf, 0.0), qb(nf, 1.0), zz(nf, 0.0), z1(nf, 1.0), a0(nf, 0.0);
+            for (int f = 0; f < nf; ++f) {
+                SumrField &sf = F[f];
+                if (!init[f]) continue;
+                if (!std::isfinite(dl[f])) throw Error{OVL_ERR_BREAKDOWN, "SUMR: non-finite residual"};
+                sf.delta = dl[f];
+                sf.resid = dl[f];
+                sf.need_init = false;
+                if (dl[f] <= tol * sf.bn) {
+                    sf.active = false;
+                    continue;
+                }
+                sf.phi_hat = 1.0 / sf.delta;
+                sf.tau_hat = sf.delta / rho;
+                sf.phi = 0.0;
+                sf.s = 0.0;
+                sf.lam = 0.0;
+                sf.c_dag = 1.0;
+                sf.cc = 1.0;
+                sf.r = 1.0;
+                qa[f] = 1.0 / sf.delta;
+                qb[f] = 0.0;
+                a0[f] = 1.0;
+                z1[f] = 0.0;
+            }
+            axpby(c, qa, rt, qb, q, nf);      // q = r~/delta on the (re)started fields
+            axpby(c, a0, q, z1, qt, nf);      // q_t = q
+            axpby(c, zz, rt, z1, om, nf);     // omega = 0  (0 times the finite r~)
+            axpby(c, zz, rt, z1, p, nf);      // p = 0
+            axpby(c, zz, rt, z1, qold, nf);   // q_old = 0
         }
         first = false;
-        double delta = norm_f64(c, rt);
-        if (!std::isfinite(delta)) throw Error{OVL_ERR_BREAKDOWN, "SUMR: non-finite residual"};
-        resid = delta;
-        if (delta <= tol * bn) {
-            out.resid = delta;
-            out.converged = true;
-            return out;
+        // residual estimates and the active set
+        int nact = 0;
+        for (int f = 0; f < nf; ++f) {
+            SumrField &sf = F[f];
+            if (!sf.active) continue;
+            sf.resid = rho * std::abs(sf.tau_hat);
+            if (sf.resid <= tol * sf.bn || sf.iters >= prm.max_middle || sf.restarts > 50) sf.active = false;
+            nact += sf.active;
         }
-        zc phi_hat = 1.0 / delta, tau_hat = delta / rho;
-        zc phi = 0.0, s = 0.0, lam = 0.0, c_dag = 1.0, cc = 1.0, gamma = 1.0;
-        double r = 1.0;
-        double sigma = 1.0;
-        zero_fields(c, om, 1, OVL_F64);
-        zero_fields(c, p, 1, OVL_F64);
-        double2 *q = qa, *q_old = qb;
-        zero_fields(c, q_old, 1, OVL_F64);
-        {
-            cplx<double> a{1.0 / delta, 0.0}, b0{0.0, 0.0};
-            axpby_f64(c, &a, rt, &b0, q, 1);
-        }
-        copy_fields(c, q, qt, 1, OVL_F64);
-        bool restart = false;
-        while (true) {
-            resid = rho * std::abs(tau_hat);
-            if (resid <= tol * bn) {
-                out.resid = resid;
-                out.converged = true;
-                return out;
+        if (nact == 0) break;
+        for (int f = 0; f < nf; ++f) eta[f] = F[f].active ? eta_for(F[f]) : 0.0;
+        unitary_f64(c, rhoK, z, q, u, nf, eta.data(), prm, st);
+        if (collect) eig_collect(c, q, u);
+        std::vector<zc> g;
+        dots(c, qt, u, nf, g);
+        SumrCoef k{};
+        for (int f = 0; f < nf; ++f) {
+            SumrField &sf = F[f];
+            k.act[f] = 0;
+            if (!sf.active) continue;
+            zc gamma = g[f];
+            if (!(std::abs(gamma) < 1.0)) {   // |gamma| >= 1: restart (Sec. 2)
+                sf.need_init = true;
+                sf.restarts += 1;
+                if (st) st[f].restarts += 1;
+                continue;
             }
-            if (out.iters >= prm.max_middle) {
-                out.resid = resid;
-                return out;
-            }
-            const double r_pp = r;
-            const double eta_j = eta_for(resid);
-            unitary_f64(c, rhoK, z, q, u, 1, eta_j, prec_for(prm, eta_j), prm.max_mscg, st);
-            if (collect) eig_collect(c, q, u);
-            gamma = dot1(c, qt, u);
-            if (!(std::abs(gamma) < 1.0)) {
-                restart = true;
-                break;
-            }
-            sigma = std::sqrt(1.0 - std::norm(gamma));
-            const zc alpha = gamma * delta;
+            const double r_pp = sf.r;
+            const double sigma = std::sqrt(1.0 - std::norm(gamma));
+            const zc alpha = gamma * sf.delta;
             gamma = -gamma;
-            const zc r_p = alpha * phi + s * zeta / rho;
-            const zc r_hat = alpha * phi_hat + c_dag * zeta / rho;
+            const zc r_p = alpha * sf.phi + sf.s * zeta / rho;
+            const zc r_hat = alpha * sf.phi_hat + sf.c_dag * zeta / rho;
             const double nrm = std::sqrt(std::norm(r_hat) + sigma * sigma);
-            c_dag = r_hat / nrm;
-            cc = std::conj(c_dag);
-            s = -sigma / nrm;
-            const zc rn = s * sigma - cc * r_hat;
-            const zc tau = -cc * tau_hat;
-            tau_hat = s * tau_hat;
-            const zc eta = tau / rn;
+            sf.c_dag = r_hat / nrm;
+            sf.cc = std::conj(sf.c_dag);
+            sf.s = -sigma / nrm;
+            const zc rn = sf.s * sigma - sf.cc * r_hat;
+            const zc tau = -sf.cc * sf.tau_hat;
+            sf.tau_hat = sf.s * sf.tau_hat;
+            const zc et = tau / rn;
             const zc kappa = r_p / r_pp;
-            // vector statements (fused), with lambda from the previous iteration
-            SumrCoef k{alpha.real(), alpha.imag(), kappa.real(), kappa.imag(), lam.real(), lam.imag(),
-                       eta.real(),   eta.imag(),   gamma.real(), gamma.imag(), sigma};
-            k_sumr_step<<<nblk, 256, 0, c.stream>>>(k, x, p, om, q_old, q, qt, u, n, part);
-            OVL_HIP(hipGetLastError());
-            std::swap(q, q_old);   // q_old <- old q, q <- new q
-            delta = sigma * delta;
-            phi = s * std::conj(gamma) / delta - cc * phi_hat;
-            // r is real in exact arithmetic for this recurrence; keep its modulus-phase form
-            r = rn.real();
-            lam = phi / rn;
-            phi_hat = s * phi_hat + c_dag * std::conj(gamma) / delta;
-            out.iters += 1;
-            if (st) st->sumr_iters += 1;
-            // ||q|| monitoring (Sec. 2)
-            sum_partials(c, part, nblk, 1, res);
-            double qn2;
-            OVL_HIP(hipMemcpyAsync(&qn2, res, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            OVL_HIP(hipStreamSynchronize(c.stream));
-            if (!std::isfinite(qn2)) throw Error{OVL_ERR_BREAKDOWN, "SUMR: non-finite basis vector"};
-            if (std::fabs(std::sqrt(qn2) - 1.0) > prm.norm_restart) {
-                restart = true;
-                break;
-            }
+            k.ar[f] = alpha.real();
+            k.ai[f] = alpha.imag();
+            k.kr[f] = kappa.real();
+            k.ki[f] = kappa.imag();
+            k.lr[f] = sf.lam.real();   // lambda of the previous iteration
+            k.li[f] = sf.lam.imag();
+            k.er[f] = et.real();
+            k.ei[f] = et.imag();
+            k.gr[f] = gamma.real();
+            k.gi[f] = gamma.imag();
+            k.sigma[f] = sigma;
+            k.act[f] = 1;
+            sf.delta = sigma * sf.delta;
+            sf.phi = sf.s * std::conj(gamma) / sf.delta - sf.cc * sf.phi_hat;
+            sf.r = rn.real();   // real for this recurrence
+            sf.lam = sf.phi / rn;
+            sf.phi_hat = sf.s * sf.phi_hat + sf.c_dag * std::conj(gamma) / sf.delta;
+            sf.iters += 1;
+            if (st) st[f].sumr_iters += 1;
         }
-        if (restart) {
-            out.restarts += 1;
-            if (st) st->restarts += 1;
-            if (out.restarts > 50) {
-                out.resid = resid;
-                return out;
+        k_sumr_step<<<dim3(nblk, nf), 256, 0, c.stream>>>(k, x, p, om, qold, q, qt, u, n, part);
+        OVL_HIP(hipGetLastError());
+        // ||q|| monitoring (Sec. 2)
+        sum_partials(c, part, nblk, nf, res);
+        std::vector<double> qn2(nf);
+        OVL_HIP(hipMemcpyAsync(qn2.data(), res, sizeof(double) * nf, hipMemcpyDeviceToHost, c.stream));
+        OVL_HIP(hipStreamSynchronize(c.stream));
+        for (int f = 0; f < nf; ++f) {
+            if (!k.act[f]) continue;
+            if (!std::isfinite(qn2[f])) throw Error{OVL_ERR_BREAKDOWN, "SUMR: non-finite basis vector"};
+            if (std::fabs(std::sqrt(qn2[f]) - 1.0) > prm.norm_restart) {
+                F[f].need_init = true;
+                F[f].restarts += 1;
+                if (st) st[f].restarts += 1;
             }
         }
     }
 }
 
-ovl_status solve_one(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *b, double2 *x,
-                     ovl_stats *st)
+ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *b, double2 *x,
+                       int nf, ovl_stats *st)
 {
+    OVL_REQUIRE(nf >= 1 && nf <= MAXF, OVL_ERR_ARG, "too many right-hand sides in one batch");
+    OVL_REQUIRE(!(prm.eig_calc && nf > 1), OVL_ERR_ARG,
+                "eigSUMR collects from one right-hand side at a time (solve calculating right-hand sides singly)");
     const auto t0 = std::chrono::steady_clock::now();
     const double mu = prm.mu;
     const double rhoK = prm.rho;
     const double rho = (1.0 - mu) / (1.0 + mu);
     const size_t FB = field_bytes(c.g, OVL_F64);
+    const int64_t fs = 12 * c.g.V;   // double2 per field
     const int maxo = prm.max_outer;
-    double2 *Cv = (double2 *)c.buf("g_C", FB * maxo);
-    double2 *Uv = (double2 *)c.buf("g_U", FB * maxo);
-    double2 *r = (double2 *)c.buf("g_r", FB);
-    double2 *uu = (double2 *)c.buf("g_u", FB);
-    double2 *cv = (double2 *)c.buf("g_c", FB);
-    double2 *bp = (double2 *)c.buf("g_bp", FB);
+    double2 *r = (double2 *)c.buf("g_r", FB * nf);
+    double2 *uu = (double2 *)c.buf("g_u", FB * nf);
+    double2 *cv = (double2 *)c.buf("g_c", FB * nf);
+    double2 *bp = (double2 *)c.buf("g_bp", FB * nf);
 
-    zero_fields(c, x, 1, OVL_F64);
-    copy_fields(c, b, r, 1, OVL_F64);
+    zero_fields(c, x, nf, OVL_F64);
+    copy_fields(c, b, r, nf, OVL_F64);
     if (prm.eig_calc) eig_configure(c, prm.n_eig, prm.m_eig, mu, prm.delta_split, prm.eig_eps, prm.k_recalc);
-    const double bn = norm_f64(c, b);
-    if (bn == 0.0) {
-        if (st) st->computed_relres = 0.0;
-        return OVL_OK;
-    }
-    double rn = bn;
-    int i = 0;
+    std::vector<double> bn, rn;
+    norms(c, b, nf, bn);
+    rn = bn;
+    std::vector<int> steps(nf, 0), active(nf, 0);
     ovl_status status = OVL_OK;
-    while (rn > 0.5 * prm.tol * bn) {
-        if (i >= maxo) {
-            status = OVL_ERR_NOT_CONVERGED;
-            break;
+    std::vector<double2 *> C, Uv;
+    while (true) {
+        int nact = 0;
+        for (int f = 0; f < nf; ++f) {
+            const bool want = bn[f] > 0.0 && rn[f] > 0.5 * prm.tol * bn[f];
+            active[f] = want && steps[f] < maxo;
+            if (want && steps[f] >= maxo) status = OVL_ERR_NOT_CONVERGED;
+            nact += active[f];
+        }
+        if (nact == 0) break;
+        const int i = *std::max_element(steps.begin(), steps.end());   // same for every active field
+        if ((int)C.size() <= i) {
+            C.push_back((double2 *)c.buf("g_C" + std::to_string(i), FB * nf));
+            Uv.push_back((double2 *)c.buf("g_U" + std::to_string(i), FB * nf));
         }
         // middle solve D u = r to relative accuracy eta_tilde: (1 + rho U) u = 2 r/(1 + mu)
         {
-            cplx<double> a{2.0 / (1.0 + mu), 0.0}, b0{0.0, 0.0};
-            axpby_f64(c, &a, r, &b0, bp, 1);
+            std::vector<zc> a(nf, 2.0 / (1.0 + mu)), b0(nf, 0.0);
+            axpby(c, a, r, b0, bp, nf);
         }
+        zero_fields(c, uu, nf, OVL_F64);
         // deflated start (Sec. 4): u0 from the eigenspace, (1 + rho U) u0 = 2 D u0/(1 + mu)
-        const bool defl = prm.use_deflation && c.eig.k >= c.eig.n && c.eig.n > 0 && c.eig.ndiag > 0;
+        const bool defl = prm.use_deflation && c.eig.n > 0 && c.eig.k >= c.eig.n && c.eig.ndiag > 0;
         double2 *Ax0 = nullptr;
         if (defl) {
-            Ax0 = (double2 *)c.buf("g_Ax0", FB);
-            double2 *Dx0 = (double2 *)c.buf("g_Dx0", FB);
-            eig_project(c, r, uu, Dx0);
-            cplx<double> a{2.0 / (1.0 + mu), 0.0}, b0{0.0, 0.0};
-            axpby_f64(c, &a, Dx0, &b0, Ax0, 1);
-        } else {
-            zero_fields(c, uu, 1, OVL_F64);
+            Ax0 = (double2 *)c.buf("g_Ax0", FB * nf);
+            double2 *Dx0 = (double2 *)c.buf("g_Dx0", FB * nf);
+            zero_fields(c, Dx0, nf, OVL_F64);
+            for (int f = 0; f < nf; ++f)
+                if (active[f]) eig_project(c, r + f * fs, uu + f * fs, Dx0 + f * fs);
+            std::vector<zc> a(nf, 2.0 / (1.0 + mu)), b0(nf, 0.0);
+            axpby(c, a, Dx0, b0, Ax0, nf);
         }
         const bool collect = prm.eig_calc != 0;
-        SumrOut so = sumr(c, z, prm, rhoK, rho, bp, uu, !defl, Ax0, prm.eta_tilde, prm.eta_tilde, collect, st);
+        sumr(c, z, prm, rhoK, rho, bp, uu, nf, active, !defl, Ax0, prm.eta_tilde, prm.eta_tilde, collect, st);
         if (collect) {
             eig_diagonalise(c);   // the closing Alg. 6 of Alg. 5
             if (c.eig.ndiag > 0 && prm.k_recalc > 0 && c.eig.ndiag % prm.k_recalc == 0)
-                eig_recompute(c, rhoK, z, 1e-12, st);
+                eig_recompute(c, rhoK, z, 1e-12, nullptr);
         }
-        (void)so;
         // c = D u, to ||D u - c|| <= eps ||b|| / 4
-        const double un = norm_f64(c, uu);
-        const double eta_c = std::fmin(1e-2, prm.tol * bn / (2.0 * (1.0 - mu) * un));
-        overlap_f64(c, rhoK, mu, z, uu, cv, 1, eta_c, prec_for(prm, eta_c), prm.max_mscg, st);
+        std::vector<double> un;
+        norms(c, uu, nf, un);
+        std::vector<double> eta_c(nf, 0.0);
+        for (int f = 0; f < nf; ++f)
+            if (active[f])
+                eta_c[f] = std::fmin(1e-2, prm.tol * bn[f] / (2.0 * (1.0 - mu) * std::max(un[f], 1e-300)));
+        overlap_impl(c, rhoK, mu, z, uu, cv, nf, eta_c.data(), prec_for(prm, min_active(eta_c.data(), nf)),
+                     prm.max_mscg, st, true);
         // modified Gram-Schmidt against C[0..i)
         for (int j = 0; j < i; ++j) {
-            const zc beta = dot1(c, Cv + (size_t)j * 12 * c.g.V, cv);
-            axpby1(c, -beta, Cv + (size_t)j * 12 * c.g.V, zc(1.0), cv);
-            axpby1(c, -beta, Uv + (size_t)j * 12 * c.g.V, zc(1.0), uu);
+            std::vector<zc> beta;
+            dots(c, C[j], cv, nf, beta);
+            std::vector<zc> mb(nf, 0.0), one(nf, 1.0);
+            for (int f = 0; f < nf; ++f)
+                if (active[f]) mb[f] = -beta[f];
+            axpby(c, mb, C[j], one, cv, nf);
+            axpby(c, mb, Uv[j], one, uu, nf);
         }
-        const double cn = norm_f64(c, cv);
-        if (!(cn > 0.0) || !std::isfinite(cn)) throw Error{OVL_ERR_BREAKDOWN, "GMRESR: zero or non-finite c"};
-        double2 *Ci = Cv + (size_t)i * 12 * c.g.V, *Ui = Uv + (size_t)i * 12 * c.g.V;
-        {
-            cplx<double> a{1.0 / cn, 0.0}, b0{0.0, 0.0};
-            axpby_f64(c, &a, cv, &b0, Ci, 1);
-            axpby_f64(c, &a, uu, &b0, Ui, 1);
-        }
-        const zc alpha = dot1(c, Ci, r);
-        axpby1(c, alpha, Ui, zc(1.0), x);
-        axpby1(c, -alpha, Ci, zc(1.0), r);
-        rn = norm_f64(c, r);
-        ++i;
-        if (st) st->gmresr_steps += 1;
+        std::vector<double> cn;
+        norms(c, cv, nf, cn);
+        std::vector<zc> inv(nf, 0.0), keep(nf, 1.0);
+        for (int f = 0; f < nf; ++f)
+            if (active[f]) {
+                if (!(cn[f] > 0.0) || !std::isfinite(cn[f]))
+                    throw Error{OVL_ERR_BREAKDOWN, "GMRESR: zero or non-finite c"};
+                inv[f] = 1.0 / cn[f];
+                keep[f] = 0.0;
+            }
+        axpby(c, inv, cv, keep, C[i], nf);
+        axpby(c, inv, uu, keep, Uv[i], nf);
+        std::vector<zc> alpha;
+        dots(c, C[i], r, nf, alpha);
+        std::vector<zc> pa(nf, 0.0), ma(nf, 0.0), one(nf, 1.0);
+        for (int f = 0; f < nf; ++f)
+            if (active[f]) {
+                pa[f] = alpha[f];
+                ma[f] = -alpha[f];
+            }
+        axpby(c, pa, Uv[i], one, x, nf);
+        axpby(c, ma, C[i], one, r, nf);
+        std::vector<double> rnew;
+        norms(c, r, nf, rnew);
+        for (int f = 0; f < nf; ++f)
+            if (active[f]) {
+                rn[f] = rnew[f];
+                steps[f] += 1;
+                if (st) st[f].gmresr_steps += 1;
+            }
         if (prm.verbose)
-            std::fprintf(stderr, "[ovl] GMRESR step %d: middle iters %d, ||r||/||b|| = %.3e\n", i, so.iters,
-                         rn / bn);
+            std::fprintf(stderr, "[ovl] GMRESR step %d: ||r||/||b|| of field 0 = %.3e\n", i + 1, rn[0] / bn[0]);
     }
     OVL_HIP(hipStreamSynchronize(c.stream));
-    if (st) {
-        st->computed_relres = rn / bn;
-        st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st)
+        for (int f = 0; f < nf; ++f) {
+            st[f].computed_relres = bn[f] > 0.0 ? rn[f] / bn[f] : 0.0;
+            st[f].seconds += secs;
+        }
     return status;
 }
 
