@@ -184,6 +184,26 @@ ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_
                              const double *in_dev, double *out_dev, int32_t nrhs, double eta,
                              int32_t prec, ovl_stats *stats_host);
 
+/* Derivatives of S = sum_f Re(chi_f^H D[mu] psi_f) over nrhs field pairs, for
+ * D[mu] (Sec. 1, eq. 1) with the rational sign function
+ * eps(K) = K sum_l omega_l (K^2 + sigma_l)^{-1} (Sec. 1, eq. 4; Sec. 3, eq. 7).
+ * Gradients are d/dRe + i d/dIm, every link entry an independent complex
+ * variable (U in the forward hop, U^dagger in the backward one).
+ *   dS_dpsi_dev (may be null): D^dagger chi_f = gamma_5 D gamma_5 chi_f per
+ *     field, canonical [nrhs][V][4][3] complex128.
+ *   dS_dU_dev (may be null): the link gradient summed over the nrhs pairs,
+ *     canonical [V][4][3][3] complex128 (same layout as the gauge field);
+ *     overwritten.  Needs psi_dev.
+ * At least one output must be given.  Each shifted inversion runs to
+ * |zeta_l| ||r|| <= eta ||source||; prec OVL_F64 or OVL_F32 (FP32 storage
+ * and arithmetic for the inversions, FP64 link accumulation).  The exactly
+ * treated low modes are not differentiated: with low modes in the context this
+ * returns OVL_ERR_UNSUPPORTED.  stats_host (may be null): one record. */
+ovl_status ovl_overlap_adjoint(ovl_context *ctx, double rho, double mu, const ovl_zolo *zolo,
+                               const double *psi_dev, const double *chi_dev, int32_t nrhs, double eta,
+                               int32_t prec, double *dS_dpsi_dev, double *dS_dU_dev,
+                               ovl_stats *stats_host);
+
 /* ---- solver (Algs. 1-3, Sec. 3 relaxation, Secs. 4-5 deflation) ---------- */
 
 /* Solve D[mu] x = b for nrhs right-hand sides (one after another) with

@@ -77,7 +77,7 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_lowmodes_get", "ovl_sign_zolotarev_mscg", "ovl_overlap_apply",
            "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
-           "ovl_deflate_project"]
+           "ovl_deflate_project", "ovl_overlap_adjoint"]
 
 _lib = None
 
@@ -108,6 +108,7 @@ def lib():
         "ovl_lowmodes_get": ([P, P], I32),
         "ovl_sign_zolotarev_mscg": ([P, D, P, P, P, I32, D, I32, P], I32),
         "ovl_overlap_apply": ([P, D, D, P, P, P, I32, D, I32, P], I32),
+        "ovl_overlap_adjoint": ([P, D, D, P, P, P, I32, D, I32, P, P, P], I32),
         "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
         "ovl_profile_enable": ([P, I32], I32),
         "ovl_profile_read": ([P, I32, I32, P, P, P], I32),
@@ -268,6 +269,24 @@ class Context:
                                        float(eta), prec, ctypes.byref(st)))
         return out, st
 
+    def overlap_adjoint(self, psi, chi, rho, mu, zolo, eta, prec=F64, want_psi=True, want_links=True):
+        """Derivatives of S = sum_f Re(chi_f^H D[mu] psi_f): (D^dagger chi or None,
+        link gradient [V,4,3,3] or None, Stats)."""
+        nrhs = self._nrhs(chi)
+        if want_links and (psi is None or psi.shape != chi.shape):
+            raise ValueError("psi and chi must have the same shape")
+        dpsi = torch.empty_like(chi) if want_psi else None
+        dU = (torch.empty((self.V, 4, 3, 3), dtype=torch.complex128, device=chi.device)
+              if want_links else None)
+        st = Stats()
+        _check(lib().ovl_overlap_adjoint(
+            self._h, float(rho), float(mu), ctypes.byref(zolo),
+            _dev(psi, (self.V, 4, 3), "psi") if want_links else None,
+            _dev(chi, (self.V, 4, 3), "chi"), nrhs, float(eta), prec,
+            _dev(dpsi, (self.V, 4, 3), "dpsi") if want_psi else None,
+            _dev(dU, (self.V, 4, 3, 3), "dU") if want_links else None, ctypes.byref(st)))
+        return dpsi, dU, st
+
     def solve(self, b, zolo, params, allow=()):
         """GMRESR(relSUMR) solve of D[mu] x = b; returns (x, [Stats per rhs], status)."""
         nrhs = self._nrhs(b)
@@ -327,3 +346,29 @@ class Context:
         _check(lib().ovl_profile_read(self._h, int(kernel), int(prec), ctypes.byref(n),
                                       ctypes.byref(ms), ctypes.byref(by)))
         return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
+
+class OverlapFunction(torch.autograd.Function):
+    """y = D[mu] psi through the library, differentiable in psi and in the
+    links (forward: ovl_overlap_apply; backward: ovl_overlap_adjoint with
+    chi = the incoming gradient).  U must be the canonical gauge field that is
+    loaded in ctx; it only carries the link gradient.  Usage:
+    OverlapFunction.apply(ctx, U, psi, rho, mu, zolo, eta, prec)."""
+
+    @staticmethod
+    def forward(fctx, ctx, U, psi, rho, mu, zolo, eta, prec=F64):
+        y, _ = ctx.overlap(psi.contiguous(), rho, mu, zolo, eta, prec)
+        fctx.save_for_backward(psi)
+        fctx.args = (ctx, rho, mu, zolo, eta, F64 if prec == F64 else F32)
+        return y
+
+    @staticmethod
+    def backward(fctx, gy):
+        (psi,) = fctx.saved_tensors
+        ctx, rho, mu, zolo, eta, prec = fctx.args
+        need_U, need_psi = fctx.needs_input_grad[1], fctx.needs_input_grad[2]
+        if not (need_U or need_psi):
+            return (None,) * 8
+        dpsi, dU, _ = ctx.overlap_adjoint(psi.contiguous(), gy.contiguous(), rho, mu, zolo, eta, prec,
+                                          want_psi=need_psi, want_links=need_U)
+        return None, dU, dpsi, None, None, None, None, None

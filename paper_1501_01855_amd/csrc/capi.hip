@@ -287,6 +287,35 @@ ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_
     });
 }
 
+ovl_status ovl_overlap_adjoint(ovl_context *ctx, double rho, double mu, const ovl_zolo *zolo,
+                               const double *psi_dev, const double *chi_dev, int32_t nrhs, double eta,
+                               int32_t prec, double *dS_dpsi_dev, double *dS_dU_dev, ovl_stats *stats_host)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        check_zolo(zolo);
+        OVL_REQUIRE(prec == OVL_F64 || prec == OVL_F32, OVL_ERR_UNSUPPORTED, "the adjoint runs in FP64 or FP32");
+        OVL_REQUIRE(chi_dev && nrhs >= 1 && nrhs <= MAX_NRHS && (dS_dpsi_dev || dS_dU_dev) &&
+                        (psi_dev || !dS_dU_dev),
+                    OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(eta > 0.0 && std::isfinite(rho) && mu >= 0.0 && mu < 1.0, OVL_ERR_ARG,
+                    "need eta > 0, finite rho, 0 <= mu < 1");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        const size_t FB = field_bytes(ctx->g, OVL_F64) * nrhs;
+        double2 *chi = (double2 *)ctx->buf("api_a64", FB);
+        double2 *psi = dS_dU_dev ? (double2 *)ctx->buf("api_c64", FB) : nullptr;
+        double2 *dpsi = dS_dpsi_dev ? (double2 *)ctx->buf("api_b64", FB) : nullptr;
+        pack_spinor(*ctx, chi_dev, chi, nrhs, OVL_F64);
+        if (psi) pack_spinor(*ctx, psi_dev, psi, nrhs, OVL_F64);
+        if (stats_host) std::memset(stats_host, 0, sizeof(ovl_stats));
+        overlap_adjoint(*ctx, rho, mu, *zolo, psi, chi, dpsi, (double2 *)dS_dU_dev, nrhs, eta, prec, 100000,
+                        stats_host);
+        if (dpsi) unpack_spinor(*ctx, dpsi, dS_dpsi_dev, nrhs, OVL_F64);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->prof_collect();
+    });
+}
+
 ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo, const ovl_solver_params *params,
                                  const double *b_dev, double *x_dev, int32_t nrhs, ovl_stats *stats_host)
 {

@@ -112,8 +112,10 @@ __global__ __launch_bounds__(256) void k_mscg_rupdate(const ST *__restrict__ rin
 
 // y += sum_l omega_l alpha_l p_l ; p_l = zeta_l' r + beta_l p_l over the active
 // shifts (on the first iteration every p_l is the source and y starts at zero).
+// With ALL, y holds one solution per shift, shift-major like p, and
+// x_l += omega_l alpha_l p_l (the caller passes omega_l = 1).
 // Every block derives the iteration's scalars; block 0 stores the next state.
-template <typename ST>
+template <typename ST, bool ALL>
 __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, const ST *__restrict__ r,
                                                     ST *__restrict__ y, ST *__restrict__ p, MscgScal *S,
                                                     const MscgConst *kc, int *stop, MscgFinal *fin, int it,
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
 #pragma unroll
             for (int c = 0; c < 12; ++c) yv[c] = {R(0), R(0)};
             ld_sp(src + fo, V, s, pv);
-        } else {
+        } else if constexpr (!ALL) {
             ld_sp(y + fo, V, s, yv);
         }
         for (int l = 0; l < nz; ++l) {
@@ -195,15 +197,28 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
             ST *pl = p + l * pstride + fo;
             if (it != 0) ld_sp(pl, V, s, pv);
             const R cy = (R)s_cy[l], zn = (R)s_zn[l], bl = (R)s_bl[l];
+            if constexpr (ALL) {
+                ST *xl = y + l * pstride + fo;
+                cplx<R> xv[12];
+                if (it != 0) {
+                    ld_sp(xl, V, s, xv);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) xv[c] = {R(0), R(0)};
+                }
+#pragma unroll
+                for (int c = 0; c < 12; ++c) xv[c] = xv[c] + cy * pv[c];
+                st_sp(xl, V, s, xv);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) yv[c] = yv[c] + cy * pv[c];
+            }
             cplx<R> nv[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                yv[c] = yv[c] + cy * pv[c];
-                nv[c] = zn * rv[c] + bl * pv[c];
-            }
+            for (int c = 0; c < 12; ++c) nv[c] = zn * rv[c] + bl * pv[c];
             st_sp(pl, V, s, nv);
         }
-        st_sp(y + fo, V, s, yv);
+        if constexpr (!ALL) st_sp(y + fo, V, s, yv);
     }
 }
 
@@ -288,10 +303,14 @@ __global__ __launch_bounds__(256) void k_low_project(const double2 *__restrict__
 }
 
 // --------------------------------------------------------------- host driver
+// out = sign(K) in, or (xs != nullptr) every shifted solution
+// xs[l][f] = (K^2 + sigma_l)^{-1} in_f, each to |zeta_l| ||r|| <= eta_f ||in_f||,
+// with no low-mode split and no final K.
 template <typename ST>
 static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
-                   const double *eta, int prec, int maxiter, ovl_stats *st)
+                   const double *eta, int prec, int maxiter, ovl_stats *st, void *xs = nullptr)
 {
+    const bool all = xs != nullptr;
     const Geom &g = c.g;
     const int64_t V = g.V;
     const size_t FB = field_bytes(g, prec);
@@ -316,7 +335,7 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     ST *r = (ST *)c.buf("ms_r", FB * nf);
     ST *t = (ST *)c.buf("ms_t", FB * nf);
     ST *w = (ST *)c.buf("ms_w", FB * nf);
-    ST *y = (ST *)c.buf("ms_y", FB * nf);
+    ST *y = all ? (ST *)xs : (ST *)c.buf("ms_y", FB * nf);
     ST *p = (ST *)c.buf("ms_p", FB * nf * nz);
     const int nl = c.n_low > 0 ? c.n_low : 1;
     double *part = (double *)c.buf("ms_part", sizeof(double) * (size_t)std::max(nblk_max, nblk * 2 * nl) * nf);
@@ -329,7 +348,7 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     MscgConst *kdev = (MscgConst *)c.buf("ms_const", sizeof(MscgConst));
 
     // 1. low-mode split: src = (1 - P) in, ex = sum sign(lambda) P in
-    const bool low = c.n_low > 0;
+    const bool low = c.n_low > 0 && !all;
     if (low) {
         std::vector<double> sg(c.n_low);
         for (int j = 0; j < c.n_low; ++j) sg[j] = c.low_evals[j] >= 0.0 ? 1.0 : -1.0;
@@ -353,12 +372,12 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     k.s0 = z.sigma[base];
     for (int l = 0; l < nz; ++l) {
         k.sigma[l] = z.sigma[l];
-        k.omega[l] = z.omega[l];
-        const double tl = 2.0 * std::sqrt(z.sigma[l]) / (nz * z.omega[l]);
+        k.omega[l] = all ? 1.0 : z.omega[l];
+        const double tl = all ? 1.0 : 2.0 * std::sqrt(z.sigma[l]) / (nz * z.omega[l]);
         k.tol2[l] = tl * tl;
     }
     OVL_HIP(hipMemcpyAsync(kdev, &k, sizeof(MscgConst), hipMemcpyHostToDevice, c.stream));
-    zero_fields(c, y, nf, prec);   // y stays zero for a zero source
+    zero_fields(c, y, all ? nf * nz : nf, prec);   // stays zero for a zero source
     k_norm2<ST><<<grid, 256, 0, c.stream>>>(src, V, part);
     double *eta2d = (double *)c.buf("ms_eta2", sizeof(double) * nf);
     OVL_HIP(hipMemcpyAsync(eta2d, eta2.data(), sizeof(double) * nf, hipMemcpyHostToDevice, c.stream));
@@ -383,8 +402,12 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
                                                            rr_part);
             PendingEvent pe;
             if (c.prof) c.prof_begin(pe, KERN_SHIFT, prec, 0.0);
-            k_mscg_shift<ST><<<ugrid, 256, 0, c.stream>>>(src, r, y, p, S, kdev, stop, fin, it, V, part, ntile,
-                                                         rr_part, nupd);
+            if (all)
+                k_mscg_shift<ST, true><<<ugrid, 256, 0, c.stream>>>(src, r, y, p, S, kdev, stop, fin, it, V, part,
+                                                                   ntile, rr_part, nupd);
+            else
+                k_mscg_shift<ST, false><<<ugrid, 256, 0, c.stream>>>(src, r, y, p, S, kdev, stop, fin, it, V, part,
+                                                                    ntile, rr_part, nupd);
             if (c.prof) c.prof_end(pe);
             OVL_HIP(hipGetLastError());
         }
@@ -402,7 +425,8 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     }
 
     // 4. s = K y + ex
-    if (low) {
+    if (all) {
+    } else if (low) {
         stencil(c, EPI_KPLUS, prec, y, out, nf, rho, 0.0, ex, nullptr);
     } else {
         stencil(c, EPI_K, prec, y, out, nf, rho, 0.0, nullptr, nullptr);
@@ -426,15 +450,18 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     }
     if (st) {
         st->mscg_iters += iters;
-        st->dslash_calls[prec] += 2 * iters + nact;
-        st->sign_calls[prec] += nact;
+        st->dslash_calls[prec] += 2 * iters + (all ? 0 : nact);
+        if (!all) st->sign_calls[prec] += nact;
     }
     c.last_mscg_iters = iters;
     c.last_field_iters.assign(nf, 0);
     for (int f = 0; f < nf; ++f)
         if (hstop_final[f] != 0) c.last_field_iters[f] = hs[f].iters;
     // algorithmic bytes of the shift kernel: r, y in, y out, 2 per active shift
-    if (c.prof) c.slots[KERN_SHIFT][prec].bytes += (double)FB * (3.0 * iters + 2.0 * act_total);
+    // (with every solution kept: r, and p_l, x_l in and out per active shift)
+    if (c.prof)
+        c.slots[KERN_SHIFT][prec].bytes +=
+            all ? (double)FB * (1.0 * iters + 4.0 * act_total) : (double)FB * (3.0 * iters + 2.0 * act_total);
     OVL_REQUIRE(!brk, OVL_ERR_BREAKDOWN, "multi-shift CG breakdown (non-positive curvature or NaN)");
     OVL_REQUIRE(!capped, OVL_ERR_NOT_CONVERGED, "multi-shift CG hit its iteration limit");
 }
@@ -448,6 +475,18 @@ void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *
         sign_t<float4>(c, rho, z, in, out, nf, eta, prec, maxiter, st);
     else
         sign_t<h8>(c, rho, z, in, out, nf, eta, prec, maxiter, st);
+}
+
+void shifts_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *xs, int nf, const double *eta,
+                 int prec, int maxiter, ovl_stats *st)
+{
+    OVL_REQUIRE(xs != nullptr, OVL_ERR_ARG, "no output for the shifted solutions");
+    if (prec == OVL_F64)
+        sign_t<double2>(c, rho, z, in, nullptr, nf, eta, prec, maxiter, st, xs);
+    else if (prec == OVL_F32)
+        sign_t<float4>(c, rho, z, in, nullptr, nf, eta, prec, maxiter, st, xs);
+    else
+        throw Error{OVL_ERR_UNSUPPORTED, "shifted solutions are kept in FP64 or FP32 only"};
 }
 
 void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,

@@ -11,6 +11,17 @@ void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *
 void sign_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
                const double *eta, int prec, int maxiter, ovl_stats *st);
 
+// Every shifted solution xs[l][f] = (K^2 + sigma_l)^{-1} in_f (shift-major,
+// nf fields per shift), each to |zeta_l| ||r|| <= eta_f ||in_f||; FP64 or FP32.
+void shifts_mscg(Context &c, double rho, const ovl_zolo &z, const void *in, void *xs, int nf, const double *eta,
+                 int prec, int maxiter, ovl_stats *st);
+
+// Derivatives of S = sum_f Re(chi_f^H D[mu] psi_f): dpsi = D^dagger chi (packed
+// FP64, nullable) and the link gradient summed over fields into dU (canonical
+// [V][4][3][3] complex, device, nullable) (adjoint.hip).
+void overlap_adjoint(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *psi, const double2 *chi,
+                     double2 *dpsi, double2 *dU, int nf, double eta, int prec, int maxiter, ovl_stats *st);
+
 // out = D[mu] in, packed FP64 in/out; the sign function in precision prec
 // (conversions at its boundary) (solver.hip).
 void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in,
