@@ -6,14 +6,25 @@ mu = 0.02, order-20 Zolotarev sign function with the 10 lowest kernel modes
 treated exactly, one complex Gaussian source (seed 102), target
 ||b - D x|| <= 1e-10 ||b||.  Set-up (gauge field, low modes, coefficients)
 is outside the timed region.  The headline value is the mixed-precision
-solver (single-precision sign function whenever the accuracy asked for is
-looser than 1e-6); the same solve with an all-FP64 sign function is timed
-beside it.  The Wilson stencil is also timed alone on 32^3 x 64 in FP32
-(working set beyond the 256 MB Infinity Cache) for its HBM bandwidth.
+solver (FP16-storage sign function while the accuracy asked for is >= 3e-3,
+FP32 while >= 1e-6, FP64 below); the same solve with an all-FP64 sign function
+is timed beside it.
+
+Beside the headline (not part of it):
+* the same solver on twelve spin-colour point sources in one batched call;
+* the adjoint (dS/dpsi and dS/dU of S = Re(chi^H D psi)) on 8^3 x 16 in FP64
+  and on 32^3 x 64 in FP32;
+* the Wilson stencil alone on 32^3 x 64 (working set beyond the 256 MB
+  Infinity Cache) for its HBM bandwidth;
+* the CPU oracle on a bounded sample of the headline workload.
+
+Kernel times come from HIP events attached to each launch's dispatch packet
+(see ovl_profile_enable), collected over the timed region.
 
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +37,11 @@ METRIC = "overlap solves/s at 1e-10 resid (mixed vs FP64) + Dslash HBM GB/s % pe
 HBM_PEAK_GBS = 8000.0
 DIMS = (16, 16, 16, 32)
 RHO, MU, NZ, NLOW, TOL = 1.4, 0.02, 20, 10, 1e-10
+PREC_NAMES = ("f64", "f32", "f16")
+KERN_NAMES = ("stencil", "shift_update")
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_overlap_solve_16c32.txt")
+# sources whose kernels the hardware-counter traffic figures describe
+KERNEL_SOURCES = ["dslash.hip", "mscg.hip", "fields.h", "kernels.h", "mscg_state.h"]
 
 
 def parse():
@@ -34,34 +50,68 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline solve (no batch, adjoint or stand-alone stencil legs)")
     ap.add_argument("--half-threshold", type=float, default=3e-3,
                     help="sign accuracies at or above this use FP16 storage (> 1 disables)")
-    ap.add_argument("--no-dslash", action="store_true", help="skip the stand-alone stencil timing")
     ap.add_argument("--profile-run", action="store_true",
-                    help="short run for hardware counters: one 1 GiB device copy (calibration) "
-                         "and one single-precision sign-function call on the 16^3x32 workload")
+                    help="short run for hardware counters: a 1 GiB elementwise copy (calibration), "
+                         "one sign-function call per precision on the 16^3x32 workload and the "
+                         "stand-alone 32^3x64 stencil")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON of stencil launch choices to install instead of autotuning (the 'tuning' "
+                         "object an earlier run printed), so that profiler runs see the same kernels")
     return ap.parse_args()
 
 
-def profile_run(torch, ovl):
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_1501_01855_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def setup_c2(ovl, tuning=None):
     ctx = ovl.Context(DIMS)
+    if tuning:   # launch choices of an earlier run, installed before any launch
+        ctx.set_tuning(tuning["16x16x16x32"])
     ctx.gauge_generate(2, 0.25)
     ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)
     zolo = ovl.zolotarev_coeffs(NZ, max(abs(e) for e in ev), lmax)
     b = ctx.source(ovl.SRC_GAUSS, seed=102)
+    return ctx, zolo, b
+
+
+def profile_run(torch, ovl, tuning):
+    """Hardware-counter run (rocprofv3 --pmc): every kernel here is a kernel
+    the benchmark times, launched in the same configuration (tuning: the
+    benchmark's launch choices, installed before any launch)."""
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     src.fill_(1.0)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    dst.copy_(src)
+    torch.mul(src, 1.0, out=dst)   # reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
-    ctx.profile(True)
-    _, st = ctx.sign(b, RHO, zolo, 1e-4, prec=ovl.F32)
+    del src, dst
+    ctx, zolo, b = setup_c2(ovl, tuning)
+    out = {"calibration_bytes_each_way": 1 << 30}
+    for prec in (ovl.HALF, ovl.F32, ovl.F64):
+        _, st = ctx.sign(b, RHO, zolo, 1e-2, prec=prec)
+        out[f"mscg_iters_{PREC_NAMES[prec]}"] = st.mscg_iters
     torch.cuda.synchronize()
-    out = {"copy_bytes": 2 * src.numel() * 8, "mscg_iters": st.mscg_iters,
-           "stencil": ctx.profile_read(ovl.KERN_STENCIL, ovl.F32),
-           "shift_update": ctx.profile_read(ovl.KERN_SHIFT, ovl.F32)}
-    print(json.dumps(out))
+    ctx.close()
+    ctx = ovl.Context((32, 32, 32, 64))
+    ctx.gauge_generate(5, 0.25)
+    if tuning:
+        ctx.set_tuning(tuning["32x32x32x64"])
+    psi = ctx.source(ovl.SRC_GAUSS, seed=7)
+    for prec in (ovl.F32, ovl.HALF):
+        for _ in range(10):
+            ctx.wilson_dslash(psi, prec)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def solve_params(ovl, mixed, half_threshold=2.0):
@@ -69,6 +119,10 @@ def solve_params(ovl, mixed, half_threshold=2.0):
                                f32_threshold=(1e-6 if mixed else 10.0),
                                half_threshold=(half_threshold if mixed else 10.0), max_outer=16,
                                max_middle=4000, max_mscg=20000)
+
+
+def read_prof(ctx, ovl):
+    return {(k, p): ctx.profile_read(k, p) for k in (ovl.KERN_STENCIL, ovl.KERN_SHIFT) for p in range(3)}
 
 
 def time_solves(torch, ctx, ovl, b, zolo, params, steps, warmup):
@@ -84,46 +138,113 @@ def time_solves(torch, ctx, ovl, b, zolo, params, steps, warmup):
         stats.append(st[0].as_dict())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = {k: [ctx.profile_read(k, p) for p in range(3)] for k in (ovl.KERN_STENCIL, ovl.KERN_SHIFT)}
+    prof = read_prof(ctx, ovl)
     ctx.profile(False)
     return dt, stats, prof, x
 
 
 def kernel_summary(prof):
     out = {}
-    for name, k in (("stencil", 0), ("shift_update", 1)):
-        ms = sum(p["ms"] for p in prof[k])
-        n = sum(p["launches"] for p in prof[k])
-        by = sum(p["bytes"] for p in prof[k])
-        out[name] = {"launches": n, "ms": ms, "bytes": by,
-                     "avg_us": 1e3 * ms / n if n else None,
-                     "GBps": by / (ms * 1e6) if ms else None,
-                     "by_prec": [{"launches": p["launches"], "ms": p["ms"],
-                                  "GBps": p["bytes"] / (p["ms"] * 1e6) if p["ms"] else None}
-                                 for p in prof[k]]}
+    for (k, p), s in prof.items():
+        if not s["launches"]:
+            continue
+        out[f"{KERN_NAMES[k]}_{PREC_NAMES[p]}"] = {
+            "launches": s["launches"], "ms": s["ms"], "avg_us": 1e3 * s["ms"] / s["launches"],
+            "bytes_per_launch": s["bytes"] / s["launches"],
+            "GBps": s["bytes"] / (s["ms"] * 1e6) if s["ms"] else None}
     return out
 
 
-def dslash_alone(torch, ovl, reps=50):
-    """Stencil alone, 32^3 x 64 FP32, the multi-shift CG's second K (K t + sigma p
-    with its fused dot) and the plain hopping term; HIP events around each launch."""
+def read_traffic(name):
+    """HBM bytes per launch of kernel slot `name` from the committed
+    hardware-counter summary, if it was taken on the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None, "no counter summary"
+    want = kernel_source_hash()
+    src = [ln.split()[-1] for ln in lines if ln.startswith("kernel_sources_sha256")]
+    if not src or src[0] != want:
+        return None, "kernel sources changed since the counters were taken"
+    for ln in lines:
+        f = ln.split()
+        if len(f) >= 3 and f[0] == "traffic" and f[1] == name:
+            return float(f[2]), "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, calibrated"
+    return None, "slot not in the counter summary"
+
+
+def batch12(torch, ovl, ctx, zolo):
+    """Twelve spin-colour point sources at site 0 in one batched solve."""
+    B = torch.stack([ctx.source(ovl.SRC_POINT, site=0, spin=s, colour=c) for s in range(4) for c in range(3)])
+    p = solve_params(ovl, True, 3e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st, code = ctx.solve(B, zolo, p)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    Dx, _ = ctx.overlap(x, RHO, MU, zolo, 1e-13)
+    res = [float(torch.linalg.vector_norm(B[f] - Dx[f]) / torch.linalg.vector_norm(B[f])) for f in range(12)]
+    return {"sources": "12 spin-colour point sources at site 0, one call", "status": code,
+            "seconds": dt, "solves_per_s": 12 / dt, "max_true_relres": max(res),
+            "mscg_iters_per_field": [s.mscg_iters for s in st],
+            "sumr_iters_per_field": [s.sumr_iters for s in st]}
+
+
+def adjoint_leg(torch, ovl):
+    """dS/dpsi and dS/dU for S = Re(chi^H D psi), N_Z = 20, no exactly treated
+    modes: 8^3 x 16 in FP64 (eta 1e-10) and 32^3 x 64 in FP32 (eta 1e-6)."""
+    out = {}
+    ctx = ovl.Context((8, 8, 8, 16))
+    ctx.gauge_generate(5, 0.25)
+    ev, lmax = ctx.lowmodes_compute(RHO, 1, tol=1e-10)
+    ctx.lowmodes_set([], None)
+    a = abs(ev[0])
+    zolo = ovl.zolotarev_coeffs(NZ, a, lmax)
+    for dims, prec, eta, reps in (((8, 8, 8, 16), ovl.F64, 1e-10, 3), ((32, 32, 32, 64), ovl.F32, 1e-6, 1)):
+        if dims != (8, 8, 8, 16):
+            ctx.close()
+            ctx = ovl.Context(dims)
+            ctx.gauge_generate(5, 0.25)
+        psi = ctx.source(ovl.SRC_GAUSS, seed=105)
+        chi = ctx.source(ovl.SRC_GAUSS, seed=106)
+        ctx.overlap_adjoint(psi, chi, RHO, 0.05, zolo, eta, prec)   # warm-up (autotuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, _, st = ctx.overlap_adjoint(psi, chi, RHO, 0.05, zolo, eta, prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["x".join(map(str, dims))] = {"prec": PREC_NAMES[prec], "eta": eta, "seconds": dt,
+                                        "adjoints_per_s": 1.0 / dt, "mscg_iters": st.mscg_iters}
+    out["interval"] = [a, lmax]
+    ctx.close()
+    return out
+
+
+def dslash_alone(torch, ovl, tuning=None, reps=50):
+    """The hopping stencil alone on 32^3 x 64 (FP32 and FP16 storage)."""
     dims = (32, 32, 32, 64)
     ctx = ovl.Context(dims)
+    if tuning and "32x32x32x64" in tuning:
+        ctx.set_tuning(tuning["32x32x32x64"])
     ctx.gauge_generate(5, 0.25)
     psi = ctx.source(ovl.SRC_GAUSS, seed=7)
-    for prec in (ovl.F32,):
+    res = {"lattice": "32^3x64"}
+    for prec in (ovl.F32, ovl.HALF):
         ctx.wilson_dslash(psi, prec)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    for _ in range(reps):
-        ctx.wilson_dslash(psi, ovl.F32)
-    torch.cuda.synchronize()
-    p = ctx.profile_read(ovl.KERN_STENCIL, ovl.F32)
-    ctx.profile(False)
-    gbs = p["bytes"] / (p["ms"] * 1e6)
-    res = {"lattice": "32^3x64", "prec": "f32", "launches": p["launches"],
-           "avg_us": 1e3 * p["ms"] / p["launches"], "bytes_per_launch": p["bytes"] / p["launches"],
-           "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(reps):
+            ctx.wilson_dslash(psi, prec)
+        torch.cuda.synchronize()
+        p = ctx.profile_read(ovl.KERN_STENCIL, prec)
+        ctx.profile(False)
+        gbs = p["bytes"] / (p["ms"] * 1e6)
+        res[PREC_NAMES[prec]] = {"launches": p["launches"], "avg_us": 1e3 * p["ms"] / p["launches"],
+                                 "bytes_per_launch": p["bytes"] / p["launches"], "GBps": gbs,
+                                 "frac_of_peak": gbs / HBM_PEAK_GBS}
+    res["tuning"] = ctx.tuning()
     ctx.close()
     return res
 
@@ -151,7 +272,7 @@ def cpu_baseline(mscg_iters_per_solve):
             "kind": "oracle",
             "sample": f"{iters} multi-shift CG iterations (20 shifts active) of the oracle on the "
                       f"16^3x32 field in {dt:.1f} s, scaled by the {mscg_iters_per_solve} multi-shift "
-                      f"iterations the GPU solve takes (an upper bound on the oracle's rate: fewer "
+                      f"iterations of the GPU's FP64 solve (an upper bound on the oracle's rate: fewer "
                       f"shifts stay active in a real solve)"}
 
 
@@ -163,23 +284,19 @@ def main():
     import torch
     import paper_1501_01855_amd as ovl
 
+    tuning = json.loads(args.tuning) if args.tuning else None
     if args.profile_run:
-        profile_run(torch, ovl)
+        profile_run(torch, ovl, tuning)
         return
-    ctx = ovl.Context(DIMS)
-    ctx.gauge_generate(2, 0.25)
-    ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)
-    a = max(abs(e) for e in ev)
-    zolo = ovl.zolotarev_coeffs(NZ, a, lmax)
-    b = ctx.source(ovl.SRC_GAUSS, seed=102)
-
+    ctx, zolo, b = setup_c2(ovl, tuning)
     dt_mix, st_mix, prof_mix, x_mix = time_solves(torch, ctx, ovl, b, zolo,
                                                   solve_params(ovl, True, args.half_threshold),
                                                   args.steps, args.warmup)
-    dt_64, st_64, prof_64, x_64 = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, False),
-                                              max(1, args.steps), 0)
-    # true residuals with the FP64 operator at full accuracy (not timed)
-    def true_res(x):
+    print(f"[bench] mixed: {args.steps} solves in {dt_mix:.2f} s", file=sys.stderr, flush=True)
+    dt_64, st_64, prof_64, x_64 = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, False), 1, 0)
+    print(f"[bench] fp64: 1 solve in {dt_64:.2f} s", file=sys.stderr, flush=True)
+
+    def true_res(x):   # FP64 operator at full accuracy (not timed)
         Dx, _ = ctx.overlap(x, RHO, MU, zolo, 1e-13)
         return float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b))
     res_mix, res_64 = true_res(x_mix), true_res(x_64)
@@ -187,9 +304,12 @@ def main():
     ks = kernel_summary(prof_mix)
     dom = max(ks, key=lambda k: ks[k]["ms"])
     d = ks[dom]
-    achieved = d["GBps"]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None}
+    traffic, traffic_note = read_traffic(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": d["bytes_per_launch"], "avg_us": d["avg_us"],
+                "traffic_note": traffic_note,
+                "working_set": "16^3x32: fields and links fit in the 256 MB Infinity Cache"}
     out = {
         "metric": METRIC,
         "value": args.steps / dt_mix,
@@ -201,25 +321,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f16-storage/f32/f64",
         "data": "synthetic",
         "config": {"workload": "overlap solve 16^3x32, rho=1.4, mu=0.02, N_Z=20, 10 exact kernel modes, "
                                "Gaussian source, GMRESR(relSUMR) to 1e-10",
                    "global_batch": 1, "lattice": "16x16x16x32", "parallelism": "single GPU"},
-        "fp64_solves_per_s": max(1, args.steps) / dt_64,
-        "mixed_over_fp64": (args.steps / dt_mix) / (max(1, args.steps) / dt_64),
+        "fp64_solves_per_s": 1.0 / dt_64,
+        "mixed_over_fp64": (args.steps / dt_mix) * dt_64,
         "true_relres": {"mixed": res_mix, "fp64": res_64},
         "solve_stats": {"mixed": st_mix[-1], "fp64": st_64[-1]},
         "kernels_mixed": ks,
         "kernels_fp64": kernel_summary(prof_64),
         "roofline": roofline,
     }
+    out["tuning"] = {"16x16x16x32": ctx.tuning()}
+    if not args.no_extras:
+        out["batch12"] = batch12(torch, ovl, ctx, zolo)
+        print("[bench] batch of 12 done", file=sys.stderr, flush=True)
     ctx.close()
-    if not args.no_dslash:
-        out["dslash_hbm"] = dslash_alone(torch, ovl)
+    if not args.no_extras:
+        out["adjoint"] = adjoint_leg(torch, ovl)
+        print("[bench] adjoint done", file=sys.stderr, flush=True)
+        out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
+        out["tuning"]["32x32x32x64"] = out["dslash_hbm"].pop("tuning")
+        print("[bench] stand-alone stencil done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(st_64[-1]["mscg_iters"])
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -238,12 +238,26 @@ ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *
 ovl_status ovl_deflate_project(ovl_context *ctx, const double *b_dev, double *x0_dev, double *Dx0_dev,
                                int32_t nrhs);
 
-/* Per-kernel timing of the context (HIP events around each launch on the
- * context's stream), for roofline reporting.  kernel: 0 = hopping stencil
- * (all K / Dslash launches), 1 = multi-shift update.  Enabling resets. */
+/* Per-kernel timing of the context for roofline reporting: while enabled,
+ * each launch of the two hot kernels carries a pair of HIP events attached to
+ * its dispatch packet (hipExtLaunchKernelGGL), which time the kernel's own
+ * execution on the context's stream.  kernel: 0 = hopping stencil (all K /
+ * Dslash launches), 1 = multi-shift update; prec selects the storage
+ * precision.  bytes: the algorithmic HBM bytes of the timed launches.
+ * Enabling (or disabling) resets the counts. */
 ovl_status ovl_profile_enable(ovl_context *ctx, int32_t on);
 ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int64_t *launches,
                             double *milliseconds, double *bytes);
+
+/* Stencil launch shapes.  The first launch of each (precision, epilogue,
+ * field count) times the launch variants on the context's lattice and keeps
+ * the fastest (variant 0/1: one lane per site, plain or XCD-contiguous tile
+ * order; 2/3: two lanes per site, likewise; FP16 storage uses 0/1 only).
+ * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the
+ * number held; ovl_tuning_set installs pairs (variants out of range are an
+ * argument error), so a run can reuse another run's choices. */
+ovl_status ovl_tuning_get(ovl_context *ctx, int32_t *keys, int32_t *variants, int32_t cap, int32_t *n);
+ovl_status ovl_tuning_set(ovl_context *ctx, const int32_t *keys, const int32_t *variants, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -77,7 +77,7 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_lowmodes_get", "ovl_sign_zolotarev_mscg", "ovl_overlap_apply",
            "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
-           "ovl_deflate_project", "ovl_overlap_adjoint"]
+           "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set"]
 
 _lib = None
 
@@ -109,6 +109,8 @@ def lib():
         "ovl_sign_zolotarev_mscg": ([P, D, P, P, P, I32, D, I32, P], I32),
         "ovl_overlap_apply": ([P, D, D, P, P, P, I32, D, I32, P], I32),
         "ovl_overlap_adjoint": ([P, D, D, P, P, P, I32, D, I32, P, P, P], I32),
+        "ovl_tuning_get": ([P, P, P, I32, P], I32),
+        "ovl_tuning_set": ([P, P, P, I32], I32),
         "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
         "ovl_profile_enable": ([P, I32], I32),
         "ovl_profile_read": ([P, I32, I32, P, P, P], I32),
@@ -336,6 +338,21 @@ class Context:
         return x0, dx0
 
     # -- profiling
+    def tuning(self):
+        """The stencil launch variants chosen so far, {key: variant}."""
+        n = ctypes.c_int32()
+        _check(lib().ovl_tuning_get(self._h, None, None, 0, ctypes.byref(n)))
+        k = (ctypes.c_int32 * max(n.value, 1))()
+        v = (ctypes.c_int32 * max(n.value, 1))()
+        _check(lib().ovl_tuning_get(self._h, k, v, n.value, ctypes.byref(n)))
+        return {int(k[i]): int(v[i]) for i in range(n.value)}
+
+    def set_tuning(self, table):
+        items = sorted((int(a), int(b)) for a, b in table.items())
+        k = (ctypes.c_int32 * max(len(items), 1))(*[a for a, _ in items])
+        v = (ctypes.c_int32 * max(len(items), 1))(*[b for _, b in items])
+        _check(lib().ovl_tuning_set(self._h, k, v, len(items)))
+
     def profile(self, on=True):
         _check(lib().ovl_profile_enable(self._h, 1 if on else 0))
 

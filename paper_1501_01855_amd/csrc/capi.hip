@@ -469,4 +469,36 @@ ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int6
     });
 }
 
+ovl_status ovl_tuning_get(ovl_context *ctx, int32_t *keys, int32_t *variants, int32_t cap, int32_t *n)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(n != nullptr && cap >= 0 && (cap == 0 || (keys && variants)), OVL_ERR_ARG, "bad arguments");
+        int i = 0;
+        for (const auto &kv : ctx->tuned) {
+            if (i < cap) {
+                keys[i] = kv.first;
+                variants[i] = kv.second;
+            }
+            ++i;
+        }
+        *n = i;
+    });
+}
+
+ovl_status ovl_tuning_set(ovl_context *ctx, const int32_t *keys, const int32_t *variants, int32_t n)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(n >= 0 && (n == 0 || (keys && variants)), OVL_ERR_ARG, "bad arguments");
+        for (int i = 0; i < n; ++i) {
+            const int prec = keys[i] / 512;
+            OVL_REQUIRE(keys[i] >= 0 && prec <= OVL_HALF && variants[i] >= 0 &&
+                            variants[i] < (prec == OVL_HALF ? 2 : 4),
+                        OVL_ERR_ARG, "tuning variant out of range");
+        }
+        for (int i = 0; i < n; ++i) ctx->tuned[keys[i]] = variants[i];
+    });
+}
+
 }  // extern "C"

@@ -5,10 +5,15 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace ovl {
 
+// A profiled launch: a and b are attached to the kernel's dispatch packet
+// (hipExtLaunchKernelGGL), so b - a is the kernel's own execution time, not
+// the distance between two markers in the stream.
 struct PendingEvent {
     int kern, prec;
     double bytes;
@@ -57,6 +62,7 @@ struct Context {
     // profiling
     bool prof = false;
     std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> event_pool;   // reused by the profiled launches
     std::vector<hipEvent_t> free_events;
     ProfileSlot slots[KERN_COUNT][3];
     int64_t last_mscg_iters = 0;
@@ -74,6 +80,8 @@ struct Context {
     void *counters();
     void *host_stage(size_t bytes);
     hipEvent_t event();
+    // prof_begin creates the events; launch the kernel with them through
+    // launch_k(); prof_end queues them for prof_collect().
     void prof_begin(PendingEvent &pe, int kern, int prec, double bytes);
     void prof_end(PendingEvent &pe);
     void prof_collect();
@@ -99,5 +107,17 @@ void pack_gauge(Context &c, const double *canon);
 // stencil: out = H in / K in; nf fields in packed layout of precision prec
 void launch_hop(Context &c, const void *in, void *out, int nf, int prec);
 void launch_K(Context &c, double rho, const void *in, void *out, int nf, int prec);
+
+// Launch a kernel on stream; with pe (profiling), its events time the
+// dispatch itself.
+template <typename... KArgs, typename... Args>
+inline void launch_k(hipStream_t stream, const PendingEvent *pe, void (*k)(KArgs...), dim3 grid, dim3 block,
+                     uint32_t shmem, Args... args)
+{
+    if (pe)
+        hipExtLaunchKernelGGL(k, grid, block, shmem, stream, pe->a, pe->b, 0, static_cast<KArgs>(args)...);
+    else
+        hipLaunchKernelGGL(k, grid, block, shmem, stream, static_cast<KArgs>(args)...);
+}
 
 }  // namespace ovl

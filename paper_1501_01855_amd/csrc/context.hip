@@ -71,16 +71,23 @@ void Context::prof_begin(PendingEvent &pe, int kern, int prec, double bytes)
     pe.kern = kern;
     pe.prec = prec;
     pe.bytes = bytes;
-    OVL_HIP(hipEventCreate(&pe.a));
-    OVL_HIP(hipEventCreate(&pe.b));
-    OVL_HIP(hipEventRecord(pe.a, stream));
+    if (event_pool.size() < 2) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            OVL_HIP(hipEventCreate(&e));
+            event_pool.push_back(e);
+        }
+    }
+    pe.a = event_pool.back();
+    event_pool.pop_back();
+    pe.b = event_pool.back();
+    event_pool.pop_back();
 }
 
 void Context::prof_end(PendingEvent &pe)
 {
-    OVL_HIP(hipEventRecord(pe.b, stream));
     pending.push_back(pe);
-    if (pending.size() > 4096) prof_collect();
+    if (pending.size() > 32768) prof_collect();
 }
 
 void Context::prof_collect()
@@ -94,8 +101,8 @@ void Context::prof_collect()
         s.launches += 1;
         s.ms += ms;
         s.bytes += pe.bytes;
-        OVL_HIP(hipEventDestroy(pe.a));
-        OVL_HIP(hipEventDestroy(pe.b));
+        event_pool.push_back(pe.a);
+        event_pool.push_back(pe.b);
     }
     pending.clear();
 }
@@ -107,6 +114,7 @@ Context::~Context()
         hipEventDestroy(pe.a);
         hipEventDestroy(pe.b);
     }
+    for (auto e : event_pool) hipEventDestroy(e);
     for (auto e : free_events) hipEventDestroy(e);
     for (auto &kv : pool)
         if (kv.second.p) hipFree(kv.second.p);

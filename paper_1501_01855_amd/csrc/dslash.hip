@@ -346,26 +346,27 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
 // Launch shape chosen per (precision, epilogue, nf) by timing the variants on
 // the context's lattice the first time that shape is used (autotuning).
 template <typename ST, typename GT, int EPI, int TPS, bool REMAP>
-static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf)
+static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, const PendingEvent *pe)
 {
     dim3 grid((unsigned)((c.g.V * TPS + 255) / 256), nf);
-    k_stencil<ST, GT, EPI, TPS, REMAP><<<grid, 256, 0, c.stream>>>(a, U);
+    launch_k(c.stream, pe, k_stencil<ST, GT, EPI, TPS, REMAP>, grid, dim3(256), 0, a, U);
 }
 
 template <typename ST, typename GT, int EPI>
-static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT *U, int nf)
+static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT *U, int nf,
+                         const PendingEvent *pe = nullptr)
 {
     if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: one thread per site only
         if (id == 0)
-            launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf);
+            launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf, pe);
         else
-            launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf);
+            launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf, pe);
     } else {
         switch (id) {
-        case 0: launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf); break;
-        case 1: launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf); break;
-        case 2: launch_variant<ST, GT, EPI, 2, false>(c, a, U, nf); break;
-        default: launch_variant<ST, GT, EPI, 2, true>(c, a, U, nf); break;
+        case 0: launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf, pe); break;
+        case 1: launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf, pe); break;
+        case 2: launch_variant<ST, GT, EPI, 2, false>(c, a, U, nf, pe); break;
+        default: launch_variant<ST, GT, EPI, 2, true>(c, a, U, nf, pe); break;
         }
     }
 }
@@ -411,11 +412,14 @@ static void launch_stencil_t(Context &c, const StencilArgs<ST> &a, const GT *U, 
 {
     const int v = tuned_variant<ST, GT, EPI>(c, a, U, nf, prec);
     PendingEvent pe;
-    const double bytes = stencil_bytes(c.g, prec, EPI) * nf;
-    if (profile && c.prof) c.prof_begin(pe, KERN_STENCIL, prec, bytes);
-    launch_by_id<ST, GT, EPI>(c, v, a, U, nf);
+    // launches inside the multi-shift CG (a.stop set) may skip converged
+    // fields; their driver books the bytes of the work actually done
+    const double bytes = a.stop ? 0.0 : stencil_bytes(c.g, prec, EPI) * nf;
+    const bool prof = profile && c.prof;
+    if (prof) c.prof_begin(pe, KERN_STENCIL, prec, bytes);
+    launch_by_id<ST, GT, EPI>(c, v, a, U, nf, prof ? &pe : nullptr);
     OVL_HIP(hipGetLastError());
-    if (profile && c.prof) c.prof_end(pe);
+    if (prof) c.prof_end(pe);
 }
 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,

@@ -402,12 +402,13 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
                                                            rr_part);
             PendingEvent pe;
             if (c.prof) c.prof_begin(pe, KERN_SHIFT, prec, 0.0);
+            const PendingEvent *ppe = c.prof ? &pe : nullptr;
             if (all)
-                k_mscg_shift<ST, true><<<ugrid, 256, 0, c.stream>>>(src, r, y, p, S, kdev, stop, fin, it, V, part,
-                                                                   ntile, rr_part, nupd);
+                launch_k(c.stream, ppe, k_mscg_shift<ST, true>, ugrid, dim3(256), 0, src, r, y, p, S, kdev, stop,
+                         fin, it, V, part, ntile, rr_part, (int)nupd);
             else
-                k_mscg_shift<ST, false><<<ugrid, 256, 0, c.stream>>>(src, r, y, p, S, kdev, stop, fin, it, V, part,
-                                                                    ntile, rr_part, nupd);
+                launch_k(c.stream, ppe, k_mscg_shift<ST, false>, ugrid, dim3(256), 0, src, r, y, p, S, kdev, stop,
+                         fin, it, V, part, ntile, rr_part, (int)nupd);
             if (c.prof) c.prof_end(pe);
             OVL_HIP(hipGetLastError());
         }
@@ -459,9 +460,14 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
         if (hstop_final[f] != 0) c.last_field_iters[f] = hs[f].iters;
     // algorithmic bytes of the shift kernel: r, y in, y out, 2 per active shift
     // (with every solution kept: r, and p_l, x_l in and out per active shift)
-    if (c.prof)
+    if (c.prof) {
         c.slots[KERN_SHIFT][prec].bytes +=
             all ? (double)FB * (1.0 * iters + 4.0 * act_total) : (double)FB * (3.0 * iters + 2.0 * act_total);
+        // the two stencils of each executed iteration (K, then K with the
+        // shift, the dot and an extra read of p)
+        c.slots[KERN_STENCIL][prec].bytes +=
+            (double)iters * (stencil_bytes(g, prec, EPI_K) + stencil_bytes(g, prec, EPI_K2DOT));
+    }
     OVL_REQUIRE(!brk, OVL_ERR_BREAKDOWN, "multi-shift CG breakdown (non-positive curvature or NaN)");
     OVL_REQUIRE(!capped, OVL_ERR_NOT_CONVERGED, "multi-shift CG hit its iteration limit");
 }
