@@ -251,8 +251,10 @@ ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int6
 
 /* Stencil launch shapes.  The first launch of each (precision, epilogue,
  * field count) times the launch variants on the context's lattice and keeps
- * the fastest (variant 0/1: one lane per site, plain or XCD-contiguous tile
- * order; 2/3: two lanes per site, likewise; FP16 storage uses 0/1 only).
+ * the fastest (variant 0/1: one lane per site, lexicographic tiles in plain
+ * or XCD-contiguous order; 2/3: two lanes per site, likewise; 4/5: one / two
+ * lanes per site, each XCD walking one of eight xyz columns through t, when
+ * the x, y, z extents split into 8 columns; FP16 storage: 0, 1, 4).
  * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the
  * number held; ovl_tuning_set installs pairs (variants out of range are an
  * argument error), so a run can reuse another run's choices. */

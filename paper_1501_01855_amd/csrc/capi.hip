@@ -493,9 +493,8 @@ ovl_status ovl_tuning_set(ovl_context *ctx, const int32_t *keys, const int32_t *
         OVL_REQUIRE(n >= 0 && (n == 0 || (keys && variants)), OVL_ERR_ARG, "bad arguments");
         for (int i = 0; i < n; ++i) {
             const int prec = keys[i] / 512;
-            OVL_REQUIRE(keys[i] >= 0 && prec <= OVL_HALF && variants[i] >= 0 &&
-                            variants[i] < (prec == OVL_HALF ? 2 : 4),
-                        OVL_ERR_ARG, "tuning variant out of range");
+            OVL_REQUIRE(keys[i] >= 0 && prec <= OVL_HALF && stencil_variant_ok(ctx->g, prec, variants[i]),
+                        OVL_ERR_ARG, "tuning variant out of range for this lattice and precision");
         }
         for (int i = 0; i < n; ++i) ctx->tuned[keys[i]] = variants[i];
     });

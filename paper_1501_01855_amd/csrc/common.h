@@ -65,10 +65,23 @@ template <typename R>
 __host__ __device__ inline cplx<R> times_mi(cplx<R> a) { return {a.im, -a.re}; }
 
 // ---------------------------------------------------------------- geometry
+// Column blocking of the x, y, z extents for the XCD-aware stencil launch:
+// the xyz volume is cut into 8 columns of cb[0] x cb[1] x cb[2] sites
+// (cn[m] columns along m), each column running through all of t.  col_ok is
+// false when no split into 8 columns divides the extents.
+// Link planes ([mu][9][Pu]) are Pu = V + LINK_PAD sites apart, not V: with a
+// power-of-two V the 36 planes of a site would otherwise sit a power of two
+// apart and compete for the same L2 sets and memory channels.
+constexpr int64_t LINK_PAD = 544;   // 17 x 32 sites: an odd number of 128 B lines for 8 B entries
+
 struct Geom {
     int32_t L[4];
     int64_t stride[4];
     int64_t V;
+    int64_t Pu;          // link plane stride (sites)
+    int32_t cb[3], cn[3];
+    int32_t col_sites;   // cb[0] cb[1] cb[2]
+    int32_t col_ok;
 };
 
 inline Geom make_geom(const int32_t d[4])
@@ -81,6 +94,39 @@ inline Geom make_geom(const int32_t d[4])
         s *= d[m];
     }
     g.V = s;
+    g.Pu = s + LINK_PAD;
+    // the split into 8 = cx cy cz columns with the smallest halo: a cut face
+    // along m re-reads 2 / cb[m] of the column's sites, a cut along x whole
+    // 128-byte lines (8 sites) per row end, so x rows stay whole if possible
+    g.col_ok = 0;
+    double best = 1e30;
+    for (int cx = 1; cx <= 8; cx *= 2)
+        for (int cy = 1; cx * cy <= 8; cy *= 2) {
+            const int cz = 8 / (cx * cy);
+            const int c[3] = {cx, cy, cz};
+            bool ok = true;
+            int b[3];
+            for (int m = 0; m < 3; ++m) {
+                ok = ok && d[m] % c[m] == 0;
+                b[m] = ok ? d[m] / c[m] : 0;
+            }
+            if (!ok || b[0] < 4) continue;
+            double cost = 0.0;
+            for (int m = 0; m < 3; ++m)
+                if (c[m] > 1) cost += (m == 0 ? 16.0 : 2.0) / b[m];
+            cost -= 1e-6 * b[2];   // ties: deeper columns in z
+            if (cost < best) {
+                best = cost;
+                g.col_ok = 1;
+                for (int m = 0; m < 3; ++m) {
+                    g.cb[m] = b[m];
+                    g.cn[m] = c[m];
+                }
+            }
+        }
+    if (!g.col_ok)
+        for (int m = 0; m < 3; ++m) g.cb[m] = g.cn[m] = 1;
+    g.col_sites = g.cb[0] * g.cb[1] * g.cb[2];
     return g;
 }
 

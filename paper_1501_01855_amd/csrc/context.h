@@ -41,9 +41,9 @@ struct Context {
     int num_cu = 256;
 
     // gauge field, packed per precision
-    double2 *U64 = nullptr;   // [4][9][V]
-    float2 *U32 = nullptr;    // [4][9][V]
-    void *U16 = nullptr;      // __half2 [4][9][V]
+    double2 *U64 = nullptr;   // [4][9][Pu] (Geom::Pu: padded plane stride)
+    float2 *U32 = nullptr;    // [4][9][Pu]
+    void *U16 = nullptr;      // __half2 [4][9][Pu]
     bool have_gauge = false;
 
     // kernel low modes: FP64 packed [n][12][V] and eigenvalues

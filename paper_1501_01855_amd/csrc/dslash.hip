@@ -9,6 +9,7 @@
 // 2 x 3 x 3 complex multiply-adds per half spinor.  Neighbour indices are
 // computed arithmetically (no index table).  Spinor and link planes are
 // site-major, so consecutive lanes issue consecutive 16-byte loads.
+#include <algorithm>
 #include <type_traits>
 
 #include "context.h"
@@ -68,7 +69,7 @@ __global__ void k_f32_to_f64(const float4 *__restrict__ in, double2 *__restrict_
 }
 
 __global__ void k_pack_gauge(const double2 *__restrict__ canon, double2 *__restrict__ U64,
-                             float2 *__restrict__ U32, __half2 *__restrict__ U16, int64_t V)
+                             float2 *__restrict__ U32, __half2 *__restrict__ U16, int64_t V, int64_t Pu)
 {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= V) return;
@@ -76,9 +77,9 @@ __global__ void k_pack_gauge(const double2 *__restrict__ canon, double2 *__restr
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const double2 u = canon[s * 36 + mu * 9 + k];
-            U64[(mu * 9 + k) * V + s] = u;
-            U32[(mu * 9 + k) * V + s] = make_float2((float)u.x, (float)u.y);
-            U16[(mu * 9 + k) * V + s] = __floats2half2_rn((float)u.x, (float)u.y);
+            U64[(mu * 9 + k) * Pu + s] = u;
+            U32[(mu * 9 + k) * Pu + s] = make_float2((float)u.x, (float)u.y);
+            U16[(mu * 9 + k) * Pu + s] = __floats2half2_rn((float)u.x, (float)u.y);
         }
 }
 
@@ -169,13 +170,13 @@ void pack_gauge(Context &c, const double *canon)
 {
     const Geom &g = c.g;
     if (!c.U64) {
-        OVL_HIP(hipMalloc(&c.U64, (size_t)g.V * 36 * sizeof(double2)));
-        OVL_HIP(hipMalloc(&c.U32, (size_t)g.V * 36 * sizeof(float2)));
-        OVL_HIP(hipMalloc(&c.U16, (size_t)g.V * 36 * sizeof(__half2)));
-        c.bytes_held += (int64_t)g.V * 36 * (16 + 8 + 4);
+        OVL_HIP(hipMalloc(&c.U64, (size_t)g.Pu * 36 * sizeof(double2)));
+        OVL_HIP(hipMalloc(&c.U32, (size_t)g.Pu * 36 * sizeof(float2)));
+        OVL_HIP(hipMalloc(&c.U16, (size_t)g.Pu * 36 * sizeof(__half2)));
+        c.bytes_held += (int64_t)g.Pu * 36 * (16 + 8 + 4);
     }
     k_pack_gauge<<<site_blocks(g), 256, 0, c.stream>>>((const double2 *)canon, c.U64, c.U32, (__half2 *)c.U16,
-                                                       g.V);
+                                                       g.V, g.Pu);
     OVL_HIP(hipGetLastError());
     c.have_gauge = true;
 }
@@ -187,7 +188,8 @@ void pack_gauge(Context &c, const double *canon)
 // each thread finishes and stores half of the output spinor -- twice the
 // threads for small lattices.
 template <int MU, typename R, typename ST, typename GT>
-__device__ __forceinline__ void gather_dir(const ST *__restrict__ in, const GT *__restrict__ U, int64_t V, int64_t s,
+__device__ __forceinline__ void gather_dir(const ST *__restrict__ in, const GT *__restrict__ U, int64_t V, int64_t Pu,
+                                           int64_t s,
                                            int32_t c, int32_t Lm, int64_t st, cplx<R> acc[12])
 {
     cplx<R> psi[12];
@@ -195,23 +197,24 @@ __device__ __forceinline__ void gather_dir(const ST *__restrict__ in, const GT *
     const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st : s + st;
     const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st : s - st;
     ld_sp(in, V, fwd, psi);
-    ld_link(U, V, MU, s, u);
+    ld_link(U, Pu, MU, s, u);
     hop_term<MU, true>(psi, u, acc);
     ld_sp(in, V, bwd, psi);
-    ld_link(U, V, MU, bwd, u);
+    ld_link(U, Pu, MU, bwd, u);
     hop_term<MU, false>(psi, u, acc);
 }
 
 // Directions MU0..MU1.  Four directions run as a non-unrolled loop (bounded
 // register use); two are unrolled.
 template <int MU0, int MU1, typename R, typename ST, typename GT>
-__device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__restrict__ U, int64_t V, int64_t s,
+__device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__restrict__ U, int64_t V, int64_t Pu,
+                                       int64_t s,
                                        const int32_t co[4], const int32_t Ls[4], const int64_t st[4],
                                        cplx<R> acc[12])
 {
     if constexpr (MU1 - MU0 == 1) {
-        gather_dir<MU0, R>(in, U, V, s, co[MU0], Ls[MU0], st[MU0], acc);
-        gather_dir<MU1, R>(in, U, V, s, co[MU1], Ls[MU1], st[MU1], acc);
+        gather_dir<MU0, R>(in, U, V, Pu, s, co[MU0], Ls[MU0], st[MU0], acc);
+        gather_dir<MU1, R>(in, U, V, Pu, s, co[MU1], Ls[MU1], st[MU1], acc);
     } else {
         cplx<R> psi[12];
         cplx<R> u[9];
@@ -221,7 +224,7 @@ __device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__re
             const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st[mu] : s + st[mu];
             const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st[mu] : s - st[mu];
             ld_sp(in, V, fwd, psi);
-            ld_link(U, V, mu, s, u);
+            ld_link(U, Pu, mu, s, u);
             switch (mu) {
             case 0: hop_term<0, true>(psi, u, acc); break;
             case 1: hop_term<1, true>(psi, u, acc); break;
@@ -229,7 +232,7 @@ __device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__re
             default: hop_term<3, true>(psi, u, acc); break;
             }
             ld_sp(in, V, bwd, psi);
-            ld_link(U, V, mu, bwd, u);
+            ld_link(U, Pu, mu, bwd, u);
             switch (mu) {
             case 0: hop_term<0, false>(psi, u, acc); break;
             case 1: hop_term<1, false>(psi, u, acc); break;
@@ -240,42 +243,84 @@ __device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__re
     }
 }
 
-template <typename ST, typename GT, int EPI, int TPS, bool REMAP>
+// Site traversal orders (MAP):
+//  MAP_LEX    block b takes sites [b n, (b + 1) n) in lexicographic order;
+//  MAP_REMAP  the same tiles, but each XCD (blocks are handed to the eight
+//             XCDs round-robin) receives a contiguous range of them;
+//  MAP_COL    each XCD owns one of eight xyz columns (Geom::cb) and walks it
+//             through t, a column slice at a time, so that the t- and
+//             z-neighbours of a slice are fetched by the same XCD shortly
+//             before or after and meet in its L2.
+// Fields run fastest within a tile (the fields of one tile share its links).
+enum { MAP_LEX = 0, MAP_REMAP = 1, MAP_COL = 2 };
+
+template <int MAP, int TPS>
+__device__ __forceinline__ void site_of_thread(const Geom &g, unsigned &tile, unsigned &f, int64_t &s, int32_t co[4],
+                                               bool &valid)
+{
+    constexpr int SPB = 256 / TPS;   // sites per block
+    const int lane = TPS == 2 ? (int)(threadIdx.x & 127) : (int)threadIdx.x;
+    if constexpr (MAP == MAP_COL) {
+        const unsigned X = gridDim.x, Y = gridDim.y;
+        const unsigned lin = blockIdx.y * X + blockIdx.x;
+        const unsigned col = lin % 8, k = lin / 8;
+        f = k % Y;
+        const unsigned rest = k / Y;              // [0, Lt tps)
+        const unsigned per_col = X / 8;           // Lt tps
+        tile = col * per_col + rest;
+        const unsigned tps = per_col / (unsigned)g.L[3];
+        const int32_t t = (int32_t)(rest / tps);
+        const int32_t local = (int32_t)(rest % tps) * SPB + lane;
+        valid = local < g.col_sites;
+        const int32_t cx = (int32_t)col % g.cn[0], cy = ((int32_t)col / g.cn[0]) % g.cn[1],
+                      cz = (int32_t)col / (g.cn[0] * g.cn[1]);
+        co[0] = cx * g.cb[0] + local % g.cb[0];
+        co[1] = cy * g.cb[1] + (local / g.cb[0]) % g.cb[1];
+        co[2] = cz * g.cb[2] + local / (g.cb[0] * g.cb[1]);
+        co[3] = t;
+        s = co[0] + (int64_t)g.L[0] * (co[1] + (int64_t)g.L[1] * (co[2] + (int64_t)g.L[2] * co[3]));
+    } else {
+        tile_of_block<MAP == MAP_REMAP>(tile, f);
+        s = (int64_t)tile * SPB + lane;
+        valid = s < g.V;
+        const int32_t si = valid ? (int32_t)s : 0;
+        co[0] = si % g.L[0];
+        int32_t rem = si / g.L[0];
+        co[1] = rem % g.L[1];
+        rem /= g.L[1];
+        co[2] = rem % g.L[2];
+        co[3] = rem / g.L[2];
+    }
+}
+
+template <typename ST, typename GT, int EPI, int TPS, int MAP>
 __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__restrict__ U)
 {
     using R = typename Planes<ST>::R;
     constexpr int NC = 12 / TPS;   // complex components owned by one lane
     unsigned tile, f;
-    tile_of_block<REMAP>(tile, f);
+    int64_t s;
+    int32_t co[4];
+    bool valid;
+    site_of_thread<MAP, TPS>(a.g, tile, f, s, co, valid);
     if (a.stop != nullptr && a.it >= a.stop[f]) return;   // field already converged
     const int64_t V = a.g.V;
-    const int64_t s = (int64_t)tile * (256 / TPS) + (TPS == 2 ? (threadIdx.x & 127) : threadIdx.x);
     const int half = TPS == 2 ? (int)(threadIdx.x >> 7) : 0;
-    const bool valid = s < V;
     const ST *in = a.in + f * fstride<ST>(V);
     double part = 0.0;
     cplx<R> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
     if (valid) {
-        const int32_t L0 = a.g.L[0], L1 = a.g.L[1], L2 = a.g.L[2], L3 = a.g.L[3];
-        const int32_t si = (int32_t)s;
-        int32_t co[4];
-        co[0] = si % L0;
-        int32_t rem = si / L0;
-        co[1] = rem % L1;
-        rem /= L1;
-        co[2] = rem % L2;
-        co[3] = rem / L2;
-        const int32_t Ls[4] = {L0, L1, L2, L3};
+        const int32_t Ls[4] = {a.g.L[0], a.g.L[1], a.g.L[2], a.g.L[3]};
         const int64_t st[4] = {a.g.stride[0], a.g.stride[1], a.g.stride[2], a.g.stride[3]};
         if constexpr (TPS == 1) {
-            gather<0, 3, R>(in, U, V, s, co, Ls, st, acc);
+            gather<0, 3, R>(in, U, V, a.g.Pu, s, co, Ls, st, acc);
         } else {
             if (half == 0)
-                gather<0, 1, R>(in, U, V, s, co, Ls, st, acc);
+                gather<0, 1, R>(in, U, V, a.g.Pu, s, co, Ls, st, acc);
             else
-                gather<2, 3, R>(in, U, V, s, co, Ls, st, acc);
+                gather<2, 3, R>(in, U, V, a.g.Pu, s, co, Ls, st, acc);
         }
     }
     if constexpr (TPS == 2) {
@@ -345,11 +390,43 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
 
 // Launch shape chosen per (precision, epilogue, nf) by timing the variants on
 // the context's lattice the first time that shape is used (autotuning).
-template <typename ST, typename GT, int EPI, int TPS, bool REMAP>
+// Launch variants: 0 / 1 one lane per site, MAP_LEX / MAP_REMAP; 2 / 3 two
+// lanes per site, likewise; 4 / 5 MAP_COL with one / two lanes per site.
+// FP16 storage runs one lane per site (variants 0, 1, 4).
+static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5) ? 2 : 1; }
+
+unsigned stencil_tiles(const Geom &g, int v)
+{
+    const int tps = variant_tps(v);
+    if (v >= 4) {
+        const int spb = 256 / tps;
+        return 8u * (unsigned)g.L[3] * (unsigned)((g.col_sites + spb - 1) / spb);
+    }
+    return (unsigned)((g.V * tps + 255) / 256);
+}
+
+int64_t stencil_tiles_max(const Geom &g)
+{
+    int64_t m = 0;
+    for (int v = 0; v < 6; ++v)
+        if (v < 4 || g.col_ok) m = std::max<int64_t>(m, stencil_tiles(g, v));
+    return m;
+}
+
+bool stencil_variant_ok(const Geom &g, int prec, int v)
+{
+    if (v < 0 || v > 5) return false;
+    if (v >= 4 && !g.col_ok) return false;
+    if (prec == OVL_HALF) return v == 0 || v == 1 || v == 4;
+    return true;
+}
+
+template <typename ST, typename GT, int EPI, int TPS, int MAP>
 static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, const PendingEvent *pe)
 {
-    dim3 grid((unsigned)((c.g.V * TPS + 255) / 256), nf);
-    launch_k(c.stream, pe, k_stencil<ST, GT, EPI, TPS, REMAP>, grid, dim3(256), 0, a, U);
+    const int v = MAP == MAP_COL ? (TPS == 2 ? 5 : 4) : (TPS == 2 ? 2 : 0) + (MAP == MAP_REMAP ? 1 : 0);
+    dim3 grid(stencil_tiles(c.g, v), nf);
+    launch_k(c.stream, pe, k_stencil<ST, GT, EPI, TPS, MAP>, grid, dim3(256), 0, a, U);
 }
 
 template <typename ST, typename GT, int EPI>
@@ -358,20 +435,24 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
 {
     if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: one thread per site only
         if (id == 0)
-            launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf, pe);
+            launch_variant<ST, GT, EPI, 1, MAP_LEX>(c, a, U, nf, pe);
+        else if (id == 1)
+            launch_variant<ST, GT, EPI, 1, MAP_REMAP>(c, a, U, nf, pe);
         else
-            launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf, pe);
+            launch_variant<ST, GT, EPI, 1, MAP_COL>(c, a, U, nf, pe);
     } else {
         switch (id) {
-        case 0: launch_variant<ST, GT, EPI, 1, false>(c, a, U, nf, pe); break;
-        case 1: launch_variant<ST, GT, EPI, 1, true>(c, a, U, nf, pe); break;
-        case 2: launch_variant<ST, GT, EPI, 2, false>(c, a, U, nf, pe); break;
-        default: launch_variant<ST, GT, EPI, 2, true>(c, a, U, nf, pe); break;
+        case 0: launch_variant<ST, GT, EPI, 1, MAP_LEX>(c, a, U, nf, pe); break;
+        case 1: launch_variant<ST, GT, EPI, 1, MAP_REMAP>(c, a, U, nf, pe); break;
+        case 2: launch_variant<ST, GT, EPI, 2, MAP_LEX>(c, a, U, nf, pe); break;
+        case 3: launch_variant<ST, GT, EPI, 2, MAP_REMAP>(c, a, U, nf, pe); break;
+        case 4: launch_variant<ST, GT, EPI, 1, MAP_COL>(c, a, U, nf, pe); break;
+        default: launch_variant<ST, GT, EPI, 2, MAP_COL>(c, a, U, nf, pe); break;
         }
     }
 }
 
-static constexpr int N_VARIANTS = 4;
+static constexpr int N_VARIANTS = 6;
 
 template <typename ST, typename GT, int EPI>
 static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, int prec)
@@ -384,12 +465,12 @@ static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int 
     StencilArgs<ST> t = a;
     t.stop = nullptr;
     t.out = (ST *)c.buf("tune_out", field_bytes(c.g, prec) * nf);
-    t.partial = (double *)c.buf("tune_part", sizeof(double) * (size_t)nf * (c.g.V * 2 / 256 + 1));
+    t.partial = (double *)c.buf("tune_part", sizeof(double) * (size_t)nf * stencil_tiles_max(c.g));
     hipEvent_t e0 = c.event(), e1 = c.event();
     int best = 0;
     float best_ms = 1e30f;
-    const int nvar = std::is_same<ST, h8>::value ? 2 : N_VARIANTS;
-    for (int v = 0; v < nvar; ++v) {
+    for (int v = 0; v < N_VARIANTS; ++v) {
+        if (!stencil_variant_ok(c.g, prec, v)) continue;
         launch_by_id<ST, GT, EPI>(c, v, t, U, nf);   // warm-up
         OVL_HIP(hipEventRecord(e0, c.stream));
         for (int r = 0; r < 5; ++r) launch_by_id<ST, GT, EPI>(c, v, t, U, nf);
@@ -463,8 +544,7 @@ int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double 
     stencil(c, EPI_K2DOT, prec, t, w, nf, rho, s0, p, partial, stop, it);
     const int key = (prec * 8 + EPI_K2DOT) * 64 + (nf < 63 ? nf : 63);
     const int v = c.tuned.count(key) ? c.tuned[key] : 1;
-    const int tps = v >= 2 ? 2 : 1;
-    return (int)((c.g.V * tps + 255) / 256);
+    return (int)stencil_tiles(c.g, v);
 }
 
 void launch_hop(Context &c, const void *in, void *out, int nf, int prec)

@@ -151,33 +151,34 @@ __device__ __forceinline__ void st_sp(h8 *__restrict__ p, int64_t V, int64_t s, 
 }
 
 // ------------------------------------------------------------------ links
-__device__ __forceinline__ void ld_link(const double2 *__restrict__ U, int64_t V, int mu,
+// Link planes [mu][9][P], P the padded plane stride (Geom::Pu).
+__device__ __forceinline__ void ld_link(const double2 *__restrict__ U, int64_t P, int mu,
                                         int64_t s, cplx<double> u[9])
 {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        double2 t = U[(mu * 9 + k) * V + s];
+        double2 t = U[(mu * 9 + k) * P + s];
         u[k] = {t.x, t.y};
     }
 }
-__device__ __forceinline__ void ld_link(const float2 *__restrict__ U, int64_t V, int mu,
+__device__ __forceinline__ void ld_link(const float2 *__restrict__ U, int64_t P, int mu,
                                         int64_t s, cplx<float> u[9])
 {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        float2 t = U[(mu * 9 + k) * V + s];
+        float2 t = U[(mu * 9 + k) * P + s];
         u[k] = {t.x, t.y};
     }
 }
 
 // FP16 links: one __half2 per complex entry, [4][9][V] (entries of a unitary
 // matrix have modulus <= 1, so no scale is needed).
-__device__ __forceinline__ void ld_link(const __half2 *__restrict__ U, int64_t V, int mu,
+__device__ __forceinline__ void ld_link(const __half2 *__restrict__ U, int64_t P, int mu,
                                         int64_t s, cplx<float> u[9])
 {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const float2 t = __half22float2(U[(mu * 9 + k) * V + s]);
+        const float2 t = __half22float2(U[(mu * 9 + k) * P + s]);
         u[k] = {t.x, t.y};
     }
 }

@@ -33,6 +33,10 @@ int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
              double sigma, const void *aux, double *partial, const int *stop = nullptr, int it = 0);
 double stencil_bytes(const Geom &g, int prec, int epi);
+// tiles (blocks per field) of stencil launch variant v; the largest over variants
+unsigned stencil_tiles(const Geom &g, int v);
+int64_t stencil_tiles_max(const Geom &g);
+bool stencil_variant_ok(const Geom &g, int prec, int v);
 
 // ---------------------------------------------------------------- BLAS-1 (packed FP64 fields)
 // All take nf fields; scalars are per field (host arrays of nf complex / real).

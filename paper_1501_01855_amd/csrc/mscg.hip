@@ -315,7 +315,7 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     const int64_t V = g.V;
     const size_t FB = field_bytes(g, prec);
     const unsigned nblk = site_blocks(g);
-    const unsigned nblk_max = site_blocks(g, 128);   // two lanes per site
+    const unsigned nblk_max = (unsigned)stencil_tiles_max(g);   // tiles of any stencil variant
     const dim3 grid(nblk, nf);
     const unsigned nupd = std::min<unsigned>(UPD_BLOCKS, nblk);
     const dim3 ugrid(nupd, nf);

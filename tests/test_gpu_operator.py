@@ -90,3 +90,50 @@ def test_hop_and_K_half(dims):
     k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4, prec=ovl.HALF))
     assert max_rel_elem(h, ora.hop(psi)) < 5e-3
     assert rel(k, ora.K(psi)) < 2e-3
+
+
+def _keys(prec, nf):
+    # stencil launch table keys: (prec * 8 + epilogue) * 64 + field count
+    return [(prec * 8 + e) * 64 + nf for e in range(4)]
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 16), (4, 6, 2, 8)])
+def test_every_launch_variant(dims):
+    """Every stencil launch variant (traversal order x lanes per site), forced
+    through the tuning table, for the plain stencil and K (two fields) and
+    for the multi-shift CG's fused K^2 + sigma / dot launch (through sign(K)),
+    in each storage precision."""
+    ovl = require_gpu()
+    from oracle import krylov
+    from oracle.zolotarev import Zolotarev
+    print("case", dims, flush=True)
+    U = synth.gauge_field(dims, 14, 0.3)
+    ora = WilsonKernel(dims, U, 1.4)
+    psi = np.stack([synth.gaussian_source(dims, 40), synth.z2_source(dims, 41)])
+    z = Zolotarev(12, 0.3, 6.6)
+    sref = krylov.SignFunction(ora, z)(psi[0], 1e-14)
+    hop_ref = [ora.hop(p) for p in psi]
+    k_ref = [ora.K(p) for p in psi]
+    tol = {ovl.F64: 1e-14, ovl.F32: 2e-6, ovl.HALF: 5e-3}
+    for prec in (ovl.F64, ovl.F32, ovl.HALF):
+        variants = [0, 1, 4] if prec == ovl.HALF else [0, 1, 2, 3, 4, 5]
+        if dims == (4, 6, 2, 8):   # no split of x, y, z into 8 columns: 4 and 5 unavailable
+            variants = [v for v in variants if v < 4]
+        for v in variants:
+            ctx = ovl.Context(dims)
+            ctx.gauge_load(to_dev(U))
+            ctx.set_tuning({k: v for nf in (1, 2) for k in _keys(prec, nf)})
+            h = to_host(ctx.wilson_dslash(to_dev(psi), prec=prec))
+            k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4, prec=prec))
+            for r in range(2):
+                assert max_rel_elem(h[r], hop_ref[r]) < tol[prec], (prec, v)
+                if prec == ovl.HALF:
+                    assert rel(k[r], k_ref[r]) < 2e-3, (prec, v)
+                else:
+                    assert max_rel_elem(k[r], k_ref[r]) < tol[prec], (prec, v)
+            zg = ovl.zolo_from(z.nz, z.a, z.b, z.delta, z.omega, z.sigma)
+            eta = {ovl.F64: 1e-13, ovl.F32: 1e-6, ovl.HALF: 1e-2}[prec]
+            s = to_host(ctx.sign(to_dev(psi[0]), 1.4, zg, eta, prec=prec)[0])
+            assert rel(s, sref) < {ovl.F64: 1e-12, ovl.F32: 1e-5, ovl.HALF: 1e-2}[prec], (prec, v)
+            assert ctx.tuning()[_keys(prec, 1)[2]] == v
+            ctx.close()
