@@ -33,6 +33,8 @@ __global__ __launch_bounds__(256) void k_dot(const double2 *__restrict__ x, cons
     }
 }
 
+// out may be host memory: the store is fenced at system scope, so it has
+// completed when the kernel has.
 __global__ __launch_bounds__(256) void k_sum_rows(const double *partial, int nblk, double *out)
 {
     __shared__ double lds[4];
@@ -40,7 +42,10 @@ __global__ __launch_bounds__(256) void k_sum_rows(const double *partial, int nbl
     const double *p = partial + (int64_t)blockIdx.x * nblk;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += p[i];
     const double t = block_sum<256>(v, lds);
-    if (threadIdx.x == 0) out[blockIdx.x] = t;
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = t;
+        __threadfence_system();
+    }
 }
 
 void sum_partials(Context &c, const double *partial, int nblk, int rows, double *out)
@@ -49,17 +54,23 @@ void sum_partials(Context &c, const double *partial, int nblk, int rows, double 
     OVL_HIP(hipGetLastError());
 }
 
+const double *sum_partials_host(Context &c, const double *partial, int nblk, int rows)
+{
+    double *dev = nullptr;
+    const double *h = c.host_results(rows, &dev);
+    k_sum_rows<<<rows, 256, 0, c.stream>>>(partial, nblk, dev);   // into host memory: no copy command
+    OVL_HIP(hipGetLastError());
+    OVL_HIP(hipStreamSynchronize(c.stream));
+    return h;
+}
+
 void dot_f64(Context &c, const double2 *x, const double2 *y, int nf, std::vector<cplx<double>> &out)
 {
     const int64_t n = 12 * c.g.V;
     double *part = (double *)c.buf("blas_part", sizeof(double) * RB * 2 * nf);
-    double *res = (double *)c.buf("blas_res", sizeof(double) * 2 * nf);
     k_dot<<<dim3(RB, nf), 256, 0, c.stream>>>(x, y, n, part);
-    k_sum_rows<<<2 * nf, 256, 0, c.stream>>>(part, RB, res);
     OVL_HIP(hipGetLastError());
-    double *h = (double *)c.host_stage(sizeof(double) * 2 * nf);
-    OVL_HIP(hipMemcpyAsync(h, res, sizeof(double) * 2 * nf, hipMemcpyDeviceToHost, c.stream));
-    OVL_HIP(hipStreamSynchronize(c.stream));
+    const double *h = sum_partials_host(c, part, RB, 2 * nf);
     out.resize(nf);
     for (int f = 0; f < nf; ++f) out[f] = {h[2 * f], h[2 * f + 1]};
 }
@@ -178,13 +189,9 @@ void multidot_f64(Context &c, const double2 *Vb, int nv, const double2 *x, int n
     const int64_t n = 12 * c.g.V;
     const int nb = 128;
     double *part = (double *)c.buf("mdot_part", sizeof(double) * nb * 2 * nf * nv);
-    double *res = (double *)c.buf("mdot_res", sizeof(double) * 2 * nf * nv);
     k_multidot<<<dim3(nb, nf, nv), 256, 0, c.stream>>>(Vb, nv, x, n, part);
-    k_sum_rows<<<2 * nf * nv, 256, 0, c.stream>>>(part, nb, res);
     OVL_HIP(hipGetLastError());
-    double *h = (double *)c.host_stage(sizeof(double) * 2 * nf * nv);
-    OVL_HIP(hipMemcpyAsync(h, res, sizeof(double) * 2 * nf * nv, hipMemcpyDeviceToHost, c.stream));
-    OVL_HIP(hipStreamSynchronize(c.stream));
+    const double *h = sum_partials_host(c, part, nb, 2 * nf * nv);
     for (int i = 0; i < nf * nv; ++i) out[i] = {h[2 * i], h[2 * i + 1]};
 }
 

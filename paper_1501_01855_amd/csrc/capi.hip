@@ -215,6 +215,7 @@ ovl_status ovl_lowmodes_set(ovl_context *ctx, int32_t n, const double *evals_hos
         check_ctx(ctx);
         OVL_REQUIRE(n >= 0 && n <= 256, OVL_ERR_ARG, "n must be in [0, 256]");
         if (n > 0) OVL_REQUIRE(evals_host && evecs_dev, OVL_ERR_ARG, "null low-mode data");
+        ctx->lowmodes_changed();
         if (ctx->low) {
             OVL_HIP(hipStreamSynchronize(ctx->stream));
             OVL_HIP(hipFree(ctx->low));

@@ -50,6 +50,19 @@ struct Context {
     int n_low = 0;
     double2 *low = nullptr;
     std::vector<double> low_evals;
+    // derived from them on first use: the basis in FP32 / FP16 storage (for
+    // the sign function in those precisions) and sign(lambda_j) on the device
+    void *low_lp[3] = {nullptr, nullptr, nullptr};
+    double *low_sgn = nullptr;
+    void lowmodes_changed();                  // drop the derived copies
+    const void *low_basis(int prec);
+    const double *low_signs();
+
+    // multi-shift CG: pinned host staging (constants, accuracies, polled
+    // flags), its two poll events and the constants last uploaded
+    void *ms_pin = nullptr;
+    hipEvent_t ms_ev[2] = {nullptr, nullptr};
+    std::vector<char> ms_const_last;
 
     // named workspace; grows on demand, freed at destroy
     std::map<std::string, DevBuf> pool;
@@ -79,6 +92,12 @@ struct Context {
     void *buf(const std::string &name, size_t bytes);
     void *counters();
     void *host_stage(size_t bytes);
+    // small results that kernels write straight into host memory (pinned,
+    // mapped, coherent): host address, and the device address of the same
+    // memory; valid until the next call (callers synchronise before reading)
+    double *host_results(size_t n, double **dev);
+    double *hres = nullptr, *hres_dev = nullptr;
+    size_t hres_n = 0;
     hipEvent_t event();
     // prof_begin creates the events; launch the kernel with them through
     // launch_k(); prof_end queues them for prof_collect().

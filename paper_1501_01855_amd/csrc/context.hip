@@ -1,6 +1,8 @@
 // Context life cycle, workspace, profiling events.
 #include <cstring>
 
+#include <algorithm>
+
 #include "context.h"
 #include "kernels.h"
 
@@ -44,6 +46,23 @@ void *Context::counters()
     return grid_counters;
 }
 
+double *Context::host_results(size_t n, double **dev)
+{
+    if (hres_n < n) {
+        if (hres) {
+            OVL_HIP(hipStreamSynchronize(stream));
+            OVL_HIP(hipHostFree(hres));
+            hres = nullptr;
+        }
+        const size_t cap = std::max<size_t>(n, 4096);
+        OVL_HIP(hipHostMalloc((void **)&hres, cap * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+        OVL_HIP(hipHostGetDevicePointer((void **)&hres_dev, hres, 0));
+        hres_n = cap;
+    }
+    *dev = hres_dev;
+    return hres;
+}
+
 void *Context::host_stage(size_t bytes)
 {
     if (pinned_bytes < bytes) {
@@ -64,6 +83,45 @@ hipEvent_t Context::event()
     OVL_HIP(hipEventCreate(&e));
     free_events.push_back(e);   // owned by the context; destroyed at exit
     return e;
+}
+
+void Context::lowmodes_changed()
+{
+    OVL_HIP(hipStreamSynchronize(stream));
+    for (int p = 1; p < 3; ++p)
+        if (low_lp[p]) {
+            OVL_HIP(hipFree(low_lp[p]));
+            bytes_held -= (int64_t)field_bytes(g, p) * n_low;
+            low_lp[p] = nullptr;
+        }
+    if (low_sgn) {
+        OVL_HIP(hipFree(low_sgn));
+        low_sgn = nullptr;
+    }
+}
+
+const void *Context::low_basis(int prec)
+{
+    if (prec == OVL_F64 || n_low == 0) return low;
+    if (!low_lp[prec]) {
+        const size_t B = field_bytes(g, prec) * n_low;
+        OVL_HIP(hipMalloc(&low_lp[prec], B));
+        bytes_held += (int64_t)B;
+        convert_spinor(*this, low, OVL_F64, low_lp[prec], prec, n_low);
+    }
+    return low_lp[prec];
+}
+
+const double *Context::low_signs()
+{
+    if (!low_sgn && n_low > 0) {
+        std::vector<double> sg(n_low);
+        for (int j = 0; j < n_low; ++j) sg[j] = low_evals[j] >= 0.0 ? 1.0 : -1.0;
+        OVL_HIP(hipMalloc(&low_sgn, sizeof(double) * n_low));
+        OVL_HIP(hipMemcpyAsync(low_sgn, sg.data(), sizeof(double) * n_low, hipMemcpyHostToDevice, stream));
+        OVL_HIP(hipStreamSynchronize(stream));   // sg is released on return
+    }
+    return low_sgn;
 }
 
 void Context::prof_begin(PendingEvent &pe, int kern, int prec, double bytes)
@@ -122,7 +180,14 @@ Context::~Context()
     if (U32) hipFree(U32);
     if (U16) hipFree(U16);
     if (low) hipFree(low);
+    for (int p = 1; p < 3; ++p)
+        if (low_lp[p]) hipFree(low_lp[p]);
+    if (low_sgn) hipFree(low_sgn);
+    if (ms_pin) hipHostFree(ms_pin);
+    for (auto e : ms_ev)
+        if (e) hipEventDestroy(e);
     if (pinned) hipHostFree(pinned);
+    if (hres) hipHostFree(hres);
     if (grid_counters) hipFree(grid_counters);
 }
 

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
     const int64_t V = a.g.V;
     const int half = TPS == 2 ? (int)(threadIdx.x >> 7) : 0;
     const ST *in = a.in + f * fstride<ST>(V);
-    double part = 0.0;
+    double part = 0.0, part1 = 0.0, part2 = 0.0;
     cplx<R> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
@@ -364,15 +364,27 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
                 const ST *aux = a.aux + f * fstride<ST>(V);
                 if constexpr (TPS == 1) ld_sp(aux, V, s, x); else ld_sp_half(aux, V, s, half, x);
                 if constexpr (EPI == EPI_K2DOT) {
-                    // w = K t + sigma p ; partial (p, w)
+                    // w = K t + sigma p ; partials (p, w), Re (r, w), (w, w) of w as stored
                     const R sg = (R)a.sigma;
-                    double d = 0.0;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) o[c] = o[c] + sg * x[c];
+                    cplx<R> ws[NC], rv[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) ws[c] = o[c];
+                    as_stored(a.out, ws, NC);
+                    const ST *aux2 = a.aux2 + f * fstride<ST>(V);
+                    if constexpr (TPS == 1) ld_sp(aux2, V, s, rv); else ld_sp_half(aux2, V, s, half, rv);
+                    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        o[c] = o[c] + sg * x[c];
-                        d += (double)x[c].re * (double)o[c].re + (double)x[c].im * (double)o[c].im;
+                        const double wr = ws[c].re, wi = ws[c].im;
+                        d0 += (double)x[c].re * wr + (double)x[c].im * wi;
+                        d1 += (double)rv[c].re * wr + (double)rv[c].im * wi;
+                        d2 += wr * wr + wi * wi;
                     }
-                    part = d;
+                    part = d0;
+                    part1 = d1;
+                    part2 = d2;
                 } else {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) o[c] = o[c] + x[c];
@@ -383,8 +395,15 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
     }
     if constexpr (EPI == EPI_K2DOT) {
         __shared__ double lds[4];
-        const double t = block_sum<256>(part, lds);
-        if (threadIdx.x == 0) a.partial[(int64_t)f * gridDim.x + tile] = t;
+        const double t0 = block_sum<256>(part, lds);
+        const double t1 = block_sum<256>(part1, lds);
+        const double t2 = block_sum<256>(part2, lds);
+        if (threadIdx.x == 0) {
+            double *pp = a.partial + (int64_t)f * 3 * gridDim.x + tile;
+            pp[0] = t0;
+            pp[gridDim.x] = t1;
+            pp[2 * gridDim.x] = t2;
+        }
     }
 }
 
@@ -465,7 +484,7 @@ static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int 
     StencilArgs<ST> t = a;
     t.stop = nullptr;
     t.out = (ST *)c.buf("tune_out", field_bytes(c.g, prec) * nf);
-    t.partial = (double *)c.buf("tune_part", sizeof(double) * (size_t)nf * stencil_tiles_max(c.g));
+    t.partial = (double *)c.buf("tune_part", sizeof(double) * 3 * (size_t)nf * stencil_tiles_max(c.g));
     hipEvent_t e0 = c.event(), e1 = c.event();
     int best = 0;
     float best_ms = 1e30f;
@@ -504,12 +523,12 @@ static void launch_stencil_t(Context &c, const StencilArgs<ST> &a, const GT *U, 
 }
 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
-             double sigma, const void *aux, double *partial, const int *stop, int it)
+             double sigma, const void *aux, double *partial, const int *stop, int it, const void *aux2)
 {
     OVL_REQUIRE(c.have_gauge, OVL_ERR_STATE, "no gauge field loaded");
     if (prec == OVL_F64) {
         StencilArgs<double2> a{c.g, (const double2 *)in, (double2 *)out, (const double2 *)aux,
-                               4.0 - rho, sigma, partial, stop, it};
+                               (const double2 *)aux2, 4.0 - rho, sigma, partial, stop, it};
         switch (epi) {
         case EPI_HOP: launch_stencil_t<double2, double2, EPI_HOP>(c, a, c.U64, nf, prec, true); break;
         case EPI_K: launch_stencil_t<double2, double2, EPI_K>(c, a, c.U64, nf, prec, true); break;
@@ -518,7 +537,7 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
         }
     } else if (prec == OVL_F32) {
         StencilArgs<float4> a{c.g, (const float4 *)in, (float4 *)out, (const float4 *)aux,
-                              4.0 - rho, sigma, partial, stop, it};
+                              (const float4 *)aux2, 4.0 - rho, sigma, partial, stop, it};
         switch (epi) {
         case EPI_HOP: launch_stencil_t<float4, float2, EPI_HOP>(c, a, c.U32, nf, prec, true); break;
         case EPI_K: launch_stencil_t<float4, float2, EPI_K>(c, a, c.U32, nf, prec, true); break;
@@ -526,7 +545,8 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
         case EPI_KPLUS: launch_stencil_t<float4, float2, EPI_KPLUS>(c, a, c.U32, nf, prec, true); break;
         }
     } else {
-        StencilArgs<h8> a{c.g, (const h8 *)in, (h8 *)out, (const h8 *)aux, 4.0 - rho, sigma, partial, stop, it};
+        StencilArgs<h8> a{c.g,  (const h8 *)in, (h8 *)out,   (const h8 *)aux, (const h8 *)aux2, 4.0 - rho,
+                          sigma, partial, stop,  it};
         const __half2 *U = (const __half2 *)c.U16;
         switch (epi) {
         case EPI_HOP: launch_stencil_t<h8, __half2, EPI_HOP>(c, a, U, nf, prec, true); break;
@@ -539,9 +559,9 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
 
 // w = K t + s0 p with (p, w) partials per tile; returns the number of tiles.
 int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double rho, double s0, const void *p,
-                   double *partial, const int *stop, int it)
+                   const void *r, double *partial, const int *stop, int it)
 {
-    stencil(c, EPI_K2DOT, prec, t, w, nf, rho, s0, p, partial, stop, it);
+    stencil(c, EPI_K2DOT, prec, t, w, nf, rho, s0, p, partial, stop, it, r);
     const int key = (prec * 8 + EPI_K2DOT) * 64 + (nf < 63 ? nf : 63);
     const int v = c.tuned.count(key) ? c.tuned[key] : 1;
     return (int)stencil_tiles(c.g, v);
@@ -559,13 +579,14 @@ void launch_K(Context &c, double rho, const void *in, void *out, int nf, int pre
 
 // Algorithmic HBM bytes of one stencil launch per field (perfect neighbour
 // reuse, no index table): read in + links, write out, plus the extra own-site
-// reads of the epilogues that take a second input.
+// reads of the epilogues that take more inputs.
 double stencil_bytes(const Geom &g, int prec, int epi)
 {
     const double S = (double)field_bytes(g, prec);
     const double G = (double)g.V * 36 * (prec == OVL_F64 ? 16 : prec == OVL_F32 ? 8 : 4);
     double b = 2 * S + G;
-    if (epi == EPI_K2DOT || epi == EPI_KPLUS) b += S;
+    if (epi == EPI_KPLUS) b += S;
+    if (epi == EPI_K2DOT) b += 2 * S;   // p and r
     return b;
 }
 

@@ -95,6 +95,11 @@ struct h8 {
     uint4 v;
 };
 
+// The values a spinor takes once stored: identity for FP64 / FP32 storage; for
+// FP16 storage the per-site scaling and rounding of st_sp(h8).
+__device__ __forceinline__ void as_stored(const double2 *, cplx<double> *, int) {}
+__device__ __forceinline__ void as_stored(const float4 *, cplx<float> *, int) {}
+
 // Number of storage elements of one field per site (planes).
 template <typename ST> struct Planes;
 template <> struct Planes<double2> { static constexpr int n = 12; using R = double; };
@@ -117,6 +122,17 @@ __device__ __forceinline__ uint32_t f22h2(float a, float b)
 {
     __half2 h = __floats2half2_rn(a, b);
     return *reinterpret_cast<uint32_t *>(&h);
+}
+
+__device__ __forceinline__ void as_stored(const h8 *, cplx<float> *v, int n)
+{
+    float m = 0.f;
+    for (int c = 0; c < n; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    for (int c = 0; c < n; ++c) {
+        const float2 q = h2f2(f22h2(v[c].re * inv, v[c].im * inv));
+        v[c] = {q.x * m, q.y * m};
+    }
 }
 
 __device__ __forceinline__ void ld_sp(const h8 *__restrict__ p, int64_t V, int64_t s, cplx<float> v[12])

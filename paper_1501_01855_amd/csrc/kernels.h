@@ -7,7 +7,7 @@ namespace ovl {
 enum Epilogue {
     EPI_HOP = 0,    // out = H in
     EPI_K = 1,      // out = K in
-    EPI_K2DOT = 2,  // out = K in + sigma aux, partial[(aux, out)]
+    EPI_K2DOT = 2,  // out = K in + sigma aux; per tile (aux, out), Re (aux2, out), (out, out)
     EPI_KPLUS = 3   // out = K in + aux
 };
 
@@ -17,21 +17,23 @@ struct StencilArgs {
     const ST *in;
     ST *out;
     const ST *aux;
+    const ST *aux2;  // second own-site input (EPI_K2DOT)
     double diag;     // 4 - rho
     double sigma;
-    double *partial; // [nf][gridDim.x] (EPI_K2DOT)
+    double *partial; // [nf][3][gridDim.x] (EPI_K2DOT)
     const int *stop; // per-field: skip when it >= stop[f] (nullable)
     int it;
 };
 
-// w = K t + s0 p with the (p, w) partial of every tile in partial[f][tile];
-// returns the number of tiles of the launch (the variant may use two lanes
-// per site).
+// w = K t + s0 p with the partials (p, w), Re (r, w) and (w, w) of every tile
+// in partial[f][q][tile] (computed on w as stored); returns the number of
+// tiles of the launch (it depends on the launch variant).
 int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double rho, double s0, const void *p,
-                   double *partial, const int *stop, int it);
+                   const void *r, double *partial, const int *stop, int it);
 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
-             double sigma, const void *aux, double *partial, const int *stop = nullptr, int it = 0);
+             double sigma, const void *aux, double *partial, const int *stop = nullptr, int it = 0,
+             const void *aux2 = nullptr);
 double stencil_bytes(const Geom &g, int prec, int epi);
 // tiles (blocks per field) of stencil launch variant v; the largest over variants
 unsigned stencil_tiles(const Geom &g, int v);
@@ -47,6 +49,9 @@ void norm2_f64(Context &c, const double2 *x, int nf, std::vector<double> &out);
 void axpby_f64(Context &c, const cplx<double> *a, const double2 *x, const cplx<double> *b, double2 *y, int nf);
 // out[row] = sum_i partial[row][i], i < nblk (fixed order)
 void sum_partials(Context &c, const double *partial, int nblk, int rows, double *out);
+// the same sums written into host memory; waits for them and returns them
+// (valid until the next call)
+const double *sum_partials_host(Context &c, const double *partial, int nblk, int rows);
 // out = a A + b B + g C over nf whole fields (real coefficients; C nullable)
 void lincomb3_f64(Context &c, double a, const double2 *A, double b, const double2 *B, double g, const double2 *C,
                   double2 *out, int nf);

@@ -155,6 +155,7 @@ void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *eva
         converged = worst <= tol;
     }
     OVL_REQUIRE(converged, OVL_ERR_NOT_CONVERGED, "low-mode eigensolver did not reach its tolerance");
+    c.lowmodes_changed();
     if (c.low) {
         OVL_HIP(hipStreamSynchronize(c.stream));
         OVL_HIP(hipFree(c.low));

@@ -19,6 +19,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <cstring>
+
 #include "context.h"
 #include "fields.h"
 #include "kernels.h"
@@ -33,8 +35,23 @@ struct MscgFinal {
     int iters, breakdown, act_total, pad;
 };
 
+// Host memory the device writes (pinned, mapped): each field's final counts
+// and then its stop flag, once, when the field stops, so that polling needs no
+// copy commands in the stream.  The host presets the flags to "running"
+// before a call; every device store there is followed by a system-scope
+// fence.  Data flows only device -> host here: the accuracies travel as a
+// kernel argument and the constants by an ordinary copy.
+constexpr int MS_MAXF = 64;   // fields of one multi-shift solve
+struct MscgPinned {
+    int stop[MS_MAXF];
+    MscgFinal fin[MS_MAXF];
+};
+struct MscgEta {
+    double e2[MS_MAXF];   // eta_f^2 (0: skip field f)
+};
+
 __global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int nblk, MscgConst k,
-                            const double *eta2)
+                            MscgEta eta2, int *stop_h, MscgFinal *fin_h)
 {
     __shared__ double lds[4];
     const int f = blockIdx.x;
@@ -43,7 +60,7 @@ __global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int n
     MscgScal &s = S[f];   // parity 0
     s.rr = b2;
     // the freezing test uses eta_f^2 ||b||^2; eta_f <= 0 marks a field to skip
-    const double e2 = eta2[f];
+    const double e2 = eta2.e2[f];
     s.b2 = e2 > 0.0 ? e2 * b2 : 0.0;
     s.alpha_old = 1.0;
     s.beta_old = 0.0;
@@ -55,7 +72,14 @@ __global__ void k_mscg_init(MscgScal *S, int *stop, const double *partial, int n
         s.zeta_old[l] = 1.0;
         s.act[l] = b2 > 0.0 ? 1 : 0;
     }
-    stop[f] = (b2 > 0.0 && e2 > 0.0) ? 0x7fffffff : 0;
+    const int st0 = (b2 > 0.0 && e2 > 0.0) ? 0x7fffffff : 0;
+    stop[f] = st0;
+    if (st0 == 0) {   // nothing to iterate: report the field stopped (the host preset "running")
+        fin_h[f] = MscgFinal{0, 0, 0, 0};
+        __threadfence_system();
+        stop_h[f] = 0;
+        __threadfence_system();   // the stores are complete before the kernel is
+    }
 }
 
 template <typename ST>
@@ -76,51 +100,27 @@ __global__ __launch_bounds__(256) void k_norm2(const ST *__restrict__ x, int64_t
     if (threadIdx.x == 0) partial[(int64_t)f * gridDim.x + blockIdx.x] = t;
 }
 
-// r' = r - alpha w (r = src on the first iteration), alpha = rr/(p, w) from the
-// stencil's tile partials; ||r'||^2 per block.
-template <typename ST>
-__global__ __launch_bounds__(256) void k_mscg_rupdate(const ST *__restrict__ rin, ST *__restrict__ r,
-                                                      const ST *__restrict__ w, const MscgScal *S,
-                                                      const int *stop, int it, int64_t V,
-                                                      const double *pw_part, int pw_n, double *rr_part)
-{
-    using R = typename Planes<ST>::R;
-    const int f = blockIdx.y;
-    if (it >= stop[f]) return;
-    __shared__ double lds[4];
-    const int nf = gridDim.y;
-    const MscgScal &sc = S[(it & 1) * nf + f];
-    const double pw = block_allsum(pw_part + (int64_t)f * pw_n, pw_n, lds);
-    const double alpha_d = sc.rr / pw;
-    const R alpha = (pw > 0.0 && isfinite(alpha_d)) ? (R)alpha_d : R(0);
-    double d = 0.0;
-    const int64_t o = f * fstride<ST>(V);
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
-        cplx<R> a[12], b[12];
-        ld_sp(rin + o, V, s, a);
-        ld_sp(w + o, V, s, b);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            a[c] = a[c] - alpha * b[c];
-            d += (double)a[c].re * (double)a[c].re + (double)a[c].im * (double)a[c].im;
-        }
-        st_sp(r + o, V, s, a);
-    }
-    const double t = block_sum<256>(d, lds);
-    if (threadIdx.x == 0) rr_part[(int64_t)f * gridDim.x + blockIdx.x] = t;
-}
-
-// y += sum_l omega_l alpha_l p_l ; p_l = zeta_l' r + beta_l p_l over the active
-// shifts (on the first iteration every p_l is the source and y starts at zero).
-// With ALL, y holds one solution per shift, shift-major like p, and
-// x_l += omega_l alpha_l p_l (the caller passes omega_l = 1).
-// Every block derives the iteration's scalars; block 0 stores the next state.
+// One multi-shift CG step after the two stencils of the iteration:
+//   alpha = (r, r) / (p, w)      (p, w) from the stencil's tile partials;
+//                                (r, r) exact, from the previous step's blocks
+//   r' = r - alpha w             in place; exact ||r'||^2 per block for the next step
+//   beta = ||r'||^2 / (r, r)     with ||r'||^2 = (r, r) - 2 alpha Re (r, w)
+//                                + alpha^2 (w, w) (the stencil's other partials),
+//                                so that no step waits on a grid-wide sum of r'
+//   y += sum_l omega_l alpha_l p_l ; p_l = zeta_l' r' + beta_l p_l (active shifts)
+// On the first step every p_l is the source and y starts at zero.  With ALL,
+// y holds one solution per shift, shift-major like p, and x_l += omega_l
+// alpha_l p_l (the caller passes omega_l = 1).  Every block derives the
+// step's scalars from the same partial sums in the same order; block 0
+// stores the next state.
 template <typename ST, bool ALL>
-__global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, const ST *__restrict__ r,
+__global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, const ST *__restrict__ rin,
+                                                    ST *__restrict__ r, const ST *__restrict__ w,
                                                     ST *__restrict__ y, ST *__restrict__ p, MscgScal *S,
                                                     const MscgConst *kc, int *stop, MscgFinal *fin, int it,
-                                                    int64_t V, const double *pw_part, int pw_n,
-                                                    const double *rr_part, int rr_n)
+                                                    int64_t V, const double *part, int pw_n,
+                                                    const double *rr_in, double *rr_out, int rr_n,
+                                                    int *stop_h, MscgFinal *fin_h)
 {
     using R = typename Planes<ST>::R;
     const int f = blockIdx.y;
@@ -131,11 +131,15 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
     __shared__ int s_act[NZMAX];
     __shared__ int s_keep_any;
     const MscgScal &sc = S[(it & 1) * nf + f];
-    const double pw = block_allsum(pw_part + (int64_t)f * pw_n, pw_n, lds);
-    const double rr_new = block_allsum(rr_part + (int64_t)f * rr_n, rr_n, lds);
-    const double alpha = sc.rr / pw;
+    const double *pf = part + (int64_t)f * 3 * pw_n;
+    const double pw = block_allsum(pf, pw_n, lds);
+    const double rw = block_allsum(pf + pw_n, pw_n, lds);
+    const double ww = block_allsum(pf + 2 * pw_n, pw_n, lds);
+    const double rr = it == 0 ? sc.rr : block_allsum(rr_in + (int64_t)f * rr_n, rr_n, lds);
+    const double alpha = rr / pw;
+    const double rr_new = fmax(0.0, rr - 2.0 * alpha * rw + alpha * alpha * ww);
     const bool ok = pw > 0.0 && isfinite(alpha) && isfinite(rr_new);
-    const double beta = rr_new / sc.rr;
+    const double beta = rr_new / rr;
     const int nz = kc->nz;
     if (threadIdx.x == 0) s_keep_any = 0;
     __syncthreads();
@@ -176,15 +180,33 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
         nx.iters = sc.iters + 1;
         nx.breakdown = sc.breakdown || !ok;
         nx.act_total = sc.act_total + na;
-        fin[f] = MscgFinal{nx.iters, nx.breakdown, nx.act_total, 0};
-        if (!s_keep_any || nx.breakdown || nx.iters >= kc->maxiter) stop[f] = it + 1;
+        const MscgFinal fv{nx.iters, nx.breakdown, nx.act_total, 0};
+        fin[f] = fv;
+        if (!s_keep_any || nx.breakdown || nx.iters >= kc->maxiter) {
+            // host memory is written once per field and call, when it stops;
+            // the counts reach the host before the flag
+            fin_h[f] = fv;
+            __threadfence_system();
+            stop[f] = it + 1;
+            stop_h[f] = it + 1;
+            __threadfence_system();   // complete before the kernel is
+        }
     }
     if (!ok) return;
     const int64_t fo = f * fstride<ST>(V);
     const int64_t pstride = nf * fstride<ST>(V);   // shift-major: p[l][f]
+    const R ar = (R)alpha;
+    double rn = 0.0;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
         cplx<R> rv[12], yv[12], pv[12];
-        ld_sp(r + fo, V, s, rv);
+        ld_sp(rin + fo, V, s, rv);
+        ld_sp(w + fo, V, s, pv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rv[c] = rv[c] - ar * pv[c];
+        st_sp(r + fo, V, s, rv);
+        as_stored(r, rv, 12);   // continue with r' as stored
+#pragma unroll
+        for (int c = 0; c < 12; ++c) rn += (double)rv[c].re * (double)rv[c].re + (double)rv[c].im * (double)rv[c].im;
         if (it == 0) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) yv[c] = {R(0), R(0)};
@@ -220,11 +242,14 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
         }
         if constexpr (!ALL) st_sp(y + fo, V, s, yv);
     }
+    const double t = block_sum<256>(rn, lds);
+    if (threadIdx.x == 0) rr_out[(int64_t)f * gridDim.x + blockIdx.x] = t;
 }
 
-// ---- low-mode projection (basis FP64 packed [n][12][V], fields in ST)
+// ---- low-mode projection (basis [n] packed fields and the fields in the
+// storage type ST of the call; sums in FP64)
 template <typename ST>
-__global__ __launch_bounds__(256) void k_low_dots(const double2 *__restrict__ basis, int n,
+__global__ __launch_bounds__(256) void k_low_dots(const ST *__restrict__ basis, int n,
                                                   const ST *__restrict__ x, int64_t V, double *partial)
 {
     using R = typename Planes<ST>::R;
@@ -236,13 +261,13 @@ __global__ __launch_bounds__(256) void k_low_dots(const double2 *__restrict__ ba
     for (int j = 0; j < n; ++j) {
         double dr = 0.0, di = 0.0;
         if (s < V) {
-            cplx<double> b[12];
-            ld_sp(basis + (int64_t)j * 12 * V, V, s, b);
+            cplx<R> b[12];
+            ld_sp(basis + (int64_t)j * fstride<ST>(V), V, s, b);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const double xr = xv[c].re, xi = xv[c].im;
-                dr += b[c].re * xr + b[c].im * xi;
-                di += b[c].re * xi - b[c].im * xr;
+                const double xr = xv[c].re, xi = xv[c].im, br = b[c].re, bi = b[c].im;
+                dr += br * xr + bi * xi;
+                di += br * xi - bi * xr;
             }
         }
         const double tr = block_sum<256>(dr, lds);
@@ -263,7 +288,7 @@ __global__ void k_reduce_rows(const double *partial, int nblk, double *out)
 
 // x_perp = x - sum_j c_j v_j ; ex = sum_j sign(lambda_j) c_j v_j
 template <typename ST>
-__global__ __launch_bounds__(256) void k_low_project(const double2 *__restrict__ basis, int n,
+__global__ __launch_bounds__(256) void k_low_project(const ST *__restrict__ basis, int n,
                                                      const double *__restrict__ coef, const double *__restrict__ sgn,
                                                      const ST *__restrict__ x, ST *__restrict__ xp,
                                                      ST *__restrict__ ex, int64_t V)
@@ -283,11 +308,11 @@ __global__ __launch_bounds__(256) void k_low_project(const double2 *__restrict__
     for (int j = 0; j < n; ++j) {
         const cplx<double> cj = {coef[((int64_t)f * n + j) * 2], coef[((int64_t)f * n + j) * 2 + 1]};
         const double sj = sgn[j];
-        cplx<double> b[12];
-        ld_sp(basis + (int64_t)j * 12 * V, V, s, b);
+        cplx<R> b[12];
+        ld_sp(basis + (int64_t)j * fstride<ST>(V), V, s, b);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const cplx<double> t = cj * b[c];
+            const cplx<double> t = cj * cplx<double>{(double)b[c].re, (double)b[c].im};
             a[c] = a[c] - t;
             e[c] = e[c] + sj * t;
         }
@@ -338,30 +363,40 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     ST *y = all ? (ST *)xs : (ST *)c.buf("ms_y", FB * nf);
     ST *p = (ST *)c.buf("ms_p", FB * nf * nz);
     const int nl = c.n_low > 0 ? c.n_low : 1;
-    double *part = (double *)c.buf("ms_part", sizeof(double) * (size_t)std::max(nblk_max, nblk * 2 * nl) * nf);
-    double *rr_part = (double *)c.buf("ms_part2", sizeof(double) * (size_t)nupd * nf);
+    double *part = (double *)c.buf("ms_part", sizeof(double) * (size_t)std::max(3 * nblk_max, nblk * 2 * nl) * nf);
+    double *rr_part = (double *)c.buf("ms_part2", sizeof(double) * 2 * (size_t)nupd * nf);   // by step parity
     double *coef = (double *)c.buf("ms_coef", sizeof(double) * (size_t)nf * 2 * nl);
-    double *sgn = (double *)c.buf("ms_sgn", sizeof(double) * nl);
     MscgScal *S = (MscgScal *)c.buf("ms_scal", sizeof(MscgScal) * 2 * nf);
     MscgFinal *fin = (MscgFinal *)c.buf("ms_fin", sizeof(MscgFinal) * nf);
     int *stop = (int *)c.buf("ms_stop", sizeof(int) * nf);
     MscgConst *kdev = (MscgConst *)c.buf("ms_const", sizeof(MscgConst));
 
-    // 1. low-mode split: src = (1 - P) in, ex = sum sign(lambda) P in
+    // pinned staging: constants, accuracies, and two slots of polled flags
+    OVL_REQUIRE(nf <= MS_MAXF, OVL_ERR_ARG, "too many fields in one multi-shift solve");
+    if (!c.ms_pin) {
+        OVL_HIP(hipHostMalloc(&c.ms_pin, sizeof(MscgPinned), hipHostMallocMapped | hipHostMallocCoherent));
+        std::memset(c.ms_pin, 0, sizeof(MscgPinned));
+        for (auto &e : c.ms_ev) OVL_HIP(hipEventCreate(&e));
+    }
+    volatile MscgPinned &hp = *(volatile MscgPinned *)c.ms_pin;
+    MscgPinned *hpd = nullptr;   // the same memory, as the device addresses it
+    OVL_HIP(hipHostGetDevicePointer((void **)&hpd, c.ms_pin, 0));
+
+    // 1. low-mode split: src = (1 - P) in, ex = sum sign(lambda) P in, with the
+    //    basis stored like the fields (its rounding is that of the call)
     const bool low = c.n_low > 0 && !all;
     if (low) {
-        std::vector<double> sg(c.n_low);
-        for (int j = 0; j < c.n_low; ++j) sg[j] = c.low_evals[j] >= 0.0 ? 1.0 : -1.0;
-        OVL_HIP(hipMemcpyAsync(sgn, sg.data(), sizeof(double) * c.n_low, hipMemcpyHostToDevice, c.stream));
-        k_low_dots<ST><<<grid, 256, 0, c.stream>>>(c.low, c.n_low, (const ST *)in, V, part);
+        const ST *basis = (const ST *)c.low_basis(prec);
+        const double *sgn = c.low_signs();
+        k_low_dots<ST><<<grid, 256, 0, c.stream>>>(basis, c.n_low, (const ST *)in, V, part);
         k_reduce_rows<<<nf * c.n_low * 2, 256, 0, c.stream>>>(part, nblk, coef);
-        k_low_project<ST><<<grid, 256, 0, c.stream>>>(c.low, c.n_low, coef, sgn, (const ST *)in, src, ex, V);
+        k_low_project<ST><<<grid, 256, 0, c.stream>>>(basis, c.n_low, coef, sgn, (const ST *)in, src, ex, V);
     } else {
         OVL_HIP(hipMemcpyAsync(src, in, FB * nf, hipMemcpyDeviceToDevice, c.stream));
     }
     OVL_HIP(hipGetLastError());
 
-    // 2. constants and initial state
+    // 2. constants (uploaded when they change) and initial state
     MscgConst k{};
     k.nz = nz;
     k.maxiter = maxiter;
@@ -376,53 +411,65 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
         const double tl = all ? 1.0 : 2.0 * std::sqrt(z.sigma[l]) / (nz * z.omega[l]);
         k.tol2[l] = tl * tl;
     }
-    OVL_HIP(hipMemcpyAsync(kdev, &k, sizeof(MscgConst), hipMemcpyHostToDevice, c.stream));
+    const char *kb = reinterpret_cast<const char *>(&k);
+    if (c.ms_const_last.size() != sizeof(k) || std::memcmp(c.ms_const_last.data(), kb, sizeof(k)) != 0) {
+        // from pageable memory: the runtime stages the copy before returning
+        OVL_HIP(hipMemcpyAsync(kdev, &k, sizeof(MscgConst), hipMemcpyHostToDevice, c.stream));
+        c.ms_const_last.assign(kb, kb + sizeof(k));
+    }
     zero_fields(c, y, all ? nf * nz : nf, prec);   // stays zero for a zero source
     k_norm2<ST><<<grid, 256, 0, c.stream>>>(src, V, part);
-    double *eta2d = (double *)c.buf("ms_eta2", sizeof(double) * nf);
-    OVL_HIP(hipMemcpyAsync(eta2d, eta2.data(), sizeof(double) * nf, hipMemcpyHostToDevice, c.stream));
-    k_mscg_init<<<nf, 256, 0, c.stream>>>(S, stop, part, nblk, k, eta2d);
+    MscgEta ea{};
+    for (int f = 0; f < nf; ++f) {
+        ea.e2[f] = eta2[f];
+        hp.stop[f] = 0x7fffffff;   // "running" until a kernel writes the field's stop
+    }
+    k_mscg_init<<<nf, 256, 0, c.stream>>>(S, stop, part, nblk, k, ea, hpd->stop, hpd->fin);
     OVL_HIP(hipGetLastError());
 
-    // 3. iterations; poll the stop flags every CHUNK iterations, one chunk behind
-    const int CHUNK = 8;
-    int *hstop = (int *)c.host_stage(sizeof(int) * nf * 2);
-    hipEvent_t evs[2] = {c.event(), c.event()};
+    // 3. iterations; poll the stop flags every CHUNK iterations, one chunk
+    //    behind, so the queue never runs dry
+    const int CHUNK = 4;
     const size_t pst = FB * nf;   // bytes between shift vectors
     ST *pbase = (ST *)((char *)p + pst * base);
     int it = 0;
     int pending = -1;
-    bool finished = false;
-    while (!finished) {
+    bool done = false;
+    while (!done) {
         for (int j = 0; j < CHUNK; ++j, ++it) {
             const ST *pin = it == 0 ? src : pbase;
+            const ST *rin = it == 0 ? src : r;
             stencil(c, EPI_K, prec, pin, t, nf, rho, 0.0, nullptr, nullptr, stop, it);
-            const int ntile = stencil_k2_dot(c, prec, t, w, nf, rho, k.s0, pin, part, stop, it);
-            k_mscg_rupdate<ST><<<ugrid, 256, 0, c.stream>>>(it == 0 ? src : r, r, w, S, stop, it, V, part, ntile,
-                                                           rr_part);
+            const int ntile = stencil_k2_dot(c, prec, t, w, nf, rho, k.s0, pin, rin, part, stop, it);
+            double *rr_in = rr_part + (size_t)(it & 1) * nupd * nf;
+            double *rr_out = rr_part + (size_t)((it + 1) & 1) * nupd * nf;
             PendingEvent pe;
             if (c.prof) c.prof_begin(pe, KERN_SHIFT, prec, 0.0);
             const PendingEvent *ppe = c.prof ? &pe : nullptr;
             if (all)
-                launch_k(c.stream, ppe, k_mscg_shift<ST, true>, ugrid, dim3(256), 0, src, r, y, p, S, kdev, stop,
-                         fin, it, V, part, ntile, rr_part, (int)nupd);
+                launch_k(c.stream, ppe, k_mscg_shift<ST, true>, ugrid, dim3(256), 0, src, rin, r, w, y, p, S, kdev,
+                         stop, fin, it, V, part, ntile, rr_in, rr_out, (int)nupd, hpd->stop, hpd->fin);
             else
-                launch_k(c.stream, ppe, k_mscg_shift<ST, false>, ugrid, dim3(256), 0, src, r, y, p, S, kdev, stop,
-                         fin, it, V, part, ntile, rr_part, (int)nupd);
+                launch_k(c.stream, ppe, k_mscg_shift<ST, false>, ugrid, dim3(256), 0, src, rin, r, w, y, p, S, kdev,
+                         stop, fin, it, V, part, ntile, rr_in, rr_out, (int)nupd, hpd->stop, hpd->fin);
             if (c.prof) c.prof_end(pe);
             OVL_HIP(hipGetLastError());
         }
         const int slot = (it / CHUNK) & 1;
-        OVL_HIP(hipMemcpyAsync(hstop + slot * nf, stop, sizeof(int) * nf, hipMemcpyDeviceToHost, c.stream));
-        OVL_HIP(hipEventRecord(evs[slot], c.stream));
+        OVL_HIP(hipEventRecord(c.ms_ev[slot], c.stream));
         if (pending >= 0) {
-            OVL_HIP(hipEventSynchronize(evs[pending]));
-            bool all = true;
-            for (int f = 0; f < nf; ++f) all = all && hstop[pending * nf + f] != 0x7fffffff;
-            if (all) finished = true;
+            // chunk `pending` has completed, so its flags are in host memory
+            // (later chunks may have written newer ones: also valid)
+            OVL_HIP(hipEventSynchronize(c.ms_ev[pending]));
+            bool every = true;
+            for (int f = 0; f < nf; ++f) every = every && hp.stop[f] != 0x7fffffff;
+            if (every) done = true;
         }
         pending = slot;
-        if (it >= maxiter + 2 * CHUNK) finished = true;
+        if (!done && it >= maxiter + 2 * CHUNK) {   // cannot happen: the kernels stop at maxiter
+            OVL_HIP(hipEventSynchronize(c.ms_ev[slot]));
+            done = true;
+        }
     }
 
     // 4. s = K y + ex
@@ -434,12 +481,16 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     }
     OVL_HIP(hipGetLastError());
 
+    // every field has stopped: no kernel writes these any more
     std::vector<MscgFinal> hs(nf);
     std::vector<int> hstop_final(nf);
-    OVL_HIP(hipMemcpyAsync(hs.data(), fin, sizeof(MscgFinal) * nf, hipMemcpyDeviceToHost, c.stream));
-    OVL_HIP(hipMemcpyAsync(hstop_final.data(), stop, sizeof(int) * nf, hipMemcpyDeviceToHost, c.stream));
-    OVL_HIP(hipStreamSynchronize(c.stream));
-    c.prof_collect();
+    for (int f = 0; f < nf; ++f) {
+        hstop_final[f] = hp.stop[f];
+        hs[f].iters = hp.fin[f].iters;
+        hs[f].breakdown = hp.fin[f].breakdown;
+        hs[f].act_total = hp.fin[f].act_total;
+    }
+    if (c.prof) c.prof_collect();
     int64_t iters = 0, act_total = 0;
     bool brk = false, capped = false;
     for (int f = 0; f < nf; ++f) {
@@ -458,11 +509,12 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     c.last_field_iters.assign(nf, 0);
     for (int f = 0; f < nf; ++f)
         if (hstop_final[f] != 0) c.last_field_iters[f] = hs[f].iters;
-    // algorithmic bytes of the shift kernel: r, y in, y out, 2 per active shift
-    // (with every solution kept: r, and p_l, x_l in and out per active shift)
+    // algorithmic bytes of the shift kernel: r, w in, r out, y in, y out and 2
+    // per active shift (with every solution kept: r, w, r out, and p_l, x_l in
+    // and out per active shift)
     if (c.prof) {
         c.slots[KERN_SHIFT][prec].bytes +=
-            all ? (double)FB * (1.0 * iters + 4.0 * act_total) : (double)FB * (3.0 * iters + 2.0 * act_total);
+            all ? (double)FB * (3.0 * iters + 4.0 * act_total) : (double)FB * (5.0 * iters + 2.0 * act_total);
         // the two stencils of each executed iteration (K, then K with the
         // shift, the dot and an extra read of p)
         c.slots[KERN_STENCIL][prec].bytes +=

@@ -220,7 +220,6 @@ static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, do
     const int64_t n = 12 * c.g.V;
     const int nblk = 256;
     double *part = (double *)c.buf("s_part", sizeof(double) * nblk * nf);
-    double *res = (double *)c.buf("s_res", sizeof(double) * nf);
     const double zeta = 1.0;
 
     std::vector<SumrField> F(nf);
@@ -371,10 +370,8 @@ static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, do
         k_sumr_step<<<dim3(nblk, nf), 256, 0, c.stream>>>(k, x, p, om, qold, q, qt, u, n, part);
         OVL_HIP(hipGetLastError());
         // ||q|| monitoring (Sec. 2)
-        sum_partials(c, part, nblk, nf, res);
-        std::vector<double> qn2(nf);
-        OVL_HIP(hipMemcpyAsync(qn2.data(), res, sizeof(double) * nf, hipMemcpyDeviceToHost, c.stream));
-        OVL_HIP(hipStreamSynchronize(c.stream));
+        const double *hq = sum_partials_host(c, part, nblk, nf);
+        const std::vector<double> qn2(hq, hq + nf);
         for (int f = 0; f < nf; ++f) {
             if (!k.act[f]) continue;
             if (!std::isfinite(qn2[f])) throw Error{OVL_ERR_BREAKDOWN, "SUMR: non-finite basis vector"};
