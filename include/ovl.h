@@ -249,6 +249,17 @@ ovl_status ovl_profile_enable(ovl_context *ctx, int32_t on);
 ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int64_t *launches,
                             double *milliseconds, double *bytes);
 
+/* Execution options of a context (value 0 = off, 1 = on):
+ *   OVL_OPT_GRAPHS   (default off) the multi-shift CG replays a graph of four
+ *                    iterations per chunk after the first chunk (off: every
+ *                    kernel is launched on its own); results are identical.
+ *                    Off by default: on MI355X the replays were slower than
+ *                    direct launches for the 16^3x32 solve.
+ *   OVL_OPT_AUTOTUNE (default on) time the stencil launch variants on first
+ *                    use (off: a fixed variant). */
+enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2 };
+ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
+
 /* Stencil launch shapes.  The first launch of each (precision, epilogue,
  * field count) times the launch variants on the context's lattice and keeps
  * the fastest (variant 0/1: one lane per site, lexicographic tiles in plain

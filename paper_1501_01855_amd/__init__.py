@@ -19,6 +19,7 @@ F64, F32, HALF = 0, 1, 2
 SRC_POINT, SRC_GAUSS, SRC_Z2 = 0, 1, 2
 MAX_NZ = 64
 KERN_STENCIL, KERN_SHIFT = 0, 1
+OPT_GRAPHS, OPT_AUTOTUNE = 1, 2
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_NOMEM", -4: "ERR_NOT_CONVERGED",
           -5: "ERR_BREAKDOWN", -6: "ERR_UNSUPPORTED", -7: "ERR_STATE"}
@@ -77,7 +78,7 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_lowmodes_get", "ovl_sign_zolotarev_mscg", "ovl_overlap_apply",
            "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
-           "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set"]
+           "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option"]
 
 _lib = None
 
@@ -111,6 +112,7 @@ def lib():
         "ovl_overlap_adjoint": ([P, D, D, P, P, P, I32, D, I32, P, P, P], I32),
         "ovl_tuning_get": ([P, P, P, I32, P], I32),
         "ovl_tuning_set": ([P, P, P, I32], I32),
+        "ovl_set_option": ([P, I32, I32], I32),
         "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
         "ovl_profile_enable": ([P, I32], I32),
         "ovl_profile_read": ([P, I32, I32, P, P, P], I32),
@@ -338,6 +340,9 @@ class Context:
         return x0, dx0
 
     # -- profiling
+    def set_option(self, option, value):
+        _check(lib().ovl_set_option(self._h, int(option), int(bool(value))))
+
     def tuning(self):
         """The stencil launch variants chosen so far, {key: variant}."""
         n = ctypes.c_int32()

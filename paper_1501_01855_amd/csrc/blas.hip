@@ -60,7 +60,9 @@ const double *sum_partials_host(Context &c, const double *partial, int nblk, int
     const double *h = c.host_results(rows, &dev);
     k_sum_rows<<<rows, 256, 0, c.stream>>>(partial, nblk, dev);   // into host memory: no copy command
     OVL_HIP(hipGetLastError());
-    OVL_HIP(hipStreamSynchronize(c.stream));
+    if (!c.sync_ev) OVL_HIP(hipEventCreate(&c.sync_ev));
+    OVL_HIP(hipEventRecord(c.sync_ev, c.stream));
+    c.spin_wait(c.sync_ev);
     return h;
 }
 

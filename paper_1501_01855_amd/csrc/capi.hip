@@ -470,6 +470,20 @@ ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int6
     });
 }
 
+ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(value == 0 || value == 1, OVL_ERR_ARG, "option value must be 0 or 1");
+        if (option == OVL_OPT_GRAPHS)
+            ctx->use_graphs = value != 0;
+        else if (option == OVL_OPT_AUTOTUNE)
+            ctx->autotune = value;
+        else
+            throw Error{OVL_ERR_ARG, "unknown option"};
+    });
+}
+
 ovl_status ovl_tuning_get(ovl_context *ctx, int32_t *keys, int32_t *variants, int32_t cap, int32_t *n)
 {
     return guard([&] {

@@ -2,6 +2,8 @@
 // precision, the kernel low modes, workspace and profiling state.
 #pragma once
 #include <map>
+#include <tuple>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -33,6 +35,8 @@ struct EigSpace {
     double2 *P = nullptr, *DP = nullptr;
     std::vector<double> dn2;
 };
+
+struct GraphRec;
 
 struct Context {
     Geom g{};
@@ -89,6 +93,11 @@ struct Context {
 
     EigSpace eig;
 
+    // graphs of multi-shift CG chunks, by launch configuration
+    bool use_graphs = false;   // measured slower than direct launches (dependent-dispatch latency dominates)
+    GraphRec *rec = nullptr;
+    std::map<std::string, hipGraphExec_t> graphs;
+
     void *buf(const std::string &name, size_t bytes);
     void *counters();
     void *host_stage(size_t bytes);
@@ -96,6 +105,10 @@ struct Context {
     // mapped, coherent): host address, and the device address of the same
     // memory; valid until the next call (callers synchronise before reading)
     double *host_results(size_t n, double **dev);
+    // wait for an event by polling it (lower latency than a blocking wait;
+    // the waits here are tens of microseconds)
+    void spin_wait(hipEvent_t e);
+    hipEvent_t sync_ev = nullptr;   // marks the end of a reduction read back by the host
     double *hres = nullptr, *hres_dev = nullptr;
     size_t hres_n = 0;
     hipEvent_t event();
@@ -127,16 +140,47 @@ void pack_gauge(Context &c, const double *canon);
 void launch_hop(Context &c, const void *in, void *out, int nf, int prec);
 void launch_K(Context &c, double rho, const void *in, void *out, int nf, int prec);
 
-// Launch a kernel on stream; with pe (profiling), its events time the
-// dispatch itself.
+// A graph being built from kernel nodes: while Context::rec is set,
+// launch_k() appends each kernel to it (after the previous node) instead of
+// launching it.
+struct GraphRec {
+    hipGraph_t g = nullptr;
+    hipGraphNode_t last = nullptr;
+};
+
+template <typename Tuple, size_t... I>
+inline void arg_ptrs(Tuple &t, void **p, std::index_sequence<I...>)
+{
+    ((p[I] = (void *)&std::get<I>(t)), ...);
+}
+
+// Launch a kernel on the context's stream; with pe (profiling), its events
+// time the dispatch itself; while a graph is being recorded, add it as a node.
 template <typename... KArgs, typename... Args>
-inline void launch_k(hipStream_t stream, const PendingEvent *pe, void (*k)(KArgs...), dim3 grid, dim3 block,
+inline void launch_k(Context &c, const PendingEvent *pe, void (*k)(KArgs...), dim3 grid, dim3 block,
                      uint32_t shmem, Args... args)
 {
+    if (c.rec) {
+        std::tuple<KArgs...> vals(static_cast<KArgs>(args)...);
+        void *ptrs[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+        arg_ptrs(vals, ptrs, std::index_sequence_for<KArgs...>{});
+        hipKernelNodeParams np{};
+        np.func = reinterpret_cast<void *>(k);
+        np.gridDim = grid;
+        np.blockDim = block;
+        np.sharedMemBytes = shmem;
+        np.kernelParams = ptrs;
+        np.extra = nullptr;
+        hipGraphNode_t node;
+        OVL_HIP(hipGraphAddKernelNode(&node, c.rec->g, c.rec->last ? &c.rec->last : nullptr, c.rec->last ? 1 : 0,
+                                      &np));
+        c.rec->last = node;
+        return;
+    }
     if (pe)
-        hipExtLaunchKernelGGL(k, grid, block, shmem, stream, pe->a, pe->b, 0, static_cast<KArgs>(args)...);
+        hipExtLaunchKernelGGL(k, grid, block, shmem, c.stream, pe->a, pe->b, 0, static_cast<KArgs>(args)...);
     else
-        hipLaunchKernelGGL(k, grid, block, shmem, stream, static_cast<KArgs>(args)...);
+        hipLaunchKernelGGL(k, grid, block, shmem, c.stream, static_cast<KArgs>(args)...);
 }
 
 }  // namespace ovl

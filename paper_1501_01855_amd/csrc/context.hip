@@ -63,6 +63,15 @@ double *Context::host_results(size_t n, double **dev)
     return hres;
 }
 
+void Context::spin_wait(hipEvent_t e)
+{
+    while (true) {
+        const hipError_t r = hipEventQuery(e);
+        if (r == hipSuccess) return;
+        if (r != hipErrorNotReady) OVL_HIP(r);
+    }
+}
+
 void *Context::host_stage(size_t bytes)
 {
     if (pinned_bytes < bytes) {
@@ -186,6 +195,8 @@ Context::~Context()
     if (ms_pin) hipHostFree(ms_pin);
     for (auto e : ms_ev)
         if (e) hipEventDestroy(e);
+    if (sync_ev) hipEventDestroy(sync_ev);
+    for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
     if (pinned) hipHostFree(pinned);
     if (hres) hipHostFree(hres);
     if (grid_counters) hipFree(grid_counters);

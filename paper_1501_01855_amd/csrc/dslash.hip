@@ -303,7 +303,8 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
     int32_t co[4];
     bool valid;
     site_of_thread<MAP, TPS>(a.g, tile, f, s, co, valid);
-    if (a.stop != nullptr && a.it >= a.stop[f]) return;   // field already converged
+    const int it = a.itb ? *a.itb + a.it : a.it;
+    if (a.stop != nullptr && it >= a.stop[f]) return;   // field already converged
     const int64_t V = a.g.V;
     const int half = TPS == 2 ? (int)(threadIdx.x >> 7) : 0;
     const ST *in = a.in + f * fstride<ST>(V);
@@ -445,7 +446,7 @@ static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, in
 {
     const int v = MAP == MAP_COL ? (TPS == 2 ? 5 : 4) : (TPS == 2 ? 2 : 0) + (MAP == MAP_REMAP ? 1 : 0);
     dim3 grid(stencil_tiles(c.g, v), nf);
-    launch_k(c.stream, pe, k_stencil<ST, GT, EPI, TPS, MAP>, grid, dim3(256), 0, a, U);
+    launch_k(c, pe, k_stencil<ST, GT, EPI, TPS, MAP>, grid, dim3(256), 0, a, U);
 }
 
 template <typename ST, typename GT, int EPI>
@@ -523,12 +524,13 @@ static void launch_stencil_t(Context &c, const StencilArgs<ST> &a, const GT *U, 
 }
 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
-             double sigma, const void *aux, double *partial, const int *stop, int it, const void *aux2)
+             double sigma, const void *aux, double *partial, const int *stop, int it, const void *aux2,
+             const int *itb)
 {
     OVL_REQUIRE(c.have_gauge, OVL_ERR_STATE, "no gauge field loaded");
     if (prec == OVL_F64) {
         StencilArgs<double2> a{c.g, (const double2 *)in, (double2 *)out, (const double2 *)aux,
-                               (const double2 *)aux2, 4.0 - rho, sigma, partial, stop, it};
+                               (const double2 *)aux2, 4.0 - rho, sigma, partial, stop, it, itb};
         switch (epi) {
         case EPI_HOP: launch_stencil_t<double2, double2, EPI_HOP>(c, a, c.U64, nf, prec, true); break;
         case EPI_K: launch_stencil_t<double2, double2, EPI_K>(c, a, c.U64, nf, prec, true); break;
@@ -537,7 +539,7 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
         }
     } else if (prec == OVL_F32) {
         StencilArgs<float4> a{c.g, (const float4 *)in, (float4 *)out, (const float4 *)aux,
-                              (const float4 *)aux2, 4.0 - rho, sigma, partial, stop, it};
+                              (const float4 *)aux2, 4.0 - rho, sigma, partial, stop, it, itb};
         switch (epi) {
         case EPI_HOP: launch_stencil_t<float4, float2, EPI_HOP>(c, a, c.U32, nf, prec, true); break;
         case EPI_K: launch_stencil_t<float4, float2, EPI_K>(c, a, c.U32, nf, prec, true); break;
@@ -545,8 +547,8 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
         case EPI_KPLUS: launch_stencil_t<float4, float2, EPI_KPLUS>(c, a, c.U32, nf, prec, true); break;
         }
     } else {
-        StencilArgs<h8> a{c.g,  (const h8 *)in, (h8 *)out,   (const h8 *)aux, (const h8 *)aux2, 4.0 - rho,
-                          sigma, partial, stop,  it};
+        StencilArgs<h8> a{c.g, (const h8 *)in, (h8 *)out, (const h8 *)aux, (const h8 *)aux2, 4.0 - rho,
+                          sigma, partial, stop, it, itb};
         const __half2 *U = (const __half2 *)c.U16;
         switch (epi) {
         case EPI_HOP: launch_stencil_t<h8, __half2, EPI_HOP>(c, a, U, nf, prec, true); break;
@@ -559,12 +561,19 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
 
 // w = K t + s0 p with (p, w) partials per tile; returns the number of tiles.
 int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double rho, double s0, const void *p,
-                   const void *r, double *partial, const int *stop, int it)
+                   const void *r, double *partial, const int *stop, int it, const int *itb)
 {
-    stencil(c, EPI_K2DOT, prec, t, w, nf, rho, s0, p, partial, stop, it, r);
+    stencil(c, EPI_K2DOT, prec, t, w, nf, rho, s0, p, partial, stop, it, r, itb);
     const int key = (prec * 8 + EPI_K2DOT) * 64 + (nf < 63 ? nf : 63);
     const int v = c.tuned.count(key) ? c.tuned[key] : 1;
     return (int)stencil_tiles(c.g, v);
+}
+
+int stencil_variant(Context &c, int epi, int prec, int nf)
+{
+    const int key = (prec * 8 + epi) * 64 + (nf < 63 ? nf : 63);
+    const auto it = c.tuned.find(key);
+    return it == c.tuned.end() ? -1 : it->second;
 }
 
 void launch_hop(Context &c, const void *in, void *out, int nf, int prec)

@@ -22,19 +22,24 @@ struct StencilArgs {
     double sigma;
     double *partial; // [nf][3][gridDim.x] (EPI_K2DOT)
     const int *stop; // per-field: skip when it >= stop[f] (nullable)
-    int it;
+    int it;          // iteration, or its offset from *itb when itb is set
+    const int *itb = nullptr;   // device iteration base (graph replays)
 };
 
 // w = K t + s0 p with the partials (p, w), Re (r, w) and (w, w) of every tile
 // in partial[f][q][tile] (computed on w as stored); returns the number of
 // tiles of the launch (it depends on the launch variant).
+// itb (nullable): the iteration is *itb + it, read on the device (so that a
+// recorded graph can be replayed for later iterations).
 int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double rho, double s0, const void *p,
-                   const void *r, double *partial, const int *stop, int it);
+                   const void *r, double *partial, const int *stop, int it, const int *itb = nullptr);
 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
              double sigma, const void *aux, double *partial, const int *stop = nullptr, int it = 0,
-             const void *aux2 = nullptr);
+             const void *aux2 = nullptr, const int *itb = nullptr);
 double stencil_bytes(const Geom &g, int prec, int epi);
+// the launch variant for (prec, epi, nf), autotuned on first use
+int stencil_variant(Context &c, int epi, int prec, int nf);
 // tiles (blocks per field) of stencil launch variant v; the largest over variants
 unsigned stencil_tiles(const Geom &g, int v);
 int64_t stencil_tiles_max(const Geom &g);

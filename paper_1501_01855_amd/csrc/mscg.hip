@@ -20,6 +20,8 @@
 #include <cmath>
 
 #include <cstring>
+#include <initializer_list>
+#include <string>
 
 #include "context.h"
 #include "fields.h"
@@ -117,15 +119,19 @@ template <typename ST, bool ALL>
 __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, const ST *__restrict__ rin,
                                                     ST *__restrict__ r, const ST *__restrict__ w,
                                                     ST *__restrict__ y, ST *__restrict__ p, MscgScal *S,
-                                                    const MscgConst *kc, int *stop, MscgFinal *fin, int it,
-                                                    int64_t V, const double *part, int pw_n,
-                                                    const double *rr_in, double *rr_out, int rr_n,
-                                                    int *stop_h, MscgFinal *fin_h)
+                                                    const MscgConst *kc, int *stop, MscgFinal *fin,
+                                                    const int *itb, int itj, int64_t V, const double *part,
+                                                    int pw_n, double *rr_part, int rr_n, int *stop_h,
+                                                    MscgFinal *fin_h)
 {
     using R = typename Planes<ST>::R;
     const int f = blockIdx.y;
+    const int it = itb ? *itb + itj : itj;   // the iteration (device base for graph replays)
     if (it >= stop[f]) return;
     const int nf = gridDim.y;
+    // exact ||r||^2 partials by iteration parity: read this step's, write the next's
+    const double *rr_in = rr_part + (size_t)(it & 1) * rr_n * nf;
+    double *rr_out = rr_part + (size_t)((it + 1) & 1) * rr_n * nf;
     __shared__ double lds[4];
     __shared__ double s_cy[NZMAX], s_zn[NZMAX], s_bl[NZMAX];
     __shared__ int s_act[NZMAX];
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
     double rn = 0.0;
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
         cplx<R> rv[12], yv[12], pv[12];
-        ld_sp(rin + fo, V, s, rv);
+        ld_sp((it == 0 ? src : rin) + fo, V, s, rv);
         ld_sp(w + fo, V, s, pv);
 #pragma unroll
         for (int c = 0; c < 12; ++c) rv[c] = rv[c] - ar * pv[c];
@@ -244,6 +250,16 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
     }
     const double t = block_sum<256>(rn, lds);
     if (threadIdx.x == 0) rr_out[(int64_t)f * gridDim.x + blockIdx.x] = t;
+}
+
+// Iteration base of graph replays: set, then advanced after each chunk.
+__global__ void k_set_it(int *itb, int v)
+{
+    if (threadIdx.x == 0) *itb = v;
+}
+__global__ void k_advance(int *itb, int n)
+{
+    if (threadIdx.x == 0) *itb += n;
 }
 
 // ---- low-mode projection (basis [n] packed fields and the fields in the
@@ -328,6 +344,45 @@ __global__ __launch_bounds__(256) void k_low_project(const ST *__restrict__ basi
 }
 
 // --------------------------------------------------------------- host driver
+// The graph of one chunk of multi-shift iterations (kernel nodes in launch
+// order, then the advance of the iteration base), recorded once per launch
+// configuration: buffers, constants that are passed by value, the stencil
+// launch variants and the field count.  record(j) issues iteration j of the
+// chunk through launch_k().
+template <typename F>
+static hipGraphExec_t chunk_graph(Context &c, int prec, int nf, bool all, int chunk, int *itb, F record,
+                                  std::initializer_list<const void *> ptrs, std::initializer_list<double> vals)
+{
+    std::string key;
+    auto put = [&](const void *d, size_t n) { key.append(reinterpret_cast<const char *>(d), n); };
+    const int head[6] = {prec, nf, all ? 1 : 0, chunk, stencil_variant(c, EPI_K, prec, nf),
+                         stencil_variant(c, EPI_K2DOT, prec, nf)};
+    put(head, sizeof(head));
+    for (const void *q : ptrs) put(&q, sizeof(q));
+    for (double v : vals) put(&v, sizeof(v));
+    put(&itb, sizeof(itb));
+    auto found = c.graphs.find(key);
+    if (found != c.graphs.end()) return found->second;
+    GraphRec gr;
+    OVL_HIP(hipGraphCreate(&gr.g, 0));
+    c.rec = &gr;
+    try {
+        for (int j = 0; j < chunk; ++j) record(j);
+        launch_k(c, nullptr, k_advance, dim3(1), dim3(64), 0, itb, chunk);
+    } catch (...) {
+        c.rec = nullptr;
+        hipGraphDestroy(gr.g);
+        throw;
+    }
+    c.rec = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, gr.g, nullptr, nullptr, 0);
+    hipGraphDestroy(gr.g);
+    OVL_HIP(e);
+    c.graphs[key] = exec;
+    return exec;
+}
+
 // out = sign(K) in, or (xs != nullptr) every shifted solution
 // xs[l][f] = (K^2 + sigma_l)^{-1} in_f, each to |zeta_l| ||r|| <= eta_f ||in_f||,
 // with no low-mode split and no final K.
@@ -428,39 +483,57 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     OVL_HIP(hipGetLastError());
 
     // 3. iterations; poll the stop flags every CHUNK iterations, one chunk
-    //    behind, so the queue never runs dry
+    //    behind, so the queue never runs dry.  The first chunk is launched
+    //    directly (it also settles the stencil launch variants); later chunks
+    //    replay a graph of CHUNK iterations whose kernels read the iteration
+    //    from *itb, unless profiling (per-launch events) is on.
     const int CHUNK = 4;
     const size_t pst = FB * nf;   // bytes between shift vectors
     ST *pbase = (ST *)((char *)p + pst * base);
+    int *itb = (int *)c.buf("ms_itb", sizeof(int));
+    auto one_iter = [&](int j, const int *ib) {   // iteration *ib + j (ib null: iteration j)
+        const bool zero = ib == nullptr && j == 0;
+        const ST *pin = zero ? src : pbase;
+        const ST *rin = zero ? src : r;
+        stencil(c, EPI_K, prec, pin, t, nf, rho, 0.0, nullptr, nullptr, stop, j, nullptr, ib);
+        const int ntile = stencil_k2_dot(c, prec, t, w, nf, rho, k.s0, pin, rin, part, stop, j, ib);
+        PendingEvent pe;
+        if (c.prof) c.prof_begin(pe, KERN_SHIFT, prec, 0.0);
+        const PendingEvent *ppe = c.prof ? &pe : nullptr;
+        if (all)
+            launch_k(c, ppe, k_mscg_shift<ST, true>, ugrid, dim3(256), 0, src, rin, r, w, y, p, S, kdev, stop, fin,
+                     ib, j, V, part, ntile, rr_part, (int)nupd, hpd->stop, hpd->fin);
+        else
+            launch_k(c, ppe, k_mscg_shift<ST, false>, ugrid, dim3(256), 0, src, rin, r, w, y, p, S, kdev, stop, fin,
+                     ib, j, V, part, ntile, rr_part, (int)nupd, hpd->stop, hpd->fin);
+        if (c.prof) c.prof_end(pe);
+        OVL_HIP(hipGetLastError());
+    };
+    hipGraphExec_t gexec = nullptr;
     int it = 0;
     int pending = -1;
     bool done = false;
     while (!done) {
-        for (int j = 0; j < CHUNK; ++j, ++it) {
-            const ST *pin = it == 0 ? src : pbase;
-            const ST *rin = it == 0 ? src : r;
-            stencil(c, EPI_K, prec, pin, t, nf, rho, 0.0, nullptr, nullptr, stop, it);
-            const int ntile = stencil_k2_dot(c, prec, t, w, nf, rho, k.s0, pin, rin, part, stop, it);
-            double *rr_in = rr_part + (size_t)(it & 1) * nupd * nf;
-            double *rr_out = rr_part + (size_t)((it + 1) & 1) * nupd * nf;
-            PendingEvent pe;
-            if (c.prof) c.prof_begin(pe, KERN_SHIFT, prec, 0.0);
-            const PendingEvent *ppe = c.prof ? &pe : nullptr;
-            if (all)
-                launch_k(c.stream, ppe, k_mscg_shift<ST, true>, ugrid, dim3(256), 0, src, rin, r, w, y, p, S, kdev,
-                         stop, fin, it, V, part, ntile, rr_in, rr_out, (int)nupd, hpd->stop, hpd->fin);
-            else
-                launch_k(c.stream, ppe, k_mscg_shift<ST, false>, ugrid, dim3(256), 0, src, rin, r, w, y, p, S, kdev,
-                         stop, fin, it, V, part, ntile, rr_in, rr_out, (int)nupd, hpd->stop, hpd->fin);
-            if (c.prof) c.prof_end(pe);
-            OVL_HIP(hipGetLastError());
+        if (it == 0 || c.prof || !c.use_graphs) {
+            for (int j = 0; j < CHUNK; ++j) one_iter(it + j, nullptr);
+        } else {
+            if (!gexec) gexec = chunk_graph(c, prec, nf, all, CHUNK, itb, [&](int j) { one_iter(j, itb); },
+                                            {src, r, t, w, y, p, S, kdev, stop, fin, part, rr_part, hpd,
+                                             (const void *)(intptr_t)base, (const void *)(intptr_t)nupd},
+                                            {rho, k.s0});
+            if (it == CHUNK) {
+                k_set_it<<<1, 64, 0, c.stream>>>(itb, it);
+                OVL_HIP(hipGetLastError());
+            }
+            OVL_HIP(hipGraphLaunch(gexec, c.stream));
         }
+        it += CHUNK;
         const int slot = (it / CHUNK) & 1;
         OVL_HIP(hipEventRecord(c.ms_ev[slot], c.stream));
         if (pending >= 0) {
             // chunk `pending` has completed, so its flags are in host memory
             // (later chunks may have written newer ones: also valid)
-            OVL_HIP(hipEventSynchronize(c.ms_ev[pending]));
+            c.spin_wait(c.ms_ev[pending]);
             bool every = true;
             for (int f = 0; f < nf; ++f) every = every && hp.stop[f] != 0x7fffffff;
             if (every) done = true;

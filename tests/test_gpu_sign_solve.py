@@ -145,3 +145,43 @@ def test_solve_c1_half_ladder(c1):
     assert norm(b - D(to_host(x), 1e-15)) / norm(b) <= 1e-10
     assert st[0].sign_calls[2] > 0
     print("half ladder stats", st[0].as_dict())
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_graph_replay_identical(c1, prec):
+    """The multi-shift CG replays graphs of four iterations after the first
+    chunk; with graphs off every kernel is launched on its own.  Same kernels,
+    same order, fixed-order reductions: bitwise the same result and count."""
+    ovl = require_gpu()
+    eta = {0: 1e-12, 1: 1e-6, 2: 1e-2}[prec]
+    psi = to_dev(synth.gaussian_source(c1.dims, 27))
+    out = []
+    for graphs in (True, False, True):
+        ctx, zg = _ctx(ovl, c1)
+        ctx.set_option(ovl.OPT_AUTOTUNE, 0)   # one launch variant: the same tile sums everywhere
+        ctx.set_option(ovl.OPT_GRAPHS, graphs)
+        s, st = ctx.sign(psi, 1.4, zg, eta, prec=prec)
+        s2, st2 = ctx.sign(psi, 1.4, zg, eta, prec=prec)   # a second call replays the cached graph
+        out.append((to_host(s), st.mscg_iters, to_host(s2)))
+        ctx.close()
+    for s, n, s2 in out[1:]:
+        assert n == out[0][1]
+        assert np.array_equal(s, out[0][0]) and np.array_equal(s2, out[0][0])
+
+
+def test_solve_graphs_off_matches(c1):
+    """A whole mixed-precision solve with and without graphs: same iterate."""
+    ovl = require_gpu()
+    b = to_dev(synth.gaussian_source(c1.dims, 28))
+    p = ovl.solver_defaults(rho=1.4, mu=0.05, tol=1e-10, eta_tilde=1e-3, f32_threshold=1e-6,
+                            half_threshold=3e-3)
+    xs = []
+    for graphs in (True, False):
+        ctx, zg = _ctx(ovl, c1)
+        ctx.set_option(ovl.OPT_AUTOTUNE, 0)
+        ctx.set_option(ovl.OPT_GRAPHS, graphs)
+        x, st, code = ctx.solve(b, zg, p)
+        assert code == 0
+        xs.append((to_host(x), st[0].mscg_iters))
+        ctx.close()
+    assert xs[0][1] == xs[1][1] and np.array_equal(xs[0][0], xs[1][0])
