@@ -12,6 +12,8 @@ is timed beside it.
 
 Beside the headline (not part of it):
 * the same solver on twelve spin-colour point sources in one batched call;
+* twenty-four independent lattice instances of four sizes solved together
+  (one context and stream each) and one after another;
 * the adjoint (dS/dpsi and dS/dU of S = Re(chi^H D psi)) on 8^3 x 16 in FP64
   and on 32^3 x 64 in FP32;
 * the Wilson stencil alone on 32^3 x 64 (working set beyond the 256 MB
@@ -205,6 +207,52 @@ def batch12(torch, ovl, ctx, zolo):
             "sumr_iters_per_field": [s.sumr_iters for s in st]}
 
 
+def uneven_leg(torch, ovl):
+    """Twenty-four independent instances, six each of 8^4, 8^3x16, 12^3x24 and
+    16^4 (links exp(i eps A), eps uniform in [0.2, 0.35] from seed 4, gauge seed
+    400 + i), Z2 sources (seed 104 + i), mu = 0.03, N_Z = 20 with 10 exact kernel
+    modes, mixed precision, 1e-10: solved together (one context and stream
+    each) and, for comparison, one after another."""
+    import numpy as np
+    eps = np.random.default_rng(4).uniform(0.2, 0.35, 24)
+    sizes = [(8, 8, 8, 8), (8, 8, 8, 16), (12, 12, 12, 24), (16, 16, 16, 16)]
+    t0 = time.perf_counter()
+    items = []
+    for i in range(24):
+        dims = sizes[i // 6]
+        ctx = ovl.Context(dims, stream=torch.cuda.Stream())
+        ctx.gauge_generate(400 + i, float(eps[i]))
+        ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)
+        zolo = ovl.zolotarev_coeffs(NZ, max(abs(e) for e in ev), lmax)
+        items.append((ctx, zolo, ctx.source(ovl.SRC_Z2, seed=104 + i)))
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    p = ovl.solver_defaults(rho=RHO, mu=0.03, tol=TOL, eta_tilde=1e-3, relax_floor=1e-2, f32_threshold=1e-6,
+                            half_threshold=3e-3, max_outer=16, max_middle=4000, max_mscg=20000)
+    ovl.solve_many(items, p)   # warm-up (autotuning, workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ovl.solve_many(items, p)
+    torch.cuda.synchronize()
+    together = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for ctx, zolo, b in items:
+        ctx.solve(b, zolo, p)
+    torch.cuda.synchronize()
+    alone = time.perf_counter() - t0
+    worst = 0.0
+    for (ctx, zolo, b), (x, st, code) in zip(items, res):
+        Dx, _ = ctx.overlap(x, RHO, 0.03, zolo, 1e-13)
+        worst = max(worst, float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b)))
+    for ctx, _, _ in items:
+        ctx.close()
+    return {"instances": "6 each of 8^4, 8^3x16, 12^3x24, 16^4", "setup_s": setup,
+            "together_s": together, "solves_per_s_together": 24 / together,
+            "one_after_another_s": alone, "solves_per_s_one_after_another": 24 / alone,
+            "speedup": alone / together, "max_true_relres": worst,
+            "status": [r[2] for r in res]}
+
+
 def adjoint_leg(torch, ovl):
     """dS/dpsi and dS/dU for S = Re(chi^H D psi), N_Z = 20, no exactly treated
     modes: 8^3 x 16 in FP64 (eta 1e-10) and 32^3 x 64 in FP32 (eta 1e-6)."""
@@ -357,6 +405,8 @@ def main():
         print("[bench] batch of 12 done", file=sys.stderr, flush=True)
     ctx.close()
     if not args.no_extras:
+        out["uneven_instances"] = uneven_leg(torch, ovl)
+        print("[bench] uneven instances done", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_leg(torch, ovl)
         print("[bench] adjoint done", file=sys.stderr, flush=True)
         out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)

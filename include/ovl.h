@@ -214,6 +214,25 @@ ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo,
                                  const ovl_solver_params *params, const double *b_dev,
                                  double *x_dev, int32_t nrhs, ovl_stats *stats_host);
 
+/* Several independent solves at once: lattice instances of any sizes, each
+ * with its own context (and so its own stream, gauge field, low modes and
+ * workspace).  One host thread drives each instance, so the GPU runs the
+ * instances' kernels side by side (small lattices alone cannot fill it).
+ * Contexts must be distinct, and their streams should be distinct for the
+ * work to overlap.  params apply to every instance.  inst[i].status receives
+ * each solve's status; the return value is the first failure in index order
+ * (OVL_OK if none).  Blocks until every solve has finished. */
+typedef struct {
+    ovl_context *ctx;
+    const ovl_zolo *zolo;
+    const double *b_dev;   /* canonical, nrhs fields */
+    double *x_dev;         /* canonical, overwritten */
+    int32_t nrhs;
+    ovl_stats *stats;      /* nrhs entries, may be null */
+    int32_t status;        /* out */
+} ovl_instance;
+ovl_status ovl_sumr_gmresr_solve_many(ovl_instance *inst, int32_t n, const ovl_solver_params *params);
+
 /* ---- eigenspace (eigSUMR basis; Secs. 4-5) ------------------------------ */
 
 /* Number of vectors held (n after a diagonalisation), their Ritz values

@@ -78,7 +78,8 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_lowmodes_get", "ovl_sign_zolotarev_mscg", "ovl_overlap_apply",
            "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
-           "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option"]
+           "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option",
+           "ovl_sumr_gmresr_solve_many"]
 
 _lib = None
 
@@ -113,6 +114,7 @@ def lib():
         "ovl_tuning_get": ([P, P, P, I32, P], I32),
         "ovl_tuning_set": ([P, P, P, I32], I32),
         "ovl_set_option": ([P, I32, I32], I32),
+        "ovl_sumr_gmresr_solve_many": ([P, I32, P], I32),
         "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
         "ovl_profile_enable": ([P, I32], I32),
         "ovl_profile_read": ([P, I32, I32, P, P, P], I32),
@@ -368,6 +370,31 @@ class Context:
         _check(lib().ovl_profile_read(self._h, int(kernel), int(prec), ctypes.byref(n),
                                       ctypes.byref(ms), ctypes.byref(by)))
         return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("zolo", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("nrhs", ctypes.c_int32), ("stats", ctypes.c_void_p),
+                ("status", ctypes.c_int32)]
+
+
+def solve_many(items, params):
+    """Solve several instances at once: items = [(ctx, zolo, b), ...] with
+    distinct contexts (give each its own stream for the work to overlap).
+    Returns [(x, [Stats], status), ...]."""
+    n = len(items)
+    arr = (Instance * n)()
+    keep = []
+    for i, (ctx, zolo, b) in enumerate(items):
+        nrhs = ctx._nrhs(b)
+        x = torch.empty_like(b)
+        st = (Stats * nrhs)()
+        keep.append((x, st))
+        arr[i] = Instance(ctx._h.value if hasattr(ctx._h, "value") else ctx._h, ctypes.addressof(zolo),
+                          _dev(b, (ctx.V, 4, 3), "b").value, _dev(x, (ctx.V, 4, 3), "x").value, nrhs,
+                          ctypes.addressof(st), 0)
+    _check(lib().ovl_sumr_gmresr_solve_many(arr, n, ctypes.byref(params)), allow=(-4,))
+    return [(keep[i][0], list(keep[i][1]), arr[i].status) for i in range(n)]
 
 
 class OverlapFunction(torch.autograd.Function):

@@ -5,6 +5,9 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "context.h"
 #include "kernels.h"
@@ -468,6 +471,37 @@ ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int6
         if (milliseconds) *milliseconds = s.ms;
         if (bytes) *bytes = s.bytes;
     });
+}
+
+ovl_status ovl_sumr_gmresr_solve_many(ovl_instance *inst, int32_t n, const ovl_solver_params *params)
+{
+    ovl_status st = guard([&] {
+        OVL_REQUIRE(inst != nullptr && n >= 1 && n <= 4096 && params != nullptr, OVL_ERR_ARG,
+                    "bad instance list");
+        std::vector<ovl_context *> seen;
+        for (int i = 0; i < n; ++i) {
+            OVL_REQUIRE(inst[i].ctx != nullptr, OVL_ERR_ARG, "null context in the instance list");
+            seen.push_back(inst[i].ctx);
+        }
+        std::sort(seen.begin(), seen.end());
+        OVL_REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), OVL_ERR_ARG,
+                    "an instance list may hold each context once");
+    });
+    if (st != OVL_OK) return st;
+    std::vector<std::thread> pool;
+    pool.reserve(n);
+    for (int i = 0; i < n; ++i)
+        pool.emplace_back([i, inst, params] {
+            ovl_instance &q = inst[i];
+            q.status = ovl_sumr_gmresr_solve(q.ctx, q.zolo, params, q.b_dev, q.x_dev, q.nrhs, q.stats);
+        });
+    for (auto &t : pool) t.join();
+    for (int i = 0; i < n; ++i)
+        if (inst[i].status != OVL_OK) {
+            set_error("instance " + std::to_string(i) + " failed (status " + std::to_string(inst[i].status) + ")");
+            return (ovl_status)inst[i].status;
+        }
+    return OVL_OK;
 }
 
 ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value)

@@ -112,3 +112,44 @@ def test_batch_limit(setup):
     p = ovl.solver_defaults(rho=RHO, mu=MU)
     with pytest.raises(ovl.OvlError):
         ctx.solve(to_dev(B), zg, p)
+
+
+def test_solve_many_uneven():
+    """Independent lattice instances of different sizes solved at once (one
+    context and stream each): every solution has a true residual <= 1e-10
+    with the oracle's D, and equals the same instance solved alone."""
+    ovl = require_gpu()
+    import torch
+    mu = 0.03
+    z = Zolotarev(16, 0.2, 8.0 - RHO)
+    specs = [((4, 4, 4, 4), 21, 0.25), ((4, 4, 4, 8), 22, 0.3), ((6, 4, 4, 8), 23, 0.2),
+             ((4, 4, 4, 4), 24, 0.35), ((8, 4, 4, 4), 25, 0.3)]
+    items, oracles = [], []
+    for i, (dims, seed, eps) in enumerate(specs):
+        U = synth.gauge_field(dims, seed, eps)
+        ctx = ovl.Context(dims, stream=torch.cuda.Stream())
+        ctx.gauge_load(to_dev(U))
+        b = synth.z2_source(dims, 104 + i)
+        zg = ovl.zolo_from(z.nz, z.a, z.b, z.delta, z.omega, z.sigma)
+        items.append((ctx, zg, to_dev(b)))
+        oracles.append((krylov.Overlap(krylov.SignFunction(WilsonKernel(dims, U, RHO), z), mu), b))
+    p = ovl.solver_defaults(rho=RHO, mu=mu, tol=1e-10, eta_tilde=1e-3, f32_threshold=1e-6, half_threshold=3e-3)
+    res = ovl.solve_many(items, p)
+    torch.cuda.synchronize()
+    for (ctx, zg, bd), (x, st, code), (D, b) in zip(items, res, oracles):
+        assert code == 0
+        xh = to_host(x)
+        assert norm(b - D(xh, 1e-15)) / norm(b) <= 1e-10
+        x1, _, code1 = ctx.solve(bd, zg, p)
+        assert code1 == 0 and np.array_equal(to_host(x1), xh)
+    for ctx, _, _ in items:
+        ctx.close()
+
+
+def test_solve_many_rejects_repeated_context(setup):
+    ovl = require_gpu()
+    U, z, _, _ = setup
+    ctx, zg = _ctx(ovl, U, z)
+    b = to_dev(synth.z2_source(DIMS, 9))
+    with pytest.raises(ovl.OvlError):
+        ovl.solve_many([(ctx, zg, b), (ctx, zg, b)], ovl.solver_defaults(rho=RHO, mu=MU))
