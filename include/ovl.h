@@ -284,7 +284,10 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
  * the fastest (variant 0/1: one lane per site, lexicographic tiles in plain
  * or XCD-contiguous order; 2/3: two lanes per site, likewise; 4/5: one / two
  * lanes per site, each XCD walking one of eight xyz columns through t, when
- * the x, y, z extents split into 8 columns; FP16 storage: 0, 1, 4).
+ * the x, y, z extents split into 8 columns; 6/7: one / two lanes per xyz site,
+ * each lane walking Lt/8 consecutive time slices with the time hops kept in
+ * registers, one t chunk per XCD, when Lt is a multiple of 8; FP16 storage:
+ * 0, 1, 4, 6).
  * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the
  * number held; ovl_tuning_set installs pairs (variants out of range are an
  * argument error), so a run can reuse another run's choices. */

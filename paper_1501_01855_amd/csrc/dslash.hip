@@ -293,11 +293,116 @@ __device__ __forceinline__ void site_of_thread(const Geom &g, unsigned &tile, un
     }
 }
 
+// With two lanes per site: half h keeps components [6h, 6h+6) of the sum and
+// receives the partner's (own half in acc[0..6) afterwards).  Every thread of
+// the block must call it.  REUSE: another exchange follows in the same kernel
+// (wait until every partner has read).
+template <bool REUSE, typename R>
+__device__ __forceinline__ void exchange_halves(cplx<R> acc[12], int half)
+{
+    __shared__ cplx<R> xch[2][6][128];
+    const int lane = threadIdx.x & 127;
+    const bool hi = half != 0;   // wave-uniform
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        xch[half][c][lane].re = hi ? acc[c].re : acc[6 + c].re;
+        xch[half][c][lane].im = hi ? acc[c].im : acc[6 + c].im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const R mr = hi ? acc[6 + c].re : acc[c].re;
+        const R mi = hi ? acc[6 + c].im : acc[c].im;
+        const cplx<R> o = xch[1 - half][c][lane];
+        acc[c] = {mr + o.re, mi + o.im};
+    }
+    if constexpr (REUSE) __syncthreads();
+}
+
+// Finish site s from the hopping sum acc (this lane's NC components) and store
+// it; K2DOT adds its three dot products to part[0..3).
+template <typename ST, int EPI, int TPS, typename R>
+__device__ __forceinline__ void stencil_epilogue(const StencilArgs<ST> &a, unsigned f, int64_t s, int half,
+                                                 const cplx<R> *acc, double part[3])
+{
+    constexpr int NC = 12 / TPS;
+    const int64_t V = a.g.V;
+    const ST *in = a.in + f * fstride<ST>(V);
+    cplx<R> o[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) o[c] = acc[c];
+    ST *out = a.out + f * fstride<ST>(V);
+    if constexpr (EPI == EPI_HOP) {
+        if constexpr (TPS == 1) st_sp(out, V, s, o); else st_sp_half(out, V, s, half, o);
+    } else {
+        // D_W psi = (4 - rho) psi - H psi / 2, then gamma_5 (negate spins 2, 3)
+        cplx<R> x[NC];
+        if constexpr (TPS == 1) ld_sp(in, V, s, x); else ld_sp_half(in, V, s, half, x);
+        const R m = (R)a.diag, hh = (R)0.5;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int cg = TPS == 1 ? c : 6 * half + c;
+            const cplx<R> d = m * x[c] - hh * o[c];
+            o[c] = (cg < 6) ? d : -d;
+        }
+        if constexpr (EPI == EPI_K2DOT || EPI == EPI_KPLUS) {
+            const ST *aux = a.aux + f * fstride<ST>(V);
+            if constexpr (TPS == 1) ld_sp(aux, V, s, x); else ld_sp_half(aux, V, s, half, x);
+            if constexpr (EPI == EPI_K2DOT) {
+                // w = K t + sigma p ; partials (p, w), Re (r, w), (w, w) of w as stored
+                const R sg = (R)a.sigma;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) o[c] = o[c] + sg * x[c];
+                cplx<R> ws[NC], rv[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) ws[c] = o[c];
+                as_stored(a.out, ws, NC);
+                const ST *aux2 = a.aux2 + f * fstride<ST>(V);
+                if constexpr (TPS == 1) ld_sp(aux2, V, s, rv); else ld_sp_half(aux2, V, s, half, rv);
+                double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const double wr = ws[c].re, wi = ws[c].im;
+                    d0 += (double)x[c].re * wr + (double)x[c].im * wi;
+                    d1 += (double)rv[c].re * wr + (double)rv[c].im * wi;
+                    d2 += wr * wr + wi * wi;
+                }
+                part[0] += d0;
+                part[1] += d1;
+                part[2] += d2;
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) o[c] = o[c] + x[c];
+            }
+        }
+        if constexpr (TPS == 1) st_sp(out, V, s, o); else st_sp_half(out, V, s, half, o);
+    }
+}
+
+// K2DOT: one partial of each dot per (field, tile).  Every thread of the block
+// must call it.
+template <typename ST, int EPI>
+__device__ __forceinline__ void store_partials(const StencilArgs<ST> &a, unsigned f, unsigned tile,
+                                               const double part[3])
+{
+    if constexpr (EPI == EPI_K2DOT) {
+        __shared__ double lds[4];
+        const double t0 = block_sum<256>(part[0], lds);
+        const double t1 = block_sum<256>(part[1], lds);
+        const double t2 = block_sum<256>(part[2], lds);
+        if (threadIdx.x == 0) {
+            double *pp = a.partial + (int64_t)f * 3 * gridDim.x + tile;
+            pp[0] = t0;
+            pp[gridDim.x] = t1;
+            pp[2 * gridDim.x] = t2;
+        }
+    }
+}
+
 template <typename ST, typename GT, int EPI, int TPS, int MAP>
 __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__restrict__ U)
 {
     using R = typename Planes<ST>::R;
-    constexpr int NC = 12 / TPS;   // complex components owned by one lane
     unsigned tile, f;
     int64_t s;
     int32_t co[4];
@@ -308,7 +413,7 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
     const int64_t V = a.g.V;
     const int half = TPS == 2 ? (int)(threadIdx.x >> 7) : 0;
     const ST *in = a.in + f * fstride<ST>(V);
-    double part = 0.0, part1 = 0.0, part2 = 0.0;
+    double part[3] = {0.0, 0.0, 0.0};
     cplx<R> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
@@ -324,121 +429,131 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
                 gather<2, 3, R>(in, U, V, a.g.Pu, s, co, Ls, st, acc);
         }
     }
-    if constexpr (TPS == 2) {
-        // half h keeps components [6h, 6h+6) and receives the partner's
-        __shared__ cplx<R> xch[2][6][128];
-        const int lane = threadIdx.x & 127;
-        const bool hi = half != 0;   // wave-uniform
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            xch[half][c][lane].re = hi ? acc[c].re : acc[6 + c].re;
-            xch[half][c][lane].im = hi ? acc[c].im : acc[6 + c].im;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            const R mr = hi ? acc[6 + c].re : acc[c].re;
-            const R mi = hi ? acc[6 + c].im : acc[c].im;
-            const cplx<R> o = xch[1 - half][c][lane];
-            acc[c] = {mr + o.re, mi + o.im};   // own half now in acc[0..6)
-        }
-    }
+    if constexpr (TPS == 2) exchange_halves<false>(acc, half);
+    if (valid) stencil_epilogue<ST, EPI, TPS>(a, f, s, half, acc, part);
+    store_partials<ST, EPI>(a, f, tile, part);
+}
+
+// The same stencil with each thread walking a column of T = Lt / 8 sites in
+// t, block lin taking t-chunk lin % 8 (so each XCD, blocks being handed to the
+// eight XCDs round-robin, owns one chunk of t for the whole x-y-z volume and
+// meets its x, y, z neighbours in its own L2).  The t hops reuse what the
+// previous site of the column loaded: the projection (1 + gamma_t) psi(t) and
+// the backward term U_t(t)^+ (1 + gamma_t) psi(t) for site t + 1 are carried
+// in registers, so psi and U_t are read once per site along t (plus once per
+// column for the chunk's first site).  With two lanes per site, half 0
+// gathers x, y and half 1 z and t.
+template <typename ST, typename GT, int EPI, int TPS>
+__global__ __launch_bounds__(256) void k_stencil_tm(StencilArgs<ST> a, const GT *__restrict__ U)
+{
+    using R = typename Planes<ST>::R;
+    constexpr int SPB = 256 / TPS;
+    const Geom &g = a.g;
+    const unsigned X = gridDim.x, Y = gridDim.y;
+    const unsigned lin = blockIdx.y * X + blockIdx.x;
+    const unsigned nxyz = X / 8;                  // x-y-z tiles
+    const unsigned chunk = lin % 8, k = lin / 8;
+    const unsigned f = k % Y, xt = k / Y;
+    const unsigned tile = chunk * nxyz + xt;
+    const int it = a.itb ? *a.itb + a.it : a.it;
+    if (a.stop != nullptr && it >= a.stop[f]) return;
+    const int64_t V = g.V, S3 = g.stride[3], Pu = g.Pu;
+    const int Lt = g.L[3], T = Lt / 8, t0 = (int)chunk * T;
+    const int lane = TPS == 2 ? (int)(threadIdx.x & 127) : (int)threadIdx.x;
+    const int half = TPS == 2 ? (int)(threadIdx.x >> 7) : 0;
+    const int64_t xyz = (int64_t)xt * SPB + lane;
+    const bool valid = xyz < S3;
+    int32_t co[4] = {0, 0, 0, 0};
     if (valid) {
-        cplx<R> o[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) o[c] = acc[c];
-        ST *out = a.out + f * fstride<ST>(V);
-        if constexpr (EPI == EPI_HOP) {
-            if constexpr (TPS == 1) st_sp(out, V, s, o); else st_sp_half(out, V, s, half, o);
-        } else {
-            // D_W psi = (4 - rho) psi - H psi / 2, then gamma_5 (negate spins 2, 3)
-            cplx<R> x[NC];
-            if constexpr (TPS == 1) ld_sp(in, V, s, x); else ld_sp_half(in, V, s, half, x);
-            const R m = (R)a.diag, hh = (R)0.5;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const int cg = TPS == 1 ? c : 6 * half + c;
-                const cplx<R> d = m * x[c] - hh * o[c];
-                o[c] = (cg < 6) ? d : -d;
-            }
-            if constexpr (EPI == EPI_K2DOT || EPI == EPI_KPLUS) {
-                const ST *aux = a.aux + f * fstride<ST>(V);
-                if constexpr (TPS == 1) ld_sp(aux, V, s, x); else ld_sp_half(aux, V, s, half, x);
-                if constexpr (EPI == EPI_K2DOT) {
-                    // w = K t + sigma p ; partials (p, w), Re (r, w), (w, w) of w as stored
-                    const R sg = (R)a.sigma;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) o[c] = o[c] + sg * x[c];
-                    cplx<R> ws[NC], rv[NC];
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) ws[c] = o[c];
-                    as_stored(a.out, ws, NC);
-                    const ST *aux2 = a.aux2 + f * fstride<ST>(V);
-                    if constexpr (TPS == 1) ld_sp(aux2, V, s, rv); else ld_sp_half(aux2, V, s, half, rv);
-                    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        const double wr = ws[c].re, wi = ws[c].im;
-                        d0 += (double)x[c].re * wr + (double)x[c].im * wi;
-                        d1 += (double)rv[c].re * wr + (double)rv[c].im * wi;
-                        d2 += wr * wr + wi * wi;
-                    }
-                    part = d0;
-                    part1 = d1;
-                    part2 = d2;
-                } else {
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) o[c] = o[c] + x[c];
-                }
-            }
-            if constexpr (TPS == 1) st_sp(out, V, s, o); else st_sp_half(out, V, s, half, o);
-        }
+        const int32_t q = (int32_t)xyz;
+        co[0] = q % g.L[0];
+        co[1] = (q / g.L[0]) % g.L[1];
+        co[2] = q / (g.L[0] * g.L[1]);
     }
-    if constexpr (EPI == EPI_K2DOT) {
-        __shared__ double lds[4];
-        const double t0 = block_sum<256>(part, lds);
-        const double t1 = block_sum<256>(part1, lds);
-        const double t2 = block_sum<256>(part2, lds);
-        if (threadIdx.x == 0) {
-            double *pp = a.partial + (int64_t)f * 3 * gridDim.x + tile;
-            pp[0] = t0;
-            pp[gridDim.x] = t1;
-            pp[2 * gridDim.x] = t2;
-        }
+    const int32_t Ls[4] = {g.L[0], g.L[1], g.L[2], g.L[3]};
+    const int64_t st[4] = {g.stride[0], g.stride[1], g.stride[2], g.stride[3]};
+    const ST *in = a.in + f * fstride<ST>(V);
+    const bool tdir = TPS == 1 || half == 1;
+    cplx<R> hp[6], gb[6];   // (1 + gamma_t) psi(t), and the backward t term of site t
+    if (valid && tdir) {
+        const int64_t s0 = xyz + (int64_t)t0 * S3;
+        const int64_t sm = t0 == 0 ? s0 + (int64_t)(Lt - 1) * S3 : s0 - S3;
+        cplx<R> v[12], u[9];
+        ld_sp(in, V, sm, v);
+        spin_proj<3, false>(v, hp);
+        ld_link(U, Pu, 3, sm, u);
+        link_mul<false>(u, hp, gb);
+        ld_sp(in, V, s0, v);
+        spin_proj<3, false>(v, hp);
     }
+    double part[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < T; ++j) {
+        const int t = t0 + j;
+        const int64_t s = xyz + (int64_t)t * S3;
+        cplx<R> acc[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+        if (valid) {
+            co[3] = t;
+            if constexpr (TPS == 1) {
+                gather<0, 2, R>(in, U, V, Pu, s, co, Ls, st, acc);
+            } else {
+                if (half == 0)
+                    gather<0, 1, R>(in, U, V, Pu, s, co, Ls, st, acc);
+                else
+                    gather_dir<2, R>(in, U, V, Pu, s, co[2], Ls[2], st[2], acc);
+            }
+            if (tdir) {
+                const int64_t sp = t == Lt - 1 ? s - (int64_t)(Lt - 1) * S3 : s + S3;
+                cplx<R> v[12], u[9], h[6], gg[6];
+                ld_sp(in, V, sp, v);
+                ld_link(U, Pu, 3, s, u);
+                spin_proj<3, true>(v, h);
+                link_mul<true>(u, h, gg);
+                spin_recon<3, true>(gg, acc);    // (1 - gamma_t) U_t(t) psi(t + 1)
+                spin_recon<3, false>(gb, acc);   // (1 + gamma_t) U_t(t - 1)^+ psi(t - 1)
+                link_mul<false>(u, hp, gb);      // the backward term of site t + 1
+                spin_proj<3, false>(v, hp);      // (1 + gamma_t) psi(t + 1)
+            }
+        }
+        if constexpr (TPS == 2) exchange_halves<true>(acc, half);
+        if (valid) stencil_epilogue<ST, EPI, TPS>(a, f, s, half, acc, part);
+    }
+    store_partials<ST, EPI>(a, f, tile, part);
 }
 
 // Launch shape chosen per (precision, epilogue, nf) by timing the variants on
 // the context's lattice the first time that shape is used (autotuning).
 // Launch variants: 0 / 1 one lane per site, MAP_LEX / MAP_REMAP; 2 / 3 two
-// lanes per site, likewise; 4 / 5 MAP_COL with one / two lanes per site.
-// FP16 storage runs one lane per site (variants 0, 1, 4).
-static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5) ? 2 : 1; }
+// lanes per site, likewise; 4 / 5 MAP_COL with one / two lanes per site; 6 / 7
+// the t-marching kernel with one / two lanes per site (Lt a multiple of 8).
+// FP16 storage runs one lane per site (variants 0, 1, 4, 6).
+static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7) ? 2 : 1; }
 
 unsigned stencil_tiles(const Geom &g, int v)
 {
     const int tps = variant_tps(v);
-    if (v >= 4) {
-        const int spb = 256 / tps;
-        return 8u * (unsigned)g.L[3] * (unsigned)((g.col_sites + spb - 1) / spb);
-    }
+    const int spb = 256 / tps;
+    if (v >= 6) return 8u * (unsigned)((g.stride[3] + spb - 1) / spb);
+    if (v >= 4) return 8u * (unsigned)g.L[3] * (unsigned)((g.col_sites + spb - 1) / spb);
     return (unsigned)((g.V * tps + 255) / 256);
+}
+
+bool stencil_variant_ok(const Geom &g, int prec, int v)
+{
+    if (v < 0 || v > 7) return false;
+    if ((v == 4 || v == 5) && !g.col_ok) return false;
+    if (v >= 6 && g.L[3] % 8 != 0) return false;
+    if (prec == OVL_HALF) return v == 0 || v == 1 || v == 4 || v == 6;
+    return true;
 }
 
 int64_t stencil_tiles_max(const Geom &g)
 {
     int64_t m = 0;
-    for (int v = 0; v < 6; ++v)
-        if (v < 4 || g.col_ok) m = std::max<int64_t>(m, stencil_tiles(g, v));
+    for (int v = 0; v < 8; ++v)
+        if (stencil_variant_ok(g, OVL_F64, v)) m = std::max<int64_t>(m, stencil_tiles(g, v));
     return m;
-}
-
-bool stencil_variant_ok(const Geom &g, int prec, int v)
-{
-    if (v < 0 || v > 5) return false;
-    if (v >= 4 && !g.col_ok) return false;
-    if (prec == OVL_HALF) return v == 0 || v == 1 || v == 4;
-    return true;
 }
 
 template <typename ST, typename GT, int EPI, int TPS, int MAP>
@@ -449,17 +564,26 @@ static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, in
     launch_k(c, pe, k_stencil<ST, GT, EPI, TPS, MAP>, grid, dim3(256), 0, a, U);
 }
 
+template <typename ST, typename GT, int EPI, int TPS>
+static void launch_tmarch(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, const PendingEvent *pe)
+{
+    dim3 grid(stencil_tiles(c.g, TPS == 2 ? 7 : 6), nf);
+    launch_k(c, pe, k_stencil_tm<ST, GT, EPI, TPS>, grid, dim3(256), 0, a, U);
+}
+
 template <typename ST, typename GT, int EPI>
 static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT *U, int nf,
                          const PendingEvent *pe = nullptr)
 {
-    if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: one thread per site only
+    if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: one lane per site only
         if (id == 0)
             launch_variant<ST, GT, EPI, 1, MAP_LEX>(c, a, U, nf, pe);
         else if (id == 1)
             launch_variant<ST, GT, EPI, 1, MAP_REMAP>(c, a, U, nf, pe);
-        else
+        else if (id == 4)
             launch_variant<ST, GT, EPI, 1, MAP_COL>(c, a, U, nf, pe);
+        else
+            launch_tmarch<ST, GT, EPI, 1>(c, a, U, nf, pe);
     } else {
         switch (id) {
         case 0: launch_variant<ST, GT, EPI, 1, MAP_LEX>(c, a, U, nf, pe); break;
@@ -467,12 +591,14 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
         case 2: launch_variant<ST, GT, EPI, 2, MAP_LEX>(c, a, U, nf, pe); break;
         case 3: launch_variant<ST, GT, EPI, 2, MAP_REMAP>(c, a, U, nf, pe); break;
         case 4: launch_variant<ST, GT, EPI, 1, MAP_COL>(c, a, U, nf, pe); break;
-        default: launch_variant<ST, GT, EPI, 2, MAP_COL>(c, a, U, nf, pe); break;
+        case 5: launch_variant<ST, GT, EPI, 2, MAP_COL>(c, a, U, nf, pe); break;
+        case 6: launch_tmarch<ST, GT, EPI, 1>(c, a, U, nf, pe); break;
+        default: launch_tmarch<ST, GT, EPI, 2>(c, a, U, nf, pe); break;
         }
     }
 }
 
-static constexpr int N_VARIANTS = 6;
+static constexpr int N_VARIANTS = 8;
 
 template <typename ST, typename GT, int EPI>
 static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, int prec)

@@ -223,12 +223,12 @@ __device__ __forceinline__ void apply_A(const cplx<R> &v0, const cplx<R> &v1, cp
     }
 }
 
-// acc += (1 - gamma_mu) W psi_fwd   (FWD = true,  W = U_mu(x))
-// acc += (1 + gamma_mu) W^+ psi_bwd (FWD = false, W = U_mu(x - mu))
+// The three parts of a hop, FWD = true: (1 - gamma_mu) U_mu(x) psi(x + mu);
+// FWD = false: (1 + gamma_mu) U_mu(x - mu)^+ psi(x - mu).
+// spin_proj: h = upper half of (1 -+ gamma_mu) psi = psi_up -+ A psi_down
 template <int MU, bool FWD, typename R>
-__device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[9], cplx<R> acc[12])
+__device__ __forceinline__ void spin_proj(const cplx<R> psi[12], cplx<R> h[6])
 {
-    cplx<R> h[6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         cplx<R> a0, a1;
@@ -241,7 +241,12 @@ __device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[
             h[3 + c] = psi[3 + c] + a1;
         }
     }
-    cplx<R> g[6];
+}
+
+// link_mul: g = W h (FWD) or W^+ h, per spin of the half spinor
+template <bool FWD, typename R>
+__device__ __forceinline__ void link_mul(const cplx<R> u[9], const cplx<R> h[6], cplx<R> g[6])
+{
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
@@ -258,6 +263,13 @@ __device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[
             }
             g[sp * 3 + a] = t;
         }
+}
+
+// spin_recon: acc += the full spinor whose upper half is g (lower half
+// -B g for FWD, B g otherwise)
+template <int MU, bool FWD, typename R>
+__device__ __forceinline__ void spin_recon(const cplx<R> g[6], cplx<R> acc[12])
+{
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         acc[c] = acc[c] + g[c];
@@ -282,6 +294,17 @@ __device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[
             }
         }
     }
+}
+
+// acc += (1 - gamma_mu) W psi_fwd   (FWD = true,  W = U_mu(x))
+// acc += (1 + gamma_mu) W^+ psi_bwd (FWD = false, W = U_mu(x - mu))
+template <int MU, bool FWD, typename R>
+__device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[9], cplx<R> acc[12])
+{
+    cplx<R> h[6], g[6];
+    spin_proj<MU, FWD>(psi, h);
+    link_mul<FWD>(u, h, g);
+    spin_recon<MU, FWD>(g, acc);
 }
 
 // ------------------------------------------------------------------ block -> tile mapping
