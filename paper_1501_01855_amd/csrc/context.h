@@ -46,8 +46,8 @@ struct Context {
 
     // gauge field, packed per precision
     double2 *U64 = nullptr;   // [4][9][Pu] (Geom::Pu: padded plane stride)
-    float2 *U32 = nullptr;    // [4][9][Pu]
-    void *U16 = nullptr;      // __half2 [4][9][Pu]
+    float2 *U32 = nullptr;    // 36 Pu float2: float4 [4][4][Pu] + float2 [4][Pu]
+    void *U16 = nullptr;      // 36 Pu __half2: uint4 [4][2][Pu] + uint32 [4][Pu]
     bool have_gauge = false;
 
     // kernel low modes: FP64 packed [n][12][V] and eigenvalues

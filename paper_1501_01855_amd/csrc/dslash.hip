@@ -73,13 +73,28 @@ __global__ void k_pack_gauge(const double2 *__restrict__ canon, double2 *__restr
 {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= V) return;
+    // FP32: float4 Q[4][4][Pu] then float2 R[4][Pu]; FP16: uint4 Q[4][2][Pu]
+    // then uint32 R[4][Pu] (the layouts ld_link reads)
+    float *Q32 = reinterpret_cast<float *>(U32);
+    float2 *R32 = reinterpret_cast<float2 *>(U32 + 32 * Pu);
+    __half2 *Q16 = U16;
+    __half2 *R16 = U16 + 32 * Pu;
     for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const double2 u = canon[s * 36 + mu * 9 + k];
             U64[(mu * 9 + k) * Pu + s] = u;
-            U32[(mu * 9 + k) * Pu + s] = make_float2((float)u.x, (float)u.y);
-            U16[(mu * 9 + k) * Pu + s] = __floats2half2_rn((float)u.x, (float)u.y);
+            const float2 f = make_float2((float)u.x, (float)u.y);
+            const __half2 h = __floats2half2_rn((float)u.x, (float)u.y);
+            if (k < 8) {
+                float *q = Q32 + 4 * ((mu * 4 + k / 2) * Pu + s) + 2 * (k % 2);
+                q[0] = f.x;
+                q[1] = f.y;
+                Q16[4 * ((mu * 2 + k / 4) * Pu + s) + k % 4] = h;
+            } else {
+                R32[mu * Pu + s] = f;
+                R16[mu * Pu + s] = h;
+            }
         }
 }
 
@@ -321,9 +336,11 @@ __device__ __forceinline__ void exchange_halves(cplx<R> acc[12], int half)
 
 // Finish site s from the hopping sum acc (this lane's NC components) and store
 // it; K2DOT adds its three dot products to part[0..3).
-template <typename ST, int EPI, int TPS, typename R>
+// OWN: the site's own input spinor is passed in own (one lane per site)
+// instead of being read again.
+template <typename ST, int EPI, int TPS, bool OWN = false, typename R>
 __device__ __forceinline__ void stencil_epilogue(const StencilArgs<ST> &a, unsigned f, int64_t s, int half,
-                                                 const cplx<R> *acc, double part[3])
+                                                 const cplx<R> *acc, double part[3], const cplx<R> *own = nullptr)
 {
     constexpr int NC = 12 / TPS;
     const int64_t V = a.g.V;
@@ -337,7 +354,13 @@ __device__ __forceinline__ void stencil_epilogue(const StencilArgs<ST> &a, unsig
     } else {
         // D_W psi = (4 - rho) psi - H psi / 2, then gamma_5 (negate spins 2, 3)
         cplx<R> x[NC];
-        if constexpr (TPS == 1) ld_sp(in, V, s, x); else ld_sp_half(in, V, s, half, x);
+        if constexpr (OWN) {
+            static_assert(TPS == 1, "own spinor with one lane per site");
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[c] = own[c];
+        } else {
+            if constexpr (TPS == 1) ld_sp(in, V, s, x); else ld_sp_half(in, V, s, half, x);
+        }
         const R m = (R)a.diag, hh = (R)0.5;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -522,18 +545,264 @@ __global__ __launch_bounds__(256) void k_stencil_tm(StencilArgs<ST> a, const GT 
     store_partials<ST, EPI>(a, f, tile, part);
 }
 
+// ----------------------------------------------------- LDS-tiled time march
+// A block owns a spatial tile of b0 x b1 x b2 = 256 sites (one lane each) and
+// walks T consecutive time slices.  At every slice each lane copies its own
+// stored spinor psi(y) into LDS (same plane layout as in memory, 256-site
+// planes); after a barrier a lane reads each x, y, z neighbour through one
+// generic pointer that points into the LDS tile when the neighbour is inside
+// it and into memory on a tile face or across a periodic wrap (no divergent
+// branches), so inside the tile every spinor is read from memory once per
+// slice instead of seven times.  Links are read from memory.  The time hops
+// are carried in registers as in the column march (psi(t + 1) becomes the next
+// slice's own spinor; U_t(t)^+ (1 + gamma_t) psi(t) is the next slice's
+// backward term), and the epilogue takes the own spinor from registers.  Math
+// in FP32 (FP32 and FP16 storage).
+struct TileShape {
+    int32_t b[3];   // tile extent per spatial direction (b0 b1 b2 = 256)
+    int32_t n[3];   // tiles per direction (the last one may be partial)
+    int32_t T;      // time slices per block
+    int32_t nch;    // time chunks, Lt / T
+};
+static constexpr int LDS_SITES = 256;
+
+// A site's spinor as stored.
+template <typename ST> struct SpRaw;
+template <> struct SpRaw<float4> {
+    float4 q[6];
+};
+template <> struct SpRaw<h8> {
+    uint4 q[3];
+    float sc;
+};
+
+// Planes at base[k * stride] (memory: stride V; LDS tile: stride 256); for
+// FP16 storage the scale at *sc.
+__device__ __forceinline__ void ld_raw(const float4 *base, const float *, int64_t stride, SpRaw<float4> &r)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.q[k] = base[k * stride];
+}
+__device__ __forceinline__ void ld_raw(const h8 *base, const float *sc, int64_t stride, SpRaw<h8> &r)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.q[k] = base[k * stride].v;
+    r.sc = *sc;
+}
+__device__ __forceinline__ void st_raw(float4 *base, float *, int64_t stride, const SpRaw<float4> &r)
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) base[k * stride] = r.q[k];
+}
+__device__ __forceinline__ void st_raw(h8 *base, float *sc, int64_t stride, const SpRaw<h8> &r)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) base[k * stride].v = r.q[k];
+    *sc = r.sc;
+}
+// the values ld_sp returns for the same stored spinor
+__device__ __forceinline__ void unpack(const SpRaw<float4> &r, cplx<float> v[12])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        v[2 * k] = {r.q[k].x, r.q[k].y};
+        v[2 * k + 1] = {r.q[k].z, r.q[k].w};
+    }
+}
+__device__ __forceinline__ void unpack(const SpRaw<h8> &r, cplx<float> v[12])
+{
+    const float sc = r.sc;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint4 t = r.q[k];
+        const float2 a = h2f2(t.x), b = h2f2(t.y), c = h2f2(t.z), d = h2f2(t.w);
+        v[4 * k] = {a.x * sc, a.y * sc};
+        v[4 * k + 1] = {b.x * sc, b.y * sc};
+        v[4 * k + 2] = {c.x * sc, c.y * sc};
+        v[4 * k + 3] = {d.x * sc, d.y * sc};
+    }
+}
+// scale plane of a field in memory (FP16 storage; unused otherwise)
+__device__ __forceinline__ const float *scale_plane(const float4 *, int64_t) { return nullptr; }
+__device__ __forceinline__ const float *scale_plane(const h8 *p, int64_t V)
+{
+    return reinterpret_cast<const float *>(p + 3 * V);
+}
+__device__ __forceinline__ void ld_raw_site(const float4 *in, const float *, int64_t V, int64_t s, SpRaw<float4> &r)
+{
+    ld_raw(in + s, nullptr, V, r);
+}
+__device__ __forceinline__ void ld_raw_site(const h8 *in, const float *sc, int64_t V, int64_t s, SpRaw<h8> &r)
+{
+    ld_raw(in + s, sc + s, V, r);
+}
+
+// Neighbour spinor of lane tid: in the LDS tile (lane tid + d) when inside,
+// at site ns in memory otherwise.
+template <typename ST>
+__device__ __forceinline__ void ld_nbr(const ST *in, const float *sc, int64_t V, int64_t ns, bool inside, const ST *Lsp,
+                                       const float *Lsc, int lane, cplx<float> v[12])
+{
+    const ST *b = inside ? Lsp + lane : in + ns;
+    const float *q = inside ? Lsc + lane : (sc ? sc + ns : nullptr);
+    SpRaw<ST> r;
+    ld_raw(b, q, inside ? (int64_t)LDS_SITES : V, r);
+    unpack(r, v);
+}
+
+template <int MU, typename ST, typename GT>
+__device__ __forceinline__ void tile_dir(const ST *in, const float *sc, const GT *__restrict__ U, int64_t V,
+                                         int64_t Pu, int64_t s, int32_t c, int32_t Lm, int64_t st, int tid, int lstep,
+                                         bool fin, bool bin, const ST *Lsp, const float *Lsc, cplx<float> acc[12])
+{
+    cplx<float> v[12], u[9];
+    const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st : s + st;
+    const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st : s - st;
+    ld_nbr(in, sc, V, fwd, fin, Lsp, Lsc, tid + lstep, v);
+    ld_link(U, Pu, MU, s, u);
+    hop_term<MU, true>(v, u, acc);
+    ld_nbr(in, sc, V, bwd, bin, Lsp, Lsc, tid - lstep, v);
+    ld_link(U, Pu, MU, bwd, u);
+    hop_term<MU, false>(v, u, acc);
+}
+
+template <typename ST, typename GT, int EPI>
+__global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT *__restrict__ U, TileShape ts)
+{
+    __shared__ ST Lsp[Planes<ST>::n * LDS_SITES];   // the tile's stored spinors at the current slice
+    __shared__ float Lsc[std::is_same<ST, h8>::value ? LDS_SITES : 1];
+    const Geom &g = a.g;
+    const unsigned X = gridDim.x, Y = gridDim.y;
+    const unsigned lin = blockIdx.y * X + blockIdx.x;
+    const unsigned ntl = (unsigned)(ts.n[0] * ts.n[1] * ts.n[2]);
+    unsigned chunk, f, tl;
+    if (ts.nch % 8 == 0) {   // XCD x (blocks go to the XCDs round-robin) owns nch / 8 consecutive chunks
+        const unsigned x = lin % 8, k = lin / 8, per = (unsigned)ts.nch / 8;
+        f = k % Y;
+        const unsigned r = k / Y;
+        chunk = x * per + r / ntl;
+        tl = r % ntl;
+    } else {
+        f = lin % Y;
+        const unsigned r = lin / Y;
+        chunk = r / ntl;
+        tl = r % ntl;
+    }
+    const unsigned tile = chunk * ntl + tl;
+    const int it = a.itb ? *a.itb + a.it : a.it;
+    if (a.stop != nullptr && it >= a.stop[f]) return;   // whole block: field converged
+    const int tid = (int)threadIdx.x;
+    const int b0 = ts.b[0], b1 = ts.b[1];
+    const int l0 = tid % b0, l1 = (tid / b0) % b1, l2 = tid / (b0 * b1);
+    int32_t co[3];
+    co[0] = (int32_t)(tl % (unsigned)ts.n[0]) * b0 + l0;
+    co[1] = (int32_t)((tl / (unsigned)ts.n[0]) % (unsigned)ts.n[1]) * b1 + l1;
+    co[2] = (int32_t)(tl / (unsigned)(ts.n[0] * ts.n[1])) * ts.b[2] + l2;
+    const bool valid = co[0] < g.L[0] && co[1] < g.L[1] && co[2] < g.L[2];
+    const int64_t V = g.V, S3 = g.stride[3], Pu = g.Pu;
+    const int64_t xyz = valid ? co[0] + (int64_t)g.L[0] * (co[1] + (int64_t)g.L[1] * co[2]) : 0;
+    // neighbour inside the tile and no periodic wrap (a valid lane's in-tile
+    // neighbours are valid)
+    const bool f0 = l0 + 1 < b0 && co[0] + 1 < g.L[0], f1 = l1 + 1 < b1 && co[1] + 1 < g.L[1],
+               f2 = l2 + 1 < ts.b[2] && co[2] + 1 < g.L[2];
+    const bool k0 = l0 > 0, k1 = l1 > 0, k2 = l2 > 0;
+    const ST *in = a.in + f * fstride<ST>(V);
+    const float *sc = scale_plane(in, V);
+    const int Lt = g.L[3], T = ts.T, t0 = (int)chunk * T;
+    SpRaw<ST> cur;     // psi(t) as stored
+    cplx<float> gb[6];  // backward t term of site t
+    if (valid) {
+        const int64_t s0 = xyz + (int64_t)t0 * S3;
+        const int64_t sm = t0 == 0 ? s0 + (int64_t)(Lt - 1) * S3 : s0 - S3;
+        cplx<float> v[12], u[9], h[6];
+        ld_sp(in, V, sm, v);
+        ld_link(U, Pu, 3, sm, u);
+        spin_proj<3, false>(v, h);
+        link_mul<false>(u, h, gb);
+        ld_raw_site(in, sc, V, s0, cur);
+    }
+    double part[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < T; ++j) {
+        const int t = t0 + j;
+        const int64_t s = xyz + (int64_t)t * S3;
+        if (valid) st_raw(Lsp + tid, Lsc + tid, LDS_SITES, cur);
+        __syncthreads();
+        if (valid) {
+            cplx<float> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+            tile_dir<0>(in, sc, U, V, Pu, s, co[0], g.L[0], g.stride[0], tid, 1, f0, k0, Lsp, Lsc, acc);
+            tile_dir<1>(in, sc, U, V, Pu, s, co[1], g.L[1], g.stride[1], tid, b0, f1, k1, Lsp, Lsc, acc);
+            tile_dir<2>(in, sc, U, V, Pu, s, co[2], g.L[2], g.stride[2], tid, b0 * b1, f2, k2, Lsp, Lsc, acc);
+            const int64_t sp = t == Lt - 1 ? s - (int64_t)(Lt - 1) * S3 : s + S3;
+            SpRaw<ST> nr;
+            ld_raw_site(in, sc, V, sp, nr);
+            cplx<float> v[12], ut[9], h[6], gg[6];
+            ld_link(U, Pu, 3, s, ut);
+            unpack(nr, v);
+            spin_proj<3, true>(v, h);
+            link_mul<true>(ut, h, gg);
+            spin_recon<3, true>(gg, acc);    // (1 - gamma_t) U_t(t) psi(t + 1)
+            spin_recon<3, false>(gb, acc);   // (1 + gamma_t) U_t(t - 1)^+ psi(t - 1)
+            unpack(cur, v);
+            spin_proj<3, false>(v, h);
+            link_mul<false>(ut, h, gb);      // the backward term of site t + 1
+            stencil_epilogue<ST, EPI, 1, true>(a, f, s, 0, acc, part, v);
+            cur = nr;
+        }
+        if (j + 1 < T) __syncthreads();     // LDS is rewritten by the next slice
+    }
+    store_partials<ST, EPI>(a, f, tile, part);
+}
+
 // Launch shape chosen per (precision, epilogue, nf) by timing the variants on
 // the context's lattice the first time that shape is used (autotuning).
 // Launch variants: 0 / 1 one lane per site, MAP_LEX / MAP_REMAP; 2 / 3 two
 // lanes per site, likewise; 4 / 5 MAP_COL with one / two lanes per site; 6 / 7
 // the t-marching kernel with one / two lanes per site (Lt a multiple of 8).
-// FP16 storage runs one lane per site (variants 0, 1, 4, 6).
+// FP16 storage runs one lane per site (variants 0, 1, 4, 6).  8 .. 11 the
+// LDS-tiled march with T = 1, 2, 4, 8 time slices per block (Lt a multiple of
+// T; FP32 and FP16 storage).
+static constexpr int N_VARIANTS = 12;
 static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7) ? 2 : 1; }
+
+// Tile of the LDS-tiled march: the 256-site box with the fewest padded sites,
+// then the fewest face sites (each face lane fetches a neighbour from memory).
+static TileShape tile_shape(const Geom &g, int v)
+{
+    static const int cand[][3] = {{8, 8, 4}, {8, 4, 8}, {4, 8, 8}, {16, 4, 4}, {4, 16, 4}, {4, 4, 16},
+                                  {16, 8, 2}, {8, 16, 2}, {16, 16, 1}, {32, 8, 1}, {32, 4, 2}, {2, 8, 16}};
+    TileShape ts{};
+    double best = 1e300;
+    for (const auto &b : cand) {
+        int64_t padded = 1;
+        double face = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            padded *= (int64_t)((g.L[m] + b[m] - 1) / b[m]) * b[m];
+            face += 1.0 / b[m];
+        }
+        const double score = (double)padded * (1.0 + 0.5 * face);
+        if (score < best) {
+            best = score;
+            for (int m = 0; m < 3; ++m) {
+                ts.b[m] = b[m];
+                ts.n[m] = (g.L[m] + b[m] - 1) / b[m];
+            }
+        }
+    }
+    ts.T = 1 << (v - 8);
+    ts.nch = g.L[3] / ts.T;
+    return ts;
+}
 
 unsigned stencil_tiles(const Geom &g, int v)
 {
     const int tps = variant_tps(v);
     const int spb = 256 / tps;
+    if (v >= 8) {
+        const TileShape ts = tile_shape(g, v);
+        return (unsigned)(ts.n[0] * ts.n[1] * ts.n[2] * ts.nch);
+    }
     if (v >= 6) return 8u * (unsigned)((g.stride[3] + spb - 1) / spb);
     if (v >= 4) return 8u * (unsigned)g.L[3] * (unsigned)((g.col_sites + spb - 1) / spb);
     return (unsigned)((g.V * tps + 255) / 256);
@@ -541,9 +810,10 @@ unsigned stencil_tiles(const Geom &g, int v)
 
 bool stencil_variant_ok(const Geom &g, int prec, int v)
 {
-    if (v < 0 || v > 7) return false;
+    if (v < 0 || v >= N_VARIANTS) return false;
     if ((v == 4 || v == 5) && !g.col_ok) return false;
-    if (v >= 6 && g.L[3] % 8 != 0) return false;
+    if ((v == 6 || v == 7) && g.L[3] % 8 != 0) return false;
+    if (v >= 8) return prec != OVL_F64 && g.L[3] % (1 << (v - 8)) == 0;
     if (prec == OVL_HALF) return v == 0 || v == 1 || v == 4 || v == 6;
     return true;
 }
@@ -551,8 +821,9 @@ bool stencil_variant_ok(const Geom &g, int prec, int v)
 int64_t stencil_tiles_max(const Geom &g)
 {
     int64_t m = 0;
-    for (int v = 0; v < 8; ++v)
-        if (stencil_variant_ok(g, OVL_F64, v)) m = std::max<int64_t>(m, stencil_tiles(g, v));
+    for (int v = 0; v < N_VARIANTS; ++v)
+        if (stencil_variant_ok(g, OVL_F64, v) || stencil_variant_ok(g, OVL_F32, v))
+            m = std::max<int64_t>(m, stencil_tiles(g, v));
     return m;
 }
 
@@ -572,9 +843,23 @@ static void launch_tmarch(Context &c, const StencilArgs<ST> &a, const GT *U, int
 }
 
 template <typename ST, typename GT, int EPI>
+static void launch_lds(Context &c, int v, const StencilArgs<ST> &a, const GT *U, int nf, const PendingEvent *pe)
+{
+    const TileShape ts = tile_shape(c.g, v);
+    dim3 grid(stencil_tiles(c.g, v), nf);
+    launch_k(c, pe, k_stencil_lds<ST, GT, EPI>, grid, dim3(256), 0, a, U, ts);
+}
+
+template <typename ST, typename GT, int EPI>
 static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT *U, int nf,
                          const PendingEvent *pe = nullptr)
 {
+    if constexpr (!std::is_same<ST, double2>::value) {   // FP32 math only
+        if (id >= 8) {
+            launch_lds<ST, GT, EPI>(c, id, a, U, nf, pe);
+            return;
+        }
+    }
     if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: one lane per site only
         if (id == 0)
             launch_variant<ST, GT, EPI, 1, MAP_LEX>(c, a, U, nf, pe);
@@ -597,8 +882,6 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
         }
     }
 }
-
-static constexpr int N_VARIANTS = 8;
 
 template <typename ST, typename GT, int EPI>
 static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, int prec)

@@ -7,11 +7,11 @@
 //   FP32: float4  [6][V]    (plane k holds complex components 2k, 2k+1)
 //   HALF: uint4   [3][V]    (plane k holds 4 complex FP16 values, 4k..4k+3)
 //         + float scale[V]  (the site's largest |real component|)
-// Gauge fields, one plane per complex entry and direction:
-//   FP64: double2 [4][9][V]; FP32: float2 [4][9][V];
-//   HALF: uint4 [4][3][V] + uint2 [4][1][V]... see ld_link below: 18 BF16
-//         values in two uint4 and one uint (36 bytes) per link, stored as
-//         uint4 [4][2][V] and uint32 [4][V].
+// Gauge fields (P = the padded plane stride, Geom::Pu):
+//   FP64: double2 [4][9][P]   (one plane per complex entry and direction)
+//   FP32: float4 [4][4][P] (entries 0..7 in pairs) + float2 [4][P] (entry 8)
+//   HALF: uint4 [4][2][P] (entries 0..7 as __half2, four per uint4)
+//         + uint32 [4][P] (entry 8)
 #pragma once
 #include <hip/hip_fp16.h>
 
@@ -177,26 +177,44 @@ __device__ __forceinline__ void ld_link(const double2 *__restrict__ U, int64_t P
         u[k] = {t.x, t.y};
     }
 }
+// FP32 links: the eight entries 0..7 of a link as four float4 planes per
+// direction, Q [4 mu][4][P], followed by entry 8 as float2 planes R [4 mu][P]
+// (five loads per link instead of nine).
 __device__ __forceinline__ void ld_link(const float2 *__restrict__ U, int64_t P, int mu,
                                         int64_t s, cplx<float> u[9])
 {
+    const float4 *Q = reinterpret_cast<const float4 *>(U);
+    const float2 *R = reinterpret_cast<const float2 *>(Q + 16 * P);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        float2 t = U[(mu * 9 + k) * P + s];
-        u[k] = {t.x, t.y};
+    for (int k = 0; k < 4; ++k) {
+        const float4 q = Q[(mu * 4 + k) * P + s];
+        u[2 * k] = {q.x, q.y};
+        u[2 * k + 1] = {q.z, q.w};
     }
+    const float2 r = R[mu * P + s];
+    u[8] = {r.x, r.y};
 }
 
-// FP16 links: one __half2 per complex entry, [4][9][V] (entries of a unitary
-// matrix have modulus <= 1, so no scale is needed).
+// FP16 links: one __half2 per complex entry (entries of a unitary matrix have
+// modulus <= 1, so no scale is needed); entries 0..7 as two uint4 planes per
+// direction, Q [4 mu][2][P], followed by entry 8 as uint32 planes R [4 mu][P]
+// (three loads per link).
 __device__ __forceinline__ void ld_link(const __half2 *__restrict__ U, int64_t P, int mu,
                                         int64_t s, cplx<float> u[9])
 {
+    const uint4 *Q = reinterpret_cast<const uint4 *>(U);
+    const uint32_t *R = reinterpret_cast<const uint32_t *>(Q + 8 * P);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const float2 t = __half22float2(U[(mu * 9 + k) * P + s]);
-        u[k] = {t.x, t.y};
+    for (int k = 0; k < 2; ++k) {
+        const uint4 q = Q[(mu * 2 + k) * P + s];
+        const float2 a = h2f2(q.x), b = h2f2(q.y), c = h2f2(q.z), d = h2f2(q.w);
+        u[4 * k] = {a.x, a.y};
+        u[4 * k + 1] = {b.x, b.y};
+        u[4 * k + 2] = {c.x, c.y};
+        u[4 * k + 3] = {d.x, d.y};
     }
+    const float2 r = h2f2(R[mu * P + s]);
+    u[8] = {r.x, r.y};
 }
 
 // ------------------------------------------------------------------ spin algebra
