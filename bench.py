@@ -61,6 +61,9 @@ def parse():
                     help="short run for hardware counters: a 1 GiB elementwise copy (calibration), "
                          "one sign-function call per precision on the 16^3x32 workload and the "
                          "stand-alone 32^3x64 stencil")
+    ap.add_argument("--eig", action="store_true",
+                    help="add the eigSUMR leg on 24^3x48 (12 point sources, calculating solves then a "
+                         "deflated batch; several minutes)")
     ap.add_argument("--tuning", default=None,
                     help="JSON of stencil launch choices to install instead of autotuning (the 'tuning' "
                          "object an earlier run printed), so that profiler runs see the same kernels")
@@ -253,6 +256,88 @@ def uneven_leg(torch, ovl):
             "status": [r[2] for r in res]}
 
 
+def eig_leg(torch, ovl, n_calc=3):
+    """eigSUMR on 24^3 x 48 (links eps 0.25, seed 3; rho 1.4, mu 0.01, N_Z 20
+    with 10 exact kernel modes; n_eig 20, m 60): n_calc calculating solves
+    (Alg. 5 collection, Alg. 6 Rayleigh-Ritz) on the first spin-colour point
+    sources at site 0, the eigenspace's D psi' recomputed in FP64, then all 12
+    sources in one deflated batched solve; for comparison one undeflated mixed
+    solve and one deflated FP64 solve of the first source, and the 12-field
+    stencil's algorithmic GB/s."""
+    dims, mu = (24, 24, 24, 48), 0.01
+    ctx = ovl.Context(dims)
+    t0 = time.perf_counter()
+    ctx.gauge_generate(3, 0.25)
+    ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)
+    zolo = ovl.zolotarev_coeffs(NZ, max(abs(e) for e in ev), lmax)
+    B = torch.stack([ctx.source(ovl.SRC_POINT, site=0, spin=s, colour=c) for s in range(4) for c in range(3)])
+    torch.cuda.synchronize()
+    setup_lowmodes = time.perf_counter() - t0
+
+    def params(mixed, calc, defl):
+        return ovl.solver_defaults(rho=RHO, mu=mu, tol=TOL, eta_tilde=1e-3, relax_floor=1e-2,
+                                   f32_threshold=(1e-6 if mixed else 10.0),
+                                   half_threshold=(3e-3 if mixed else 10.0), max_outer=16, max_middle=6000,
+                                   max_mscg=20000, use_deflation=defl, eig_calc=calc, n_eig=20, m_eig=60,
+                                   verbose=1)   # one line per GMRESR step (progress of long solves)
+
+    out = {"lattice": "24x24x24x48", "mu": mu, "n_eig": 20, "m_eig": 60, "setup_lowmodes_s": setup_lowmodes}
+    calc = []
+    t0 = time.perf_counter()
+    for i in range(n_calc):
+        t1 = time.perf_counter()
+        _, st, code = ctx.solve(B[i:i + 1], zolo, params(True, 1, 1))
+        torch.cuda.synchronize()
+        calc.append({"seconds": time.perf_counter() - t1, "status": code, **st[0].as_dict()})
+        print(f"[bench] eigSUMR calculating solve {i} done", file=sys.stderr, flush=True)
+    ctx.eigspace_recompute(RHO, zolo, 1e-12)
+    torch.cuda.synchronize()
+    out["calculating_solves"] = calc
+    out["eig_setup_s"] = time.perf_counter() - t0
+    info = ctx.eigspace_info()
+    out["eigenspace"] = {"held": info["held"], "diagonalisations": info["ndiag"], "ritz": info["ritz"],
+                         "max_ritz_residual": max(info["resid"]) if info["resid"] else None}
+    t0 = time.perf_counter()
+    X, st, code = ctx.solve(B, zolo, params(True, 0, 1))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("[bench] eigSUMR deflated batch done", file=sys.stderr, flush=True)
+    DX, _ = ctx.overlap(X, RHO, mu, zolo, 1e-13)
+    res = [float(torch.linalg.vector_norm(B[f] - DX[f]) / torch.linalg.vector_norm(B[f])) for f in range(12)]
+    del DX
+    out["deflated_batch12"] = {"status": code, "seconds": dt, "solves_per_s": 12 / dt,
+                               "max_true_relres": max(res),
+                               "sumr_iters_per_field": [s.sumr_iters for s in st],
+                               "mscg_iters_per_field": [s.mscg_iters for s in st]}
+    out["solves_per_s_including_eig_setup"] = (12 + 0) / (dt + out["eig_setup_s"])
+    t0 = time.perf_counter()
+    _, st, code = ctx.solve(B[0:1], zolo, params(True, 0, 0))
+    torch.cuda.synchronize()
+    out["undeflated_mixed_single"] = {"status": code, "seconds": time.perf_counter() - t0, **st[0].as_dict()}
+    t0 = time.perf_counter()
+    _, st, code = ctx.solve(B[0:1], zolo, params(False, 0, 1))
+    torch.cuda.synchronize()
+    out["deflated_fp64_single"] = {"status": code, "seconds": time.perf_counter() - t0, **st[0].as_dict()}
+    print("[bench] eigSUMR comparison solves done", file=sys.stderr, flush=True)
+    sten = {}
+    for prec in (ovl.HALF, ovl.F32):
+        ctx.wilson_dslash(B, prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(10):
+            ctx.wilson_dslash(B, prec)
+        torch.cuda.synchronize()
+        pr = ctx.profile_read(ovl.KERN_STENCIL, prec)
+        ctx.profile(False)
+        sten[PREC_NAMES[prec]] = {"avg_us": 1e3 * pr["ms"] / pr["launches"],
+                                  "bytes_per_launch": pr["bytes"] / pr["launches"],
+                                  "GBps": pr["bytes"] / (pr["ms"] * 1e6)}
+    out["stencil_12rhs"] = sten
+    out["tuning"] = ctx.tuning()
+    ctx.close()
+    return out
+
+
 def adjoint_leg(torch, ovl):
     """dS/dpsi and dS/dU for S = Re(chi^H D psi), N_Z = 20, no exactly treated
     modes: 8^3 x 16 in FP64 (eta 1e-10) and 32^3 x 64 in FP32 (eta 1e-6)."""
@@ -412,6 +497,9 @@ def main():
         out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
         out["tuning"]["32x32x32x64"] = out["dslash_hbm"].pop("tuning")
         print("[bench] stand-alone stencil done", file=sys.stderr, flush=True)
+    if args.eig:
+        out["eigsumr_24c48"] = eig_leg(torch, ovl)
+        print("[bench] eigSUMR leg done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(st_64[-1]["mscg_iters"])
     print(json.dumps(out), flush=True)
