@@ -275,8 +275,18 @@ ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int6
  *                    Off by default: on MI355X the replays were slower than
  *                    direct launches for the 16^3x32 solve.
  *   OVL_OPT_AUTOTUNE (default on) time the stencil launch variants on first
- *                    use (off: a fixed variant). */
-enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2 };
+ *                    use (off: a fixed variant).
+ *   OVL_OPT_ADAPTIVE_NZ (default off) inside the solvers, each sign-function
+ *                    call at accuracy eta uses the fewest Zolotarev poles n <= n_z
+ *                    whose approximation error Delta(n) on the same interval
+ *                    [a, b] is at most eta / 4, and gives the multi-shift CG the
+ *                    rest, eta - Delta(n) (the error of a sign call is bounded by
+ *                    the larger of Delta and the inversion error, Sec. 3).  Relaxed
+ *                    calls then run fewer shifted systems with a larger smallest
+ *                    shift; calls at tight accuracy keep all n_z poles.  Direct
+ *                    calls of the sign function and the overlap operator through
+ *                    this ABI always use the coefficients passed. */
+enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2, OVL_OPT_ADAPTIVE_NZ = 3 };
 ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
 
 /* Stencil launch shapes.  The first launch of each (precision, epilogue,

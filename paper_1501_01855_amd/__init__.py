@@ -19,7 +19,7 @@ F64, F32, HALF = 0, 1, 2
 SRC_POINT, SRC_GAUSS, SRC_Z2 = 0, 1, 2
 MAX_NZ = 64
 KERN_STENCIL, KERN_SHIFT = 0, 1
-OPT_GRAPHS, OPT_AUTOTUNE = 1, 2
+OPT_GRAPHS, OPT_AUTOTUNE, OPT_ADAPTIVE_NZ = 1, 2, 3
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_NOMEM", -4: "ERR_NOT_CONVERGED",
           -5: "ERR_BREAKDOWN", -6: "ERR_UNSUPPORTED", -7: "ERR_STATE"}

@@ -513,6 +513,8 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value)
             ctx->use_graphs = value != 0;
         else if (option == OVL_OPT_AUTOTUNE)
             ctx->autotune = value;
+        else if (option == OVL_OPT_ADAPTIVE_NZ)
+            ctx->adaptive_nz = value != 0;
         else
             throw Error{OVL_ERR_ARG, "unknown option"};
     });

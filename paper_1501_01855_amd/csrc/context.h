@@ -91,6 +91,12 @@ struct Context {
     std::map<int, int> tuned;
     int autotune = 1;
 
+    // sign calls inside the solvers take as few Zolotarev poles as their
+    // accuracy allows (coefficients per pole count for the interval zolo_ab)
+    bool adaptive_nz = false;
+    std::map<int, ovl_zolo> zolo_by_n;
+    double zolo_ab[2] = {0.0, 0.0};
+
     EigSpace eig;
 
     // graphs of multi-shift CG chunks, by launch configuration

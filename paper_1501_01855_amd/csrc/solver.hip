@@ -58,12 +58,44 @@ static double min_active(const double *eta, int nf)
     return m;
 }
 
+// With the adaptive option: the fewest poles n <= z.n_z whose rational
+// approximation error Delta(n) on [z.a, z.b] is at most eta / 4 (eta the
+// strictest accuracy asked for); the multi-shift CG then gets eta - Delta(n)
+// per field, so that the call's error stays within eta (Sec. 3: the error of
+// the sign function is bounded by the larger of the approximation and the
+// inversion errors).  Returns z itself when no smaller order qualifies.
+static const ovl_zolo &zolo_for_accuracy(Context &c, const ovl_zolo &z, double eta_min)
+{
+    if (!c.adaptive_nz || !(eta_min < 1e300) || !(z.a > 0.0) || !(z.b > z.a)) return z;
+    if (c.zolo_ab[0] != z.a || c.zolo_ab[1] != z.b) {
+        c.zolo_by_n.clear();
+        c.zolo_ab[0] = z.a;
+        c.zolo_ab[1] = z.b;
+    }
+    for (int n = 2; n < z.n_z; ++n) {
+        auto it = c.zolo_by_n.find(n);
+        if (it == c.zolo_by_n.end()) {
+            ovl_zolo zn{};
+            zolotarev(n, z.a, z.b, zn);
+            it = c.zolo_by_n.emplace(n, zn).first;
+        }
+        if (it->second.delta <= 0.25 * eta_min) return it->second;
+    }
+    return z;
+}
+
 // s = sign(K) in (FP64 packed in/out) with the multi-shift CG in precision
 // prec.  Counters: with per_field, st has nf entries and field f's work goes
 // to st[f]; otherwise st is one aggregate.
-static void sign_f64(Context &c, double rho, const ovl_zolo &z, const double2 *in, double2 *s, int nf,
-                     const double *eta, int prec, int maxiter, ovl_stats *st, bool per_field)
+static void sign_f64(Context &c, double rho, const ovl_zolo &zin, const double2 *in, double2 *s, int nf,
+                     const double *eta_in, int prec, int maxiter, ovl_stats *st, bool per_field)
 {
+    const ovl_zolo &z = zolo_for_accuracy(c, zin, min_active(eta_in, nf));
+    std::vector<double> eta_v(eta_in, eta_in + nf);
+    if (&z != &zin)
+        for (double &e : eta_v)
+            if (e > 0.0) e -= z.delta;   // >= 3/4 of the accuracy asked for
+    const double *eta = eta_v.data();
     ovl_stats *agg = per_field ? nullptr : st;
     if (prec == OVL_F64) {
         sign_mscg(c, rho, z, in, s, nf, eta, prec, maxiter, agg);

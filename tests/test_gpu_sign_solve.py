@@ -185,3 +185,28 @@ def test_solve_graphs_off_matches(c1):
         xs.append((to_host(x), st[0].mscg_iters))
         ctx.close()
     assert xs[0][1] == xs[1][1] and np.array_equal(xs[0][0], xs[1][0])
+
+
+def test_solve_adaptive_poles(c1):
+    """With the adaptive option every sign call inside the solver takes the
+    fewest Zolotarev poles whose error Delta(n) on the same interval is at
+    most a quarter of the accuracy asked for (Sec. 3: the sign error is
+    bounded by the larger of Delta and the inversion error).  The solve
+    still reaches a true residual <= 1e-10 with the oracle's FP64 D, with
+    fewer multi-shift iterations than with all 16 poles in every call."""
+    ovl = require_gpu()
+    b = synth.z2_source(c1.dims, 32)
+    p = ovl.solver_defaults(rho=1.4, mu=0.05, tol=1e-10, eta_tilde=1e-3, f32_threshold=1e-6,
+                            half_threshold=3e-3)
+    D = krylov.Overlap(c1.sign, 0.05)
+    iters = {}
+    for adaptive in (False, True):
+        ctx, zg = _ctx(ovl, c1)
+        ctx.set_option(ovl.OPT_ADAPTIVE_NZ, adaptive)
+        x, st, code = ctx.solve(to_dev(b), zg, p)
+        assert code == 0
+        assert norm(b - D(to_host(x), 1e-15)) / norm(b) <= 1e-10
+        iters[adaptive] = st[0].mscg_iters
+        ctx.close()
+    print("multi-shift iterations, fixed / adaptive poles:", iters)
+    assert iters[True] < iters[False]
