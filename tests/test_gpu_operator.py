@@ -139,3 +139,65 @@ def test_every_launch_variant(dims):
             assert rel(s, sref) < {ovl.F64: 1e-12, ovl.F32: 1e-5, ovl.HALF: 1e-2}[prec], (prec, v)
             assert ctx.tuning()[_keys(prec, 1)[2]] == v
             ctx.close()
+
+
+def _sample_sites(dims, n, seed):
+    V = int(np.prod(dims))
+    L0, L1, L2 = dims[0], dims[1], dims[2]
+    S3 = L0 * L1 * L2
+    # lattice corners, the last site of the first x row, a time-slice boundary
+    # and the faces of 8 x 8 x 4 tiles, then random sites
+    fixed = [0, V - 1, L0 - 1, S3 - 1, S3, 7, 8, 7 * L0, 8 * L0, 3 * L0 * L1, 4 * L0 * L1]
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([fixed, rng.integers(0, V, n)]))
+
+
+@pytest.mark.parametrize("prec", ["f32", "half"])
+def test_dslash_32c64_sampled(prec):
+    """The stand-alone 32^3 x 64 stencil as the benchmark launches it (links
+    eps 0.25 seed 5, Gaussian source seed 7, autotuned launch variant): H psi
+    on sampled sites against the oracle."""
+    ovl = require_gpu()
+    import torch
+    dims = (32, 32, 32, 64)
+    V = 32 * 32 * 32 * 64
+    p = {"f32": ovl.F32, "half": ovl.HALF}[prec]
+    ctx = ovl.Context(dims)
+    Ud = torch.zeros((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    ctx.gauge_generate(5, 0.25, out=Ud)
+    psi = ctx.source(ovl.SRC_GAUSS, seed=7)
+    h = ctx.wilson_dslash(psi, p)
+    print("case", dims, prec, "variant", ctx.tuning(), flush=True)
+    sites = _sample_sites(dims, 400, 3)
+    got = to_host(h)[sites]
+    del h
+    ref = WilsonKernel(dims, to_host(Ud), 1.4).hop_sites(to_host(psi), sites)
+    assert max_rel_elem(got, ref) < {"f32": 2e-6, "half": 5e-3}[prec]
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "half"])
+def test_dslash_24c48_12fields_sampled(prec):
+    """Twelve fields in one stencil launch on 24^3 x 48 (the batched form of
+    the eigSUMR workload, links eps 0.25 seed 3, autotuned launch variant):
+    H psi_f on sampled sites of every field against the oracle."""
+    ovl = require_gpu()
+    import torch
+    dims = (24, 24, 24, 48)
+    V = 24 * 24 * 24 * 48
+    p = {"f32": ovl.F32, "half": ovl.HALF}[prec]
+    ctx = ovl.Context(dims)
+    Ud = torch.zeros((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    ctx.gauge_generate(3, 0.25, out=Ud)
+    B = torch.stack([ctx.source(ovl.SRC_GAUSS, seed=300 + f) for f in range(12)])
+    h = ctx.wilson_dslash(B, p)
+    print("case", dims, prec, "variant", ctx.tuning(), flush=True)
+    sites = _sample_sites(dims, 120, 4)
+    got = to_host(h)[:, sites]
+    del h
+    ora = WilsonKernel(dims, to_host(Ud), 1.4)
+    Bh = to_host(B)
+    for f in range(12):
+        ref = ora.hop_sites(Bh[f], sites)
+        assert max_rel_elem(got[f], ref) < {"f32": 2e-6, "half": 5e-3}[prec], f
+    ctx.close()
