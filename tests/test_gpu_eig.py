@@ -109,3 +109,33 @@ def test_eigsumr_solves(lat):
     x, st, code = ctx.solve(to_dev(b), zg, p2)
     assert code == 0
     assert norm(b.reshape(-1) - D @ to_host(x).reshape(-1)) <= 1e-10 * norm(b)
+
+
+def test_eigsumr_trajectory_matches_oracle(lat):
+    """Three calculating solves (Alg. 5 collection, Alg. 6 at every k = m and
+    at the end of each middle solve) on the GPU and in the oracle, from the
+    same sources: after each solve the same number of diagonalisations, and
+    Ritz values and residual norms that agree (the relaxed sign calls round
+    differently on the two sides, so the Krylov vectors drift apart slowly)."""
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, lat)
+    p = ovl.solver_defaults(rho=1.4, mu=MU, tol=1e-10, eta_tilde=1e-3, eig_calc=1, use_deflation=1,
+                            n_eig=6, m_eig=30, f32_threshold=10.0)
+    sign = krylov.SignFunction(lat["k"], lat["z"])
+    ov = krylov.Overlap(sign, MU)
+    E = eig.EigSUMR(6, 30, MU)
+    for s in range(3):
+        b = synth.z2_source(lat["dims"], 60 + s)
+        _, _, code = ctx.solve(to_dev(b), zg, p)
+        assert code == 0
+        eig.gmresr_eigsumr(ov, b, 1e-10, 1e-3, E, calc=True)
+        info = ctx.eigspace_info()
+        vals, res = E.ritz()
+        print("solve", s, "ndiag", info["ndiag"], E.ndiag, "ritz", np.round(info["ritz"], 5), np.round(vals, 5))
+        assert info["ndiag"] == E.ndiag
+        assert np.abs(np.sort(info["ritz"]) - np.sort(vals)).max() < 1e-3
+        assert np.abs(np.sort(info["resid"]) - np.sort(res)).max() < 1e-3
+    # after the third solve every Ritz value sits on an eigenvalue of gamma_5 D
+    # (within its residual; not necessarily the six smallest)
+    for th, r in zip(info["ritz"], info["resid"]):
+        assert np.min(np.abs(lat["h"] - th)) <= min(1e-4, r)
