@@ -15,6 +15,10 @@ TEST INFRASTRUCTURE ONLY.
   relaxation eta_j = eps_A ||b|| / ||r_j|| of Sec. 3 with a floor on the
   accuracy, and the normalisation-monitoring restart of Sec. 2.
 * ``gmresr``         -- Alg. 3.
+* ``SpectralPreconditioner``, ``cgne``, ``gmresr_cg`` -- the deflated CGNE
+  of Sec. 4 (its printed algorithm) with the spectral preconditioner built
+  from approximate eigenvectors of H = gamma_5 D[mu], the CG relaxation of
+  Sec. 3, and GMRESR(relCG) (Alg. 3 with that middle solve).
 
 Readings where the paper is silent or garbled (each also listed in the design
 notes):
@@ -26,6 +30,12 @@ notes):
   omega_l |zeta_l| ||r|| / (2 sqrt(sigma_l)) <= eta ||b|| / N_Z, which bounds
   the inversion error of the rational function by eta ||b||
   (||K (K^2 + sigma)^{-1}|| <= 1 / (2 sqrt(sigma))).
+* CG relaxation (Sec. 3): eta_j = eps_A ||r_0|| sqrt(zeta_j) with zeta_j the
+  sum of ||r_i||^-2 over the residuals so far, r_0 the (preconditioned)
+  starting residual, capped at the same floor as SUMR; the closing
+  x = H Hhat^{-1} x_j uses accuracy eps_A.
+* CGNE for the GMRESR middle solve D u = r: D = gamma_5 H, so u solves
+  H u = gamma_5 r.
 * GMRESR's "compute c with ||A u - c|| < eps ||b|| ||u|| / ||r||": taken
   literally it lets each outer step open a residual gap of up to
   eps ||b|| ||u|| / ||r||, i.e. up to eps ||b|| / mu.  The rule used asks for
@@ -382,6 +392,83 @@ def gmresr_sumr(overlap, b, eps, eta_tilde, floor=1e-2, deflation=None, maxiter=
         x0 = None if deflation is None else deflation.x0(r)
         res = sumr_overlap(overlap, r, eta_tilde, x0=x0, eps_A=eta_tilde, floor=floor,
                            maxiter=maxiter)
+        return res.x, res.iters
+
+    return gmresr(apply_A, middle, b, 0.5 * eps)
+
+
+class SpectralPreconditioner:
+    """Hhat^{-1} = 1 + sum_i |psi_i><psi_i| (c / sqrt(m_i) - 1)  (Sec. 4), with
+    psi_i orthonormal approximate eigenvectors of H^2 and m_i their Ritz
+    values (psi_i, H^2 psi_i); c = sqrt(3)/2 as in the paper.  Applied on both
+    sides of H^2: with exact eigenvectors the n smallest eigenvalues of
+    Hhat^{-1} H^2 Hhat^{-1} become c^2 and the rest stay."""
+
+    def __init__(self, psis, ritz, c=np.sqrt(3.0) / 2.0):
+        self.psis = [np.asarray(p) for p in psis]
+        self.ritz = [float(m) for m in ritz]
+        self.c = float(c)
+
+    def __call__(self, v):
+        out = v.copy()
+        for p, m in zip(self.psis, self.ritz):
+            out = out + (self.c / np.sqrt(m) - 1.0) * dot(p, v) * p
+        return out
+
+
+class CGResult:
+    def __init__(self, x, iters, resid):
+        self.x, self.iters, self.resid = x, iters, resid
+
+
+def cgne(apply_H, b, tol, precond=None, eps_A=None, floor=1e-2, maxiter=10000):
+    """The preconditioned CGNE of Sec. 4 for H x = b (H Hermitian):
+    r_0 = p_0 = Hhat^{-1} b, x_0 = 0; per iteration z = Hhat^{-1} H^2
+    Hhat^{-1} p, alpha = (r, r) / (r, z), r -= alpha z, x += alpha p,
+    beta = (r', r') / (r, r), p = r' + beta p; until ||r|| < tol ||b||; then
+    x = H Hhat^{-1} x.  apply_H(v, eta) applies H with sign accuracy eta,
+    relaxed as in Sec. 3 for CG (module notes)."""
+    P = precond if precond is not None else (lambda v: v)
+    eps_A = tol if eps_A is None else eps_A
+    bn = norm(b)
+    r = P(b)
+    p = r.copy()
+    x = np.zeros_like(b)
+    rr = dot(r, r).real
+    r0n = np.sqrt(rr)
+    zeta = 1.0 / rr if rr > 0 else 0.0
+    it = 0
+    while np.sqrt(rr) >= tol * bn and it < maxiter:
+        eta = min(floor, eps_A * r0n * np.sqrt(zeta))
+        z = P(apply_H(apply_H(P(p), eta), eta))
+        alpha = rr / dot(r, z)
+        r = r - alpha * z
+        x = x + alpha * p
+        rr_new = dot(r, r).real
+        beta = rr_new / rr
+        p = r + beta * p
+        rr = rr_new
+        zeta += 1.0 / rr if rr > 0 else 0.0
+        it += 1
+    return CGResult(apply_H(P(x), eps_A), it, np.sqrt(rr))
+
+
+def gmresr_cg(overlap, b, eps, eta_tilde, floor=1e-2, precond=None, maxiter=10000):
+    """GMRESR(relCG): Alg. 3 with the Sec. 4 CGNE as the preconditioner for
+    D u = r (H u = gamma_5 r, H = gamma_5 D), optionally with the spectral
+    preconditioner; the outer c = D u as in gmresr_sumr."""
+    mu = overlap.mu
+    bnorm = norm(b)
+
+    def apply_A(u):
+        eta = min(1e-2, eps * bnorm / (2.0 * (1.0 - mu) * norm(u)))
+        return overlap(u, eta)
+
+    def H(v, eta):
+        return g5(overlap(v, eta))
+
+    def middle(r):
+        res = cgne(H, g5(r), eta_tilde, precond=precond, eps_A=eta_tilde, floor=floor, maxiter=maxiter)
         return res.x, res.iters
 
     return gmresr(apply_A, middle, b, 0.5 * eps)
