@@ -80,7 +80,7 @@ typedef struct {
     int64_t dslash_calls[3];
     int64_t sign_calls[3];
     int64_t mscg_iters;
-    int64_t sumr_iters;
+    int64_t sumr_iters;       /* middle-solve iterations (SUMR or CG)            */
     int64_t gmresr_steps;
     int64_t restarts;
     double computed_relres;     /* solver: final recurrence residual / ||b|| */
@@ -108,6 +108,14 @@ typedef struct {
     int32_t verbose;
     double eig_eps;        /* eigSUMR: target eigenvector accuracy (Sec. 6: 1e-4)    */
     double delta_split;    /* eigSUMR: pair splitting in M (Sec. 5), 0 < delta < 1/2 */
+    int32_t middle_cg;     /* 0: relSUMR middle solve (Algs. 1, 2); 1: relCG, the
+                              preconditioned CGNE of Sec. 4 on H^2 = D^+ D for
+                              H u = gamma_5 r, relaxed as in Sec. 3 for CG; with
+                              use_deflation the spectral preconditioner of Sec. 4 is
+                              built from the held eigenspace (Rayleigh-Ritz vectors
+                              of H^2 in its span, c = sqrt(3)/2).  eig_calc needs
+                              the SUMR middle solve (collecting eigenvectors during
+                              CG is not provided).                               */
 } ovl_solver_params;
 
 typedef struct ovl_context ovl_context;

@@ -69,7 +69,7 @@ class SolverParams(ctypes.Structure):
                 ("use_deflation", ctypes.c_int32), ("eig_calc", ctypes.c_int32),
                 ("n_eig", ctypes.c_int32), ("m_eig", ctypes.c_int32), ("k_recalc", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("eig_eps", ctypes.c_double),
-                ("delta_split", ctypes.c_double)]
+                ("delta_split", ctypes.c_double), ("middle_cg", ctypes.c_int32)]
 
 
 EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults", "ovl_device_bytes",

@@ -86,6 +86,7 @@ void ovl_solver_defaults(ovl_solver_params *p)
     p->verbose = 0;
     p->eig_eps = 1e-4;
     p->delta_split = 0.1;
+    p->middle_cg = 0;
 }
 
 ovl_status ovl_create(const int32_t dims[4], void *hip_stream, ovl_context **out)

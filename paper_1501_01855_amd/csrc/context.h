@@ -34,6 +34,12 @@ struct EigSpace {
     int ndefl = 0;
     double2 *P = nullptr, *DP = nullptr;
     std::vector<double> dn2;
+    // spectral preconditioner (Sec. 4): orthonormal vectors S and the factors
+    // c / sqrt(m_i) - 1 of their Ritz values m_i of H^2
+    bool spec_ready = false;
+    int nspec = 0;
+    double2 *S = nullptr;
+    std::vector<double> spec_f;
 };
 
 struct GraphRec;

@@ -56,6 +56,7 @@ void eig_configure(Context &c, int n, int m, double mu, double delta, double eps
         e.ritz.clear();
         e.resid.clear();
         e.defl_ready = false;
+        e.spec_ready = false;
     }
     e.n = n;
     e.m = m;
@@ -137,6 +138,7 @@ void eig_diagonalise(Context &c)
     e.k = n;
     e.ndiag += 1;
     e.defl_ready = false;
+    e.spec_ready = false;
 }
 
 // Eq. (bound) of Sec. 5.1 as a sign-function accuracy.
@@ -166,6 +168,7 @@ void eig_recompute(Context &c, double rho, const ovl_zolo &z, double eta, ovl_st
         overlap_f64(c, rho, e.mu, z, e.V + off, e.VD + off, 1, eta, OVL_F64, 100000, st);
     }
     e.defl_ready = false;
+    e.spec_ready = false;
 }
 
 // Sec. 4: rotate so that (psi'_i, gamma_5 D psi'_j) is diagonal.
@@ -207,6 +210,66 @@ void eig_project(Context &c, const double2 *b, double2 *x0, double2 *Dx0)
     }
     rotate_f64(c, e.P, n, a, 1, x0, 0.0);
     rotate_f64(c, e.DP, n, a, 1, Dx0, 0.0);
+}
+
+// Sec. 4, the spectral preconditioner Hhat^{-1} = 1 + sum_i |s_i><s_i| (c / sqrt(m_i) - 1),
+// c = sqrt(3)/2.  Its vectors are the Rayleigh-Ritz vectors of H^2 = D^+ D in
+// the span of the held eigenspace V (using V^D = D V: E = V^H V = R^H R, the
+// eigenpairs (m_i, y_i) of R^{-H} (V^D)^H V^D R^{-1}, s_i = V R^{-1} y_i), so
+// that they are orthonormal as the formula assumes; for exact eigenvectors
+// they are the eigenvectors themselves and m_i their eigenvalues of H^2.
+static void spectral_prepare(Context &c)
+{
+    EigSpace &e = c.eig;
+    const int n = std::min(e.n, e.k);
+    OVL_REQUIRE(n >= 1, OVL_ERR_STATE, "spectral preconditioner: the eigenspace is empty");
+    const size_t FB = field_bytes(c.g, OVL_F64);
+    std::vector<cplx<double>> g;
+    gram_f64(c, e.V, n, e.V, n, false, g);
+    const std::vector<zc> E = to_z(g);
+    gram_f64(c, e.VD, n, e.VD, n, false, g);
+    const std::vector<zc> MD = to_z(g);
+    std::vector<zc> R;
+    OVL_REQUIRE(dense::cholesky_upper(n, E, R), OVL_ERR_BREAKDOWN,
+                "spectral preconditioner: eigenspace vectors are linearly dependent");
+    const std::vector<zc> Rinv = dense::inv_upper(n, R);
+    const std::vector<zc> G = dense::matmul_ah(n, n, n, Rinv, dense::matmul(n, n, n, MD, Rinv));
+    std::vector<double> m;
+    std::vector<zc> Y;
+    dense::eigh(n, G, m, Y);
+    const std::vector<zc> C = dense::matmul(n, n, n, Rinv, Y);
+    e.S = (double2 *)c.buf("eig_S", FB * n);
+    rotate_f64(c, e.V, n, from_z(C), n, e.S, 0.0);
+    const double cc = 0.5 * std::sqrt(3.0);
+    e.spec_f.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        OVL_REQUIRE(m[i] > 0.0, OVL_ERR_BREAKDOWN, "spectral preconditioner: non-positive Ritz value of H^2");
+        e.spec_f[i] = cc / std::sqrt(m[i]) - 1.0;
+    }
+    e.nspec = n;
+    e.spec_ready = true;
+}
+
+bool spectral_available(const Context &c)
+{
+    return c.eig.n > 0 && c.eig.k >= 1 && c.eig.ndiag > 0;
+}
+
+// out_f = Hhat^{-1} v_f for nf packed FP64 fields (out may equal v).
+void spectral_apply(Context &c, const double2 *v, double2 *out, int nf)
+{
+    EigSpace &e = c.eig;
+    if (!e.spec_ready) spectral_prepare(c);
+    const int n = e.nspec;
+    std::vector<cplx<double>> d;
+    multidot_f64(c, e.S, n, v, nf, d);   // d[f][i] = (s_i, v_f)
+    for (int f = 0; f < nf; ++f)
+        for (int i = 0; i < n; ++i) {
+            cplx<double> &x = d[(size_t)f * n + i];
+            x = {x.re * e.spec_f[i], x.im * e.spec_f[i]};
+        }
+    if (out != v) copy_fields(c, v, out, nf, OVL_F64);
+    multiaxpy_f64(c, e.S, n, d.data(), out, nf);
 }
 
 }  // namespace ovl

@@ -49,6 +49,9 @@ void eig_diagonalise(Context &c);
 double eig_sign_accuracy(const Context &c);
 void eig_recompute(Context &c, double rho, const ovl_zolo &z, double eta, ovl_stats *st);
 void eig_project(Context &c, const double2 *b, double2 *x0, double2 *Dx0);
+// the spectral preconditioner of Sec. 4 from the held eigenspace
+bool spectral_available(const Context &c);
+void spectral_apply(Context &c, const double2 *v, double2 *out, int nf);
 
 // Generators (gen.hip).
 void gauge_generate(Context &c, uint64_t seed, double eps, double *canon_out);

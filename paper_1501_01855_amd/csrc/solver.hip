@@ -416,12 +416,119 @@ static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, do
     }
 }
 
+// h_f = H w_f = gamma_5 D[mu] w_f for the fields with eta[f] > 0 (sign
+// accuracy eta[f], precision from the ladder).
+static void apply_H(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *w, double2 *h,
+                    int nf, const double *eta, ovl_stats *st)
+{
+    overlap_impl(c, prm.rho, prm.mu, z, w, h, nf, eta, prec_for(prm, min_active(eta, nf)), prm.max_mscg, st, true);
+    gamma5_f64(c, h, nf);
+}
+
+// relCG: the preconditioned CGNE of Sec. 4 for H x_f = b_f (H = gamma_5 D[mu]
+// Hermitian) on the fields with mask[f]:
+//   r = p = Hhat^{-1} b, x = 0;
+//   z = Hhat^{-1} H^2 Hhat^{-1} p, alpha = (r, r) / (r, z), r -= alpha z,
+//   x += alpha p, beta = (r', r') / (r, r), p = r' + beta p, until
+//   ||r|| < tol ||b||; then x = H Hhat^{-1} x.
+// Each H is applied with the CG relaxation of Sec. 3,
+// eta_j = min(floor, epsA ||r_0|| sqrt(sum_{i<=j} ||r_i||^-2)); the closing H
+// with accuracy epsA.  Hhat^{-1} is the identity unless precond.
+static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *b, double2 *x, int nf,
+                 const std::vector<int> &mask, double tol, double epsA, bool precond, ovl_stats *st)
+{
+    const size_t FB = field_bytes(c.g, OVL_F64);
+    double2 *r = (double2 *)c.buf("cg_r", FB * nf);
+    double2 *p = (double2 *)c.buf("cg_p", FB * nf);
+    double2 *xj = (double2 *)c.buf("cg_x", FB * nf);
+    double2 *w = (double2 *)c.buf("cg_w", FB * nf);
+    double2 *t = (double2 *)c.buf("cg_t", FB * nf);
+    auto P = [&](const double2 *in, double2 *out) {
+        if (precond)
+            spectral_apply(c, in, out, nf);
+        else if (out != in)
+            copy_fields(c, in, out, nf, OVL_F64);
+    };
+    std::vector<double> bn, rr(nf, 0.0), r0n(nf, 0.0), zeta(nf, 0.0);
+    norms(c, b, nf, bn);
+    P(b, r);
+    copy_fields(c, r, p, nf, OVL_F64);
+    zero_fields(c, xj, nf, OVL_F64);
+    std::vector<int> act(nf, 0), its(nf, 0);
+    {
+        std::vector<double> n0;
+        norms(c, r, nf, n0);
+        for (int f = 0; f < nf; ++f) {
+            rr[f] = n0[f] * n0[f];
+            r0n[f] = n0[f];
+            zeta[f] = rr[f] > 0.0 ? 1.0 / rr[f] : 0.0;
+            act[f] = mask[f] != 0 && bn[f] > 0.0;
+        }
+    }
+    std::vector<double> eta(nf, 0.0);
+    while (true) {
+        int nact = 0;
+        for (int f = 0; f < nf; ++f) {
+            if (act[f] && (std::sqrt(rr[f]) < tol * bn[f] || its[f] >= prm.max_middle)) act[f] = 0;
+            nact += act[f];
+        }
+        if (nact == 0) break;
+        for (int f = 0; f < nf; ++f)
+            eta[f] = act[f] ? std::fmin(prm.relax_floor, epsA * r0n[f] * std::sqrt(zeta[f])) : 0.0;
+        P(p, w);
+        apply_H(c, z, prm, w, t, nf, eta.data(), st);
+        apply_H(c, z, prm, t, w, nf, eta.data(), st);
+        P(w, t);   // t = Hhat^{-1} H^2 Hhat^{-1} p
+        std::vector<zc> rz;
+        dots(c, r, t, nf, rz);
+        std::vector<zc> ma(nf, 0.0), pa(nf, 0.0), one(nf, 1.0);
+        for (int f = 0; f < nf; ++f)
+            if (act[f]) {
+                if (!(std::abs(rz[f]) > 0.0) || !std::isfinite(std::abs(rz[f])))
+                    throw Error{OVL_ERR_BREAKDOWN, "CG: (r, z) zero or non-finite"};
+                const zc alpha = rr[f] / rz[f];
+                ma[f] = -alpha;
+                pa[f] = alpha;
+            }
+        axpby(c, ma, t, one, r, nf);
+        axpby(c, pa, p, one, xj, nf);
+        std::vector<double> rn;
+        norms(c, r, nf, rn);
+        std::vector<zc> a1(nf, 0.0), bb(nf, 1.0);
+        for (int f = 0; f < nf; ++f)
+            if (act[f]) {
+                const double rr_new = rn[f] * rn[f];
+                if (!std::isfinite(rr_new)) throw Error{OVL_ERR_BREAKDOWN, "CG: non-finite residual"};
+                a1[f] = 1.0;
+                bb[f] = rr_new / rr[f];
+                rr[f] = rr_new;
+                zeta[f] += rr_new > 0.0 ? 1.0 / rr_new : 0.0;
+                its[f] += 1;
+                if (st) st[f].sumr_iters += 1;
+            }
+        axpby(c, a1, r, bb, p, nf);   // p = r + beta p
+    }
+    // x = H Hhat^{-1} x_j
+    P(xj, w);
+    for (int f = 0; f < nf; ++f) eta[f] = mask[f] && bn[f] > 0.0 ? epsA : 0.0;
+    apply_H(c, z, prm, w, t, nf, eta.data(), st);
+    std::vector<zc> a(nf, 0.0), b0(nf, 1.0);
+    for (int f = 0; f < nf; ++f)
+        if (mask[f] && bn[f] > 0.0) {
+            a[f] = 1.0;
+            b0[f] = 0.0;
+        }
+    axpby(c, a, t, b0, x, nf);
+}
+
 ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *b, double2 *x,
                        int nf, ovl_stats *st)
 {
     OVL_REQUIRE(nf >= 1 && nf <= MAXF, OVL_ERR_ARG, "too many right-hand sides in one batch");
     OVL_REQUIRE(!(prm.eig_calc && nf > 1), OVL_ERR_ARG,
                 "eigSUMR collects from one right-hand side at a time (solve calculating right-hand sides singly)");
+    OVL_REQUIRE(!(prm.eig_calc && prm.middle_cg), OVL_ERR_UNSUPPORTED,
+                "collecting eigenvectors during a CG middle solve (eigCG) is not provided; use the SUMR middle solve");
     const auto t0 = std::chrono::steady_clock::now();
     const double mu = prm.mu;
     const double rhoK = prm.rho;
@@ -457,6 +564,14 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
             C.push_back((double2 *)c.buf("g_C" + std::to_string(i), FB * nf));
             Uv.push_back((double2 *)c.buf("g_U" + std::to_string(i), FB * nf));
         }
+        if (prm.middle_cg) {
+            // middle solve D u = r with relCG: H u = gamma_5 r (Sec. 4)
+            copy_fields(c, r, bp, nf, OVL_F64);
+            gamma5_f64(c, bp, nf);
+            const bool pre = prm.use_deflation && spectral_available(c);
+            zero_fields(c, uu, nf, OVL_F64);
+            cgne(c, z, prm, bp, uu, nf, active, prm.eta_tilde, prm.eta_tilde, pre, st);
+        } else {
         // middle solve D u = r to relative accuracy eta_tilde: (1 + rho U) u = 2 r/(1 + mu)
         {
             std::vector<zc> a(nf, 2.0 / (1.0 + mu)), b0(nf, 0.0);
@@ -481,6 +596,7 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
             eig_diagonalise(c);   // the closing Alg. 6 of Alg. 5
             if (c.eig.ndiag > 0 && prm.k_recalc > 0 && c.eig.ndiag % prm.k_recalc == 0)
                 eig_recompute(c, rhoK, z, 1e-12, nullptr);
+        }
         }
         // c = D u, to ||D u - c|| <= eps ||b|| / 4
         std::vector<double> un;
