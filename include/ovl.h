@@ -113,7 +113,9 @@ typedef struct {
                               H u = gamma_5 r, relaxed as in Sec. 3 for CG; with
                               use_deflation the spectral preconditioner of Sec. 4 is
                               built from the held eigenspace (Rayleigh-Ritz vectors
-                              of H^2 in its span, c = sqrt(3)/2).  eig_calc needs
+                              of H^2 in its span, c = sqrt(3)/2).  Its sign calls
+                              use FP32 at most (FP16 rounding swamps the lowest
+                              eigenvalues of H^2, ~mu^2).  eig_calc needs
                               the SUMR middle solve (collecting eigenvectors during
                               CG is not provided).                               */
 } ovl_solver_params;

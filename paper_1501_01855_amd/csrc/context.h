@@ -89,6 +89,7 @@ struct Context {
     std::vector<hipEvent_t> free_events;
     ProfileSlot slots[KERN_COUNT][3];
     int64_t last_mscg_iters = 0;
+    int64_t precision_retries = 0;   // sign calls redone one precision up after a breakdown
     std::vector<int64_t> last_field_iters;   // per field, last sign call
 
     unsigned *grid_counters = nullptr;   // zero between launches (reset by the last block)

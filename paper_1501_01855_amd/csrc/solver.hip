@@ -97,15 +97,28 @@ static void sign_f64(Context &c, double rho, const ovl_zolo &zin, const double2 
             if (e > 0.0) e -= z.delta;   // >= 3/4 of the accuracy asked for
     const double *eta = eta_v.data();
     ovl_stats *agg = per_field ? nullptr : st;
-    if (prec == OVL_F64) {
-        sign_mscg(c, rho, z, in, s, nf, eta, prec, maxiter, agg);
-    } else {
-        const size_t FB = field_bytes(c.g, prec) * nf;
-        void *a = c.buf("u_lo_in", FB);
-        void *b = c.buf("u_lo_out", FB);
-        convert_spinor(c, in, OVL_F64, a, prec, nf);
-        sign_mscg(c, rho, z, a, b, nf, eta, prec, maxiter, agg);
-        convert_spinor(c, b, prec, s, OVL_F64, nf);
+    // A multi-shift CG that breaks down in reduced precision (the curvature
+    // (p, (K^2 + sigma) p) of a direction near the bottom of the spectrum is
+    // below the storage rounding of K^2 p) is redone one precision up; the
+    // accuracy asked for is unchanged.
+    while (true) {
+        try {
+            if (prec == OVL_F64) {
+                sign_mscg(c, rho, z, in, s, nf, eta, prec, maxiter, agg);
+            } else {
+                const size_t FB = field_bytes(c.g, prec) * nf;
+                void *a = c.buf("u_lo_in", FB);
+                void *b = c.buf("u_lo_out", FB);
+                convert_spinor(c, in, OVL_F64, a, prec, nf);
+                sign_mscg(c, rho, z, a, b, nf, eta, prec, maxiter, agg);
+                convert_spinor(c, b, prec, s, OVL_F64, nf);
+            }
+            break;
+        } catch (const Error &e) {
+            if (e.code != OVL_ERR_BREAKDOWN || prec == OVL_F64) throw;
+            prec = prec == OVL_HALF ? OVL_F32 : OVL_F64;
+            c.precision_retries += 1;
+        }
     }
     if (per_field && st)
         for (int f = 0; f < nf; ++f)
@@ -417,11 +430,17 @@ static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, do
 }
 
 // h_f = H w_f = gamma_5 D[mu] w_f for the fields with eta[f] > 0 (sign
-// accuracy eta[f], precision from the ladder).
+// accuracy eta[f], precision from the ladder, FP32 at most: CG works on
+// H^2 = D^+ D, whose lowest eigenvalues (about mu^2, 4e-4 at mu = 0.02) are
+// below the uncorrelated rounding of FP16 storage (~5e-4 of a site's largest
+// component), and the CG then diverges -- seen on the 16^3 x 32 workload;
+// SUMR works on D itself, whose singular values are >= mu).
 static void apply_H(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *w, double2 *h,
                     int nf, const double *eta, ovl_stats *st)
 {
-    overlap_impl(c, prm.rho, prm.mu, z, w, h, nf, eta, prec_for(prm, min_active(eta, nf)), prm.max_mscg, st, true);
+    int prec = prec_for(prm, min_active(eta, nf));
+    if (prec == OVL_HALF) prec = OVL_F32;
+    overlap_impl(c, prm.rho, prm.mu, z, w, h, nf, eta, prec, prm.max_mscg, st, true);
     gamma5_f64(c, h, nf);
 }
 
@@ -648,7 +667,8 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
                 if (st) st[f].gmresr_steps += 1;
             }
         if (prm.verbose)
-            std::fprintf(stderr, "[ovl] GMRESR step %d: ||r||/||b|| of field 0 = %.3e\n", i + 1, rn[0] / bn[0]);
+            std::fprintf(stderr, "[ovl] GMRESR step %d: ||r||/||b|| of field 0 = %.3e (sign calls redone one precision up so far: %lld)\n",
+                         i + 1, rn[0] / bn[0], (long long)c.precision_retries);
     }
     OVL_HIP(hipStreamSynchronize(c.stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
