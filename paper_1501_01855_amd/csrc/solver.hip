@@ -526,6 +526,9 @@ static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, co
                 if (st) st[f].sumr_iters += 1;
             }
         axpby(c, a1, r, bb, p, nf);   // p = r + beta p
+        if (prm.verbose && its[0] % 20 == 0)
+            std::fprintf(stderr, "[ovl] CG iteration %d: ||r||/||b|| of field 0 = %.3e\n", its[0],
+                         std::sqrt(rr[0]) / std::max(bn[0], 1e-300));
     }
     // x = H Hhat^{-1} x_j
     P(xj, w);
