@@ -485,6 +485,7 @@ static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, co
         }
     }
     std::vector<double> eta(nf, 0.0);
+    int loops = 0;
     while (true) {
         int nact = 0;
         for (int f = 0; f < nf; ++f) {
@@ -526,9 +527,13 @@ static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, co
                 if (st) st[f].sumr_iters += 1;
             }
         axpby(c, a1, r, bb, p, nf);   // p = r + beta p
-        if (prm.verbose && its[0] % 20 == 0)
-            std::fprintf(stderr, "[ovl] CG iteration %d: ||r||/||b|| of field 0 = %.3e\n", its[0],
-                         std::sqrt(rr[0]) / std::max(bn[0], 1e-300));
+        if (prm.verbose && ++loops % 20 == 0) {
+            double worst = 0.0;
+            for (int f = 0; f < nf; ++f)
+                if (act[f]) worst = std::max(worst, std::sqrt(rr[f]) / bn[f]);
+            std::fprintf(stderr, "[ovl] CG iteration %d: %d fields active, largest ||r||/||b|| = %.3e\n", loops, nact,
+                         worst);
+        }
     }
     // x = H Hhat^{-1} x_j
     P(xj, w);
