@@ -310,16 +310,6 @@ def eig_leg(torch, ovl, n_calc=3):
                                "sumr_iters_per_field": [s.sumr_iters for s in st],
                                "mscg_iters_per_field": [s.mscg_iters for s in st]}
     out["solves_per_s_including_eig_setup"] = (12 + 0) / (dt + out["eig_setup_s"])
-    # GMRESR(relCG) on the first source, with the spectral preconditioner of
-    # Sec. 4 built from the same eigenspace and without it
-    for name, defl in (("relcg_preconditioned_single", 1), ("relcg_undeflated_single", 0)):
-        pc = params(True, 0, defl)
-        pc.middle_cg = 1
-        t0 = time.perf_counter()
-        _, st, code = ctx.solve(B[0:1], zolo, pc)
-        torch.cuda.synchronize()
-        out[name] = {"status": code, "seconds": time.perf_counter() - t0, **st[0].as_dict()}
-        print(f"[bench] {name} done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     _, st, code = ctx.solve(B[0:1], zolo, params(True, 0, 0))
     torch.cuda.synchronize()
