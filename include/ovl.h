@@ -6,7 +6,8 @@
  *     D[mu] = (1 + mu + (1 - mu) gamma_5 sign(K)) / 2          (Sec. 1, eq. 1)
  * with the Wilson kernel K = gamma_5 D_W(-rho)                  (Sec. 1, eq. 2)
  * and solves D[mu] x = b with GMRESR(relSUMR)                   (Secs. 2-3, Algs. 1-3)
- * with eigSUMR deflation                                        (Secs. 4-5, Algs. 5-6).
+ * with eigSUMR deflation                                        (Secs. 4-5, Algs. 5-6),
+ * or with GMRESR(relCG) and the spectral preconditioner          (Sec. 4, its CGNE).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -34,7 +35,7 @@
  *           creation (0 = the null stream).  Operator calls are asynchronous;
  *           solver calls and calls that return host data block until done.
  * Precision: OVL_F64 (FP64 storage and arithmetic), OVL_F32 (FP32 storage and
- *           arithmetic, FP64 reductions and scalars), OVL_HALF (BF16 links,
+ *           arithmetic, FP64 reductions and scalars), OVL_HALF (FP16 links,
  *           FP16 spinors with one FP32 scale per site, FP32 arithmetic).
  */
 #ifndef OVL_H
@@ -93,12 +94,12 @@ typedef struct {
     double mu;             /* overlap mass parameter, 0 <= mu < 1                   */
     double tol;            /* outer target ||b - D x|| <= tol ||b|| (Alg. 3 eps)    */
     double eta_tilde;      /* middle-solve relative accuracy (Alg. 3 eta~)          */
-    double relax_floor;    /* worst sign accuracy allowed in relSUMR (Sec. 3: 1e-2) */
+    double relax_floor;    /* worst sign accuracy allowed in the middle solve (Sec. 3: 1e-2) */
     double f32_threshold;  /* sign accuracies >= this use OVL_F32 (Sec. 3: ~1e-7, larger) */
     double half_threshold; /* sign accuracies >= this use OVL_HALF; > 1 disables    */
     double norm_restart;   /* SUMR restart when | ||q|| - 1 | exceeds this (Sec. 6: 0.1) */
     int32_t max_outer;     /* GMRESR steps                                          */
-    int32_t max_middle;    /* SUMR iterations per middle solve                      */
+    int32_t max_middle;    /* SUMR or CG iterations per middle solve                */
     int32_t max_mscg;      /* multi-shift CG iterations per sign call               */
     int32_t use_deflation; /* 1: start middle solves from the eigenspace projection (Sec. 4) */
     int32_t eig_calc;      /* 1: collect eigSUMR vectors during this solve (Alg. 5)  */
