@@ -670,7 +670,7 @@ template <typename ST, typename GT, int EPI>
 __global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT *__restrict__ U, TileShape ts)
 {
     __shared__ ST Lsp[Planes<ST>::n * LDS_SITES];   // the tile's stored spinors at the current slice
-    __shared__ float Lsc[std::is_same<ST, h8>::value ? LDS_SITES : 1];
+    __shared__ float Lsc[LDS_SITES];                 // their scales (FP16 storage; unused otherwise)
     const Geom &g = a.g;
     const unsigned X = gridDim.x, Y = gridDim.y;
     const unsigned lin = blockIdx.y * X + blockIdx.x;
