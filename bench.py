@@ -398,8 +398,9 @@ def dslash_alone(torch, ovl, tuning=None, reps=50):
 
 def cpu_baseline(mscg_iters_per_solve):
     """The oracle (FP64, C stencil + numpy) on a bounded sample of the same
-    workload: 12 multi-shift CG iterations with all 20 shifts active on the
-    16^3 x 32 field, scaled by the GPU solve's multi-shift iteration count."""
+    workload: 96 multi-shift CG iterations (about 15 s on the host) with all
+    20 shifts active on the 16^3 x 32 field, scaled by the GPU solve's
+    multi-shift iteration count."""
     import numpy as np
     import synth
     from oracle import krylov
@@ -409,7 +410,7 @@ def cpu_baseline(mscg_iters_per_solve):
     k = WilsonKernel(DIMS, U, RHO)
     z = Zolotarev(NZ, 0.6, 8.0 - RHO)
     b = synth.gaussian_source(DIMS, 102)
-    iters = 12
+    iters = 96
     t0 = time.perf_counter()
     krylov.multishift_cg(k.K2s, z.sigma, b, np.full(NZ, 1e-300), maxiter=iters)
     dt = time.perf_counter() - t0
