@@ -1,0 +1,98 @@
+"""GPU edge cases and full-size checks in the benchmark's launch
+configurations: empty and oversized batches, the largest accepted batch, the
+reduced-precision K at 16^3 x 32 on sampled sites against the oracle, and
+sign(K)^2 = 1 at 16^3 x 32 in every storage precision (a property that holds
+at any size, Sec. 1)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.lattice import WilsonKernel
+from gpu_util import max_rel_elem, rel, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+MAX_NRHS = 16
+
+
+def test_empty_and_oversized_batches_rejected():
+    ovl = require_gpu()
+    import torch
+    dims = (4, 4, 4, 4)
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(synth.gauge_field(dims, 1, 0.3)))
+    z = ovl.zolotarev_coeffs(8, 0.5, 6.6)
+    empty = torch.zeros((0, 256, 4, 3), dtype=torch.complex128, device="cuda")
+    big = torch.zeros((MAX_NRHS + 1, 256, 4, 3), dtype=torch.complex128, device="cuda")
+    for psi in (empty, big):
+        for call in (lambda: ctx.wilson_dslash(psi), lambda: ctx.kernel_K_apply(psi, 1.4),
+                     lambda: ctx.sign(psi, 1.4, z, 1e-6), lambda: ctx.overlap(psi, 1.4, 0.05, z, 1e-6)):
+            with pytest.raises(ovl.OvlError) as e:
+                call()
+            assert e.value.code == -1
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "half"])
+def test_largest_batch_matches_oracle(prec):
+    """MAX_NRHS fields in one stencil launch on a ragged lattice, each against
+    the oracle."""
+    ovl = require_gpu()
+    dims = (6, 4, 6, 5)
+    p = {"f64": ovl.F64, "f32": ovl.F32, "half": ovl.HALF}[prec]
+    U = synth.gauge_field(dims, 21, 0.4)
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(U))
+    psi = np.stack([synth.gaussian_source(dims, 500 + f) for f in range(MAX_NRHS)])
+    h = to_host(ctx.wilson_dslash(to_dev(psi), prec=p))
+    ora = WilsonKernel(dims, U, 1.4)
+    tol = {"f64": 1e-14, "f32": 2e-6, "half": 5e-3}[prec]
+    for f in range(MAX_NRHS):
+        assert max_rel_elem(h[f], ora.hop(psi[f])) < tol, f
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    """The 16^3 x 32 workload: links eps 0.25 seed 2, ten exact kernel modes,
+    N_Z = 20 on [|lambda_10|, lambda_max], Gaussian source seed 102."""
+    ovl = require_gpu()
+    dims = (16, 16, 16, 32)
+    V = int(np.prod(dims))
+    ctx = ovl.Context(dims)
+    Ud = to_dev(np.zeros((V, 4, 3, 3)))
+    ctx.gauge_generate(2, 0.25, out=Ud)
+    ev, lmax = ctx.lowmodes_compute(1.4, 10, tol=1e-10)
+    z = ovl.zolotarev_coeffs(20, max(abs(e) for e in ev), lmax)
+    yield dict(ctx=ctx, Ud=Ud, z=z, dims=dims, V=V, ovl=ovl)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "half"])
+def test_K_16c32_sampled(c2, prec):
+    """K in FP32 / FP16 storage at 16^3 x 32, autotuned as in the solve, on
+    sampled sites against the oracle."""
+    ovl, ctx = c2["ovl"], c2["ctx"]
+    p = {"f32": ovl.F32, "half": ovl.HALF}[prec]
+    psi = synth.gaussian_source(c2["dims"], 102)
+    k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4, prec=p))
+    rng = np.random.default_rng(1)
+    V = c2["V"]
+    sites = np.unique(np.concatenate([[0, V - 1, 15, 16 * 16 * 16 - 1, 16 * 16 * 16], rng.integers(0, V, 300)]))
+    ref = WilsonKernel(c2["dims"], to_host(c2["Ud"]), 1.4).K_sites(psi, sites)
+    err = max_rel_elem(k[sites], ref)
+    print("case", prec, "max rel elem", err, "variants", ctx.tuning(), flush=True)
+    assert err < {"f32": 2e-6, "half": 5e-3}[prec]
+
+
+@pytest.mark.parametrize("prec,eta,tol", [("f32", 1e-6, 1e-5), ("half", 1e-2, 2e-2)])
+def test_sign_squared_16c32(c2, prec, eta, tol):
+    """sign(K)^2 psi = psi at 16^3 x 32 with the ten exact modes, in the
+    reduced storage precisions the solver uses, to the accuracy asked for."""
+    ovl, ctx = c2["ovl"], c2["ctx"]
+    p = {"f32": ovl.F32, "half": ovl.HALF}[prec]
+    psi = to_dev(synth.gaussian_source(c2["dims"], 103))
+    s1, st = ctx.sign(psi, 1.4, c2["z"], eta, prec=p)
+    s2, _ = ctx.sign(s1, 1.4, c2["z"], eta, prec=p)
+    err = rel(to_host(s2), to_host(psi))
+    print("case", prec, "sign^2 error", err, "mscg iterations", st.mscg_iters, flush=True)
+    assert err < tol
