@@ -59,8 +59,8 @@ def parse():
                     help="sign accuracies at or above this use FP16 storage (> 1 disables)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware counters: a 1 GiB elementwise copy (calibration), "
-                         "one sign-function call per precision on the 16^3x32 workload and the "
-                         "stand-alone 32^3x64 stencil")
+                         "one sign-function call per precision on the 16^3x32 workload, the "
+                         "stand-alone 32^3x64 stencil and the 12-field 24^3x48 stencil")
     ap.add_argument("--eig", action="store_true",
                     help="add the eigSUMR leg on 24^3x48 (12 point sources, calculating solves then a "
                          "deflated batch; several minutes)")
@@ -115,6 +115,17 @@ def profile_run(torch, ovl, tuning):
     for prec in (ovl.F32, ovl.HALF):
         for _ in range(10):
             ctx.wilson_dslash(psi, prec)
+    torch.cuda.synchronize()
+    ctx.close()
+    # the 12-field stencil of the eigSUMR workload (24^3 x 48, links seed 3)
+    ctx = ovl.Context((24, 24, 24, 48))
+    ctx.gauge_generate(3, 0.25)
+    if tuning and "24x24x24x48" in tuning:
+        ctx.set_tuning(tuning["24x24x24x48"])
+    B = torch.stack([ctx.source(ovl.SRC_GAUSS, seed=300 + f) for f in range(12)])
+    for prec in (ovl.F32, ovl.HALF):
+        for _ in range(10):
+            ctx.wilson_dslash(B, prec)
     torch.cuda.synchronize()
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -369,15 +380,8 @@ def adjoint_leg(torch, ovl):
     return out
 
 
-def dslash_alone(torch, ovl, tuning=None, reps=50):
-    """The hopping stencil alone on 32^3 x 64 (FP32 and FP16 storage)."""
-    dims = (32, 32, 32, 64)
-    ctx = ovl.Context(dims)
-    if tuning and "32x32x32x64" in tuning:
-        ctx.set_tuning(tuning["32x32x32x64"])
-    ctx.gauge_generate(5, 0.25)
-    psi = ctx.source(ovl.SRC_GAUSS, seed=7)
-    res = {"lattice": "32^3x64"}
+def _stencil_rates(torch, ovl, ctx, psi, reps):
+    res = {}
     for prec in (ovl.F32, ovl.HALF):
         ctx.wilson_dslash(psi, prec)
         torch.cuda.synchronize()
@@ -391,7 +395,29 @@ def dslash_alone(torch, ovl, tuning=None, reps=50):
         res[PREC_NAMES[prec]] = {"launches": p["launches"], "avg_us": 1e3 * p["ms"] / p["launches"],
                                  "bytes_per_launch": p["bytes"] / p["launches"], "GBps": gbs,
                                  "frac_of_peak": gbs / HBM_PEAK_GBS}
-    res["tuning"] = ctx.tuning()
+    return res
+
+
+def dslash_alone(torch, ovl, tuning=None, reps=50):
+    """The hopping stencil alone (FP32 and FP16 storage) on 32^3 x 64 (links
+    seed 5, one Gaussian field) and, in its batched form, on twelve fields of
+    24^3 x 48 (links seed 3): algorithmic bytes are the spinors in and out of
+    every field plus one read of the links per launch."""
+    ctx = ovl.Context((32, 32, 32, 64))
+    if tuning and "32x32x32x64" in tuning:
+        ctx.set_tuning(tuning["32x32x32x64"])
+    ctx.gauge_generate(5, 0.25)
+    psi = ctx.source(ovl.SRC_GAUSS, seed=7)
+    res = {"lattice": "32^3x64", **_stencil_rates(torch, ovl, ctx, psi, reps)}
+    res["tuning"] = {"32x32x32x64": ctx.tuning()}
+    ctx.close()
+    ctx = ovl.Context((24, 24, 24, 48))
+    if tuning and "24x24x24x48" in tuning:
+        ctx.set_tuning(tuning["24x24x24x48"])
+    ctx.gauge_generate(3, 0.25)
+    B = torch.stack([ctx.source(ovl.SRC_GAUSS, seed=300 + f) for f in range(12)])
+    res["fields12_24c48"] = _stencil_rates(torch, ovl, ctx, B, 20)
+    res["tuning"]["24x24x24x48"] = ctx.tuning()
     ctx.close()
     return res
 
@@ -519,7 +545,7 @@ def main():
         out["adjoint"] = adjoint_leg(torch, ovl)
         print("[bench] adjoint done", file=sys.stderr, flush=True)
         out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
-        out["tuning"]["32x32x32x64"] = out["dslash_hbm"].pop("tuning")
+        out["tuning"].update(out["dslash_hbm"].pop("tuning"))
         print("[bench] stand-alone stencil done", file=sys.stderr, flush=True)
     if args.eig:
         out["eigsumr_24c48"] = eig_leg(torch, ovl)

@@ -927,7 +927,9 @@ static void launch_stencil_t(Context &c, const StencilArgs<ST> &a, const GT *U, 
     PendingEvent pe;
     // launches inside the multi-shift CG (a.stop set) may skip converged
     // fields; their driver books the bytes of the work actually done
-    const double bytes = a.stop ? 0.0 : stencil_bytes(c.g, prec, EPI) * nf;
+    // nf fields in one launch share one read of the links
+    const double G = stencil_link_bytes(c.g, prec);
+    const double bytes = a.stop ? 0.0 : (stencil_bytes(c.g, prec, EPI) - G) * nf + G;
     const bool prof = profile && c.prof;
     if (prof) c.prof_begin(pe, KERN_STENCIL, prec, bytes);
     launch_by_id<ST, GT, EPI>(c, v, a, U, nf, prof ? &pe : nullptr);
@@ -1001,10 +1003,15 @@ void launch_K(Context &c, double rho, const void *in, void *out, int nf, int pre
 // Algorithmic HBM bytes of one stencil launch per field (perfect neighbour
 // reuse, no index table): read in + links, write out, plus the extra own-site
 // reads of the epilogues that take more inputs.
+double stencil_link_bytes(const Geom &g, int prec)
+{
+    return (double)g.V * 36 * (prec == OVL_F64 ? 16 : prec == OVL_F32 ? 8 : 4);
+}
+
 double stencil_bytes(const Geom &g, int prec, int epi)
 {
     const double S = (double)field_bytes(g, prec);
-    const double G = (double)g.V * 36 * (prec == OVL_F64 ? 16 : prec == OVL_F32 ? 8 : 4);
+    const double G = stencil_link_bytes(g, prec);
     double b = 2 * S + G;
     if (epi == EPI_KPLUS) b += S;
     if (epi == EPI_K2DOT) b += 2 * S;   // p and r

@@ -37,7 +37,10 @@ int stencil_k2_dot(Context &c, int prec, const void *t, void *w, int nf, double 
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
              double sigma, const void *aux, double *partial, const int *stop = nullptr, int it = 0,
              const void *aux2 = nullptr, const int *itb = nullptr);
+// algorithmic bytes of one field's stencil (spinors and links), and of the
+// links alone (read once by a launch over several fields)
 double stencil_bytes(const Geom &g, int prec, int epi);
+double stencil_link_bytes(const Geom &g, int prec);
 // the launch variant for (prec, epi, nf), autotuned on first use
 int stencil_variant(Context &c, int epi, int prec, int nf);
 // tiles (blocks per field) of stencil launch variant v; the largest over variants

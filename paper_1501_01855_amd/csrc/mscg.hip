@@ -564,11 +564,12 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
         hs[f].act_total = hp.fin[f].act_total;
     }
     if (c.prof) c.prof_collect();
-    int64_t iters = 0, act_total = 0;
+    int64_t iters = 0, act_total = 0, launches = 0;
     bool brk = false, capped = false;
     for (int f = 0; f < nf; ++f) {
         if (hstop_final[f] == 0) continue;   // zero source: no iteration ran
         iters += hs[f].iters;
+        launches = std::max<int64_t>(launches, hs[f].iters);
         act_total += hs[f].act_total;
         brk = brk || hs[f].breakdown;
         capped = capped || hs[f].iters >= maxiter;
@@ -589,9 +590,12 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
         c.slots[KERN_SHIFT][prec].bytes +=
             all ? (double)FB * (3.0 * iters + 4.0 * act_total) : (double)FB * (5.0 * iters + 2.0 * act_total);
         // the two stencils of each executed iteration (K, then K with the
-        // shift, the dot and an extra read of p)
+        // shift, the dot and an extra read of p), the links read once per
+        // launch however many fields it carries
+        const double G = stencil_link_bytes(g, prec);
         c.slots[KERN_STENCIL][prec].bytes +=
-            (double)iters * (stencil_bytes(g, prec, EPI_K) + stencil_bytes(g, prec, EPI_K2DOT));
+            (double)iters * (stencil_bytes(g, prec, EPI_K) + stencil_bytes(g, prec, EPI_K2DOT) - 2.0 * G) +
+            (double)launches * 2.0 * G;
     }
     OVL_REQUIRE(!brk, OVL_ERR_BREAKDOWN, "multi-shift CG breakdown (non-positive curvature or NaN)");
     OVL_REQUIRE(!capped, OVL_ERR_NOT_CONVERGED, "multi-shift CG hit its iteration limit");
