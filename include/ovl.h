@@ -310,7 +310,7 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
  * registers, one t chunk per XCD, when Lt is a multiple of 8; 8 .. 11: one
  * lane per site of a 256-site spatial tile whose spinors are shared through
  * LDS, each block walking T = 1, 2, 4, 8 time slices (FP32 and FP16 storage,
- * Lt a multiple of T); FP16 storage: 0, 1, 4, 6, 8 .. 11).
+ * Lt a multiple of T)).
  * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the
  * number held; ovl_tuning_set installs pairs (variants out of range are an
  * argument error), so a run can reuse another run's choices. */

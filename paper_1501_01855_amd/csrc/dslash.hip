@@ -402,6 +402,63 @@ __device__ __forceinline__ void stencil_epilogue(const StencilArgs<ST> &a, unsig
     }
 }
 
+// The epilogue for FP16 storage with two lanes per site: the lanes of a site
+// sit in different waves (threadIdx.x and threadIdx.x ^ 128) and must store
+// with one scale, the larger of their halves' maxima, exchanged through LDS.
+// Every thread of the block calls it (valid: the lane has a site).
+template <int EPI>
+__device__ __forceinline__ void stencil_epilogue_pair_h8(const StencilArgs<h8> &a, unsigned f, int64_t s, int half,
+                                                         const cplx<float> *acc, double part[3], bool valid)
+{
+    __shared__ float mx[256];
+    const int64_t V = a.g.V;
+    const h8 *in = a.in + f * fstride<h8>(V);
+    h8 *out = a.out + f * fstride<h8>(V);
+    cplx<float> o[6], x[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) o[c] = acc[c];
+    if (valid && EPI != EPI_HOP) {
+        ld_sp_half(in, V, s, half, x);
+        const float m = (float)a.diag;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const cplx<float> d = m * x[c] - 0.5f * o[c];
+            o[c] = half == 0 ? d : -d;   // gamma_5: spins 2, 3 are components 6..11
+        }
+        if constexpr (EPI == EPI_K2DOT || EPI == EPI_KPLUS) {
+            ld_sp_half(a.aux + f * fstride<h8>(V), V, s, half, x);
+            const float sg = EPI == EPI_K2DOT ? (float)a.sigma : 1.f;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) o[c] = o[c] + sg * x[c];
+        }
+    }
+    const float ml = valid ? half_max(o) : 0.f;
+    mx[threadIdx.x] = ml;
+    __syncthreads();
+    const float m = fmaxf(ml, mx[threadIdx.x ^ 128]);
+    if (!valid) return;
+    if constexpr (EPI == EPI_K2DOT) {
+        // partials (p, w), Re (r, w), (w, w) on w as stored
+        cplx<float> ws[6], rv[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) ws[c] = o[c];
+        as_stored_scaled(ws, m);
+        ld_sp_half(a.aux2 + f * fstride<h8>(V), V, s, half, rv);
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const double wr = ws[c].re, wi = ws[c].im;
+            d0 += (double)x[c].re * wr + (double)x[c].im * wi;
+            d1 += (double)rv[c].re * wr + (double)rv[c].im * wi;
+            d2 += wr * wr + wi * wi;
+        }
+        part[0] += d0;
+        part[1] += d1;
+        part[2] += d2;
+    }
+    st_sp_half_scaled(out, V, s, half, o, m);
+}
+
 // K2DOT: one partial of each dot per (field, tile).  Every thread of the block
 // must call it.
 template <typename ST, int EPI>
@@ -453,7 +510,10 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
         }
     }
     if constexpr (TPS == 2) exchange_halves<false>(acc, half);
-    if (valid) stencil_epilogue<ST, EPI, TPS>(a, f, s, half, acc, part);
+    if constexpr (TPS == 2 && std::is_same<ST, h8>::value)
+        stencil_epilogue_pair_h8<EPI>(a, f, s, half, acc, part, valid);
+    else if (valid)
+        stencil_epilogue<ST, EPI, TPS>(a, f, s, half, acc, part);
     store_partials<ST, EPI>(a, f, tile, part);
 }
 
@@ -540,7 +600,10 @@ __global__ __launch_bounds__(256) void k_stencil_tm(StencilArgs<ST> a, const GT 
             }
         }
         if constexpr (TPS == 2) exchange_halves<true>(acc, half);
-        if (valid) stencil_epilogue<ST, EPI, TPS>(a, f, s, half, acc, part);
+        if constexpr (TPS == 2 && std::is_same<ST, h8>::value)
+            stencil_epilogue_pair_h8<EPI>(a, f, s, half, acc, part, valid);
+        else if (valid)
+            stencil_epilogue<ST, EPI, TPS>(a, f, s, half, acc, part);
     }
     store_partials<ST, EPI>(a, f, tile, part);
 }
@@ -760,7 +823,7 @@ __global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT
 // Launch variants: 0 / 1 one lane per site, MAP_LEX / MAP_REMAP; 2 / 3 two
 // lanes per site, likewise; 4 / 5 MAP_COL with one / two lanes per site; 6 / 7
 // the t-marching kernel with one / two lanes per site (Lt a multiple of 8).
-// FP16 storage runs one lane per site (variants 0, 1, 4, 6).  8 .. 11 the
+// With FP16 storage the two lanes of a site share its scale through LDS.  8 .. 11 the
 // LDS-tiled march with T = 1, 2, 4, 8 time slices per block (Lt a multiple of
 // T; FP32 and FP16 storage).
 static constexpr int N_VARIANTS = 12;
@@ -814,7 +877,6 @@ bool stencil_variant_ok(const Geom &g, int prec, int v)
     if ((v == 4 || v == 5) && !g.col_ok) return false;
     if ((v == 6 || v == 7) && g.L[3] % 8 != 0) return false;
     if (v >= 8) return prec != OVL_F64 && g.L[3] % (1 << (v - 8)) == 0;
-    if (prec == OVL_HALF) return v == 0 || v == 1 || v == 4 || v == 6;
     return true;
 }
 
@@ -860,16 +922,7 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
             return;
         }
     }
-    if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: one lane per site only
-        if (id == 0)
-            launch_variant<ST, GT, EPI, 1, MAP_LEX>(c, a, U, nf, pe);
-        else if (id == 1)
-            launch_variant<ST, GT, EPI, 1, MAP_REMAP>(c, a, U, nf, pe);
-        else if (id == 4)
-            launch_variant<ST, GT, EPI, 1, MAP_COL>(c, a, U, nf, pe);
-        else
-            launch_tmarch<ST, GT, EPI, 1>(c, a, U, nf, pe);
-    } else {
+    {
         switch (id) {
         case 0: launch_variant<ST, GT, EPI, 1, MAP_LEX>(c, a, U, nf, pe); break;
         case 1: launch_variant<ST, GT, EPI, 1, MAP_REMAP>(c, a, U, nf, pe); break;

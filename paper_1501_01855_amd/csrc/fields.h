@@ -166,6 +166,59 @@ __device__ __forceinline__ void st_sp(h8 *__restrict__ p, int64_t V, int64_t s, 
     reinterpret_cast<float *>(p + 3 * V)[s] = m;
 }
 
+// Half of an FP16-stored spinor (two lanes per site): half 0 holds complex
+// components 0..5 (plane 0 and the low half of plane 1), half 1 components
+// 6..11 (the high half of plane 1 and plane 2).  The site's scale is shared,
+// so the store takes it (the larger of both halves' maxima) as an argument;
+// half 0 writes it.
+__device__ __forceinline__ void ld_sp_half(const h8 *__restrict__ p, int64_t V, int64_t s, int h,
+                                           cplx<float> v[6])
+{
+    const float sc = reinterpret_cast<const float *>(p + 3 * V)[s];
+    const uint2 mid = reinterpret_cast<const uint2 *>(p + V + s)[h];
+    const uint4 q = p[(h == 0 ? 0 : 2) * V + s].v;
+    const uint32_t w[6] = {h == 0 ? q.x : mid.x, h == 0 ? q.y : mid.y, h == 0 ? q.z : q.x,
+                           h == 0 ? q.w : q.y, h == 0 ? mid.x : q.z, h == 0 ? mid.y : q.w};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const float2 a = h2f2(w[c]);
+        v[c] = {a.x * sc, a.y * sc};
+    }
+}
+__device__ __forceinline__ float half_max(const cplx<float> v[6])
+{
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    return m;
+}
+// the values st_sp_half_scaled stores, with the site scale m
+__device__ __forceinline__ void as_stored_scaled(cplx<float> v[6], float m)
+{
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const float2 q = h2f2(f22h2(v[c].re * inv, v[c].im * inv));
+        v[c] = {q.x * m, q.y * m};
+    }
+}
+__device__ __forceinline__ void st_sp_half_scaled(h8 *__restrict__ p, int64_t V, int64_t s, int h,
+                                                  const cplx<float> v[6], float m)
+{
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    uint32_t w[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w[c] = f22h2(v[c].re * inv, v[c].im * inv);
+    if (h == 0) {
+        p[s].v = make_uint4(w[0], w[1], w[2], w[3]);
+        reinterpret_cast<uint2 *>(p + V + s)[0] = make_uint2(w[4], w[5]);
+        reinterpret_cast<float *>(p + 3 * V)[s] = m;
+    } else {
+        reinterpret_cast<uint2 *>(p + V + s)[1] = make_uint2(w[0], w[1]);
+        p[2 * V + s].v = make_uint4(w[2], w[3], w[4], w[5]);
+    }
+}
+
 // ------------------------------------------------------------------ links
 // Link planes [mu][9][P], P the padded plane stride (Geom::Pu).
 __device__ __forceinline__ void ld_link(const double2 *__restrict__ U, int64_t P, int mu,
