@@ -137,11 +137,26 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
     __shared__ int s_act[NZMAX];
     __shared__ int s_keep_any;
     const MscgScal &sc = S[(it & 1) * nf + f];
+    const int64_t fo = f * fstride<ST>(V);
+    const int64_t s0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // the four sums of partials, their loads issued in one pass (each sum in
+    // the same per-thread order as a separate pass)
     const double *pf = part + (int64_t)f * 3 * pw_n;
-    const double pw = block_allsum(pf, pw_n, lds);
-    const double rw = block_allsum(pf + pw_n, pw_n, lds);
-    const double ww = block_allsum(pf + 2 * pw_n, pw_n, lds);
-    const double rr = it == 0 ? sc.rr : block_allsum(rr_in + (int64_t)f * rr_n, rr_n, lds);
+    const double *rf = rr_in + (int64_t)f * rr_n;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    const int nmax = pw_n > rr_n ? pw_n : rr_n;
+    for (int i = threadIdx.x; i < nmax; i += blockDim.x) {
+        if (i < pw_n) {
+            v0 += pf[i];
+            v1 += pf[pw_n + i];
+            v2 += pf[2 * pw_n + i];
+        }
+        if (it != 0 && i < rr_n) v3 += rf[i];
+    }
+    const double pw = block_bcast_sum(v0, lds);
+    const double rw = block_bcast_sum(v1, lds);
+    const double ww = block_bcast_sum(v2, lds);
+    const double rr = it == 0 ? sc.rr : block_bcast_sum(v3, lds);
     const double alpha = rr / pw;
     const double rr_new = fmax(0.0, rr - 2.0 * alpha * rw + alpha * alpha * ww);
     const bool ok = pw > 0.0 && isfinite(alpha) && isfinite(rr_new);
@@ -199,11 +214,10 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
         }
     }
     if (!ok) return;
-    const int64_t fo = f * fstride<ST>(V);
     const int64_t pstride = nf * fstride<ST>(V);   // shift-major: p[l][f]
     const R ar = (R)alpha;
     double rn = 0.0;
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t s = s0; s < V; s += (int64_t)gridDim.x * blockDim.x) {
         cplx<R> rv[12], yv[12], pv[12];
         ld_sp((it == 0 ? src : rin) + fo, V, s, rv);
         ld_sp(w + fo, V, s, pv);

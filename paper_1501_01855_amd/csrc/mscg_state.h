@@ -26,12 +26,10 @@ struct MscgConst {
     double sigma[NZMAX], omega[NZMAX], tol2[NZMAX];
 };
 
-// Sum of p[0..n) by the whole block in a fixed order; the result is returned
-// to every thread.
-__device__ inline double block_allsum(const double *p, int n, double *lds)
+// The block's sum of the per-thread values v (fixed order), returned to every
+// thread.
+__device__ inline double block_bcast_sum(double v, double *lds)
 {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
     const double t = block_sum<256>(v, lds);
     __shared__ double bcast;
     if (threadIdx.x == 0) bcast = t;
@@ -39,6 +37,15 @@ __device__ inline double block_allsum(const double *p, int n, double *lds)
     const double r = bcast;
     __syncthreads();
     return r;
+}
+
+// Sum of p[0..n) by the whole block in a fixed order; the result is returned
+// to every thread.
+__device__ inline double block_allsum(const double *p, int n, double *lds)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    return block_bcast_sum(v, lds);
 }
 
 }  // namespace ovl
