@@ -153,10 +153,10 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
         }
         if (it != 0 && i < rr_n) v3 += rf[i];
     }
-    const double pw = block_bcast_sum(v0, lds);
-    const double rw = block_bcast_sum(v1, lds);
-    const double ww = block_bcast_sum(v2, lds);
-    const double rr = it == 0 ? sc.rr : block_bcast_sum(v3, lds);
+    double vv[4] = {v0, v1, v2, v3}, tot[4];
+    block_bcast_sum4(vv, tot);
+    const double pw = tot[0], rw = tot[1], ww = tot[2];
+    const double rr = it == 0 ? sc.rr : tot[3];
     const double alpha = rr / pw;
     const double rr_new = fmax(0.0, rr - 2.0 * alpha * rw + alpha * alpha * ww);
     const bool ok = pw > 0.0 && isfinite(alpha) && isfinite(rr_new);

@@ -39,6 +39,31 @@ __device__ inline double block_bcast_sum(double v, double *lds)
     return r;
 }
 
+// Four block sums at once (256 threads), each with the same reduction tree as
+// block_bcast_sum (so the same values), returned to every thread; one pair of
+// barriers instead of four.
+__device__ inline void block_bcast_sum4(double v[4], double out[4])
+{
+    __shared__ double l4[4][4];   // [value][wave]
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) l4[k][wave] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double r = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) r += l4[k][w];
+        out[k] = r;
+    }
+}
+
 // Sum of p[0..n) by the whole block in a fixed order; the result is returned
 // to every thread.
 __device__ inline double block_allsum(const double *p, int n, double *lds)
