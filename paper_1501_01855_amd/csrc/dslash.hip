@@ -466,11 +466,28 @@ __device__ __forceinline__ void store_partials(const StencilArgs<ST> &a, unsigne
                                                const double part[3])
 {
     if constexpr (EPI == EPI_K2DOT) {
-        __shared__ double lds[4];
-        const double t0 = block_sum<256>(part[0], lds);
-        const double t1 = block_sum<256>(part[1], lds);
-        const double t2 = block_sum<256>(part[2], lds);
+        // the three block sums in one LDS pass, each with block_sum's tree
+        __shared__ double l3[3][4];
+        double v[3] = {part[0], part[1], part[2]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        __syncthreads();
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) l3[k][wave] = v[k];
+        __syncthreads();
         if (threadIdx.x == 0) {
+            double t[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                t[k] = 0.0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) t[k] += l3[k][w];
+            }
+            const double t0 = t[0], t1 = t[1], t2 = t[2];
             double *pp = a.partial + (int64_t)f * 3 * gridDim.x + tile;
             pp[0] = t0;
             pp[gridDim.x] = t1;
