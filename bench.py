@@ -349,6 +349,35 @@ def eig_leg(torch, ovl, n_calc=3):
     return out
 
 
+def c1_leg(torch, ovl, reps=10):
+    """The plain method on 4^4 (links eps 0.3 seed 1, rho 1.4, N_Z = 16 on
+    [lambda_min, lambda_max] of |K| from the GPU's Lanczos, no exact modes,
+    mu = 0.05, point source at site 0 spin 0 colour 0, GMRESR(relSUMR) to
+    1e-10): solves/s in FP64 and with the precision ladder."""
+    ctx = ovl.Context((4, 4, 4, 4))
+    ctx.gauge_generate(1, 0.3)
+    ev, lmax = ctx.lowmodes_compute(RHO, 1, tol=1e-12)
+    ctx.lowmodes_set([], None)   # the interval only; no exactly treated mode
+    zolo = ovl.zolotarev_coeffs(16, abs(ev[0]), lmax)
+    b = ctx.source(ovl.SRC_POINT, site=0, spin=0, colour=0)
+    out = {"lattice": "4^4", "interval": [abs(ev[0]), lmax]}
+    for name, mixed in (("fp64", False), ("mixed", True)):
+        p = ovl.solver_defaults(rho=RHO, mu=0.05, tol=TOL, eta_tilde=1e-3, f32_threshold=(1e-6 if mixed else 10.0))
+        ctx.solve(b, zolo, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x, st, code = ctx.solve(b, zolo, p)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        Dx, _ = ctx.overlap(x, RHO, 0.05, zolo, 1e-14)
+        out[name] = {"status": code, "seconds": dt, "solves_per_s": 1.0 / dt,
+                     "true_relres": float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b)),
+                     "sumr_iters": st[0].sumr_iters, "mscg_iters": st[0].mscg_iters}
+    ctx.close()
+    return out
+
+
 def adjoint_leg(torch, ovl):
     """dS/dpsi and dS/dU for S = Re(chi^H D psi), N_Z = 20, no exactly treated
     modes: 8^3 x 16 in FP64 (eta 1e-10) and 32^3 x 64 in FP32 (eta 1e-6)."""
@@ -426,7 +455,8 @@ def cpu_baseline(mscg_iters_per_solve):
     """The oracle (FP64, C stencil + numpy) on a bounded sample of the same
     workload: 96 multi-shift CG iterations (about 15 s on the host) with all
     20 shifts active on the 16^3 x 32 field, scaled by the GPU solve's
-    multi-shift iteration count."""
+    multi-shift iteration count; and the oracle's whole plain-method solve on
+    4^4 (c1_solve_seconds), to set beside the GPU's on the same problem."""
     import numpy as np
     import synth
     from oracle import krylov
@@ -442,7 +472,16 @@ def cpu_baseline(mscg_iters_per_solve):
     dt = time.perf_counter() - t0
     per_iter = dt / iters
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the whole plain-method solve on 4^4, where the oracle finishes in seconds
+    dims1 = (4, 4, 4, 4)
+    k1 = WilsonKernel(dims1, synth.gauge_field(dims1, 1, 0.3), RHO)
+    w1 = np.linalg.eigvalsh(k1.dense("K"))
+    ov1 = krylov.Overlap(krylov.SignFunction(k1, Zolotarev(16, np.abs(w1).min(), np.abs(w1).max())), 0.05)
+    t0 = time.perf_counter()
+    krylov.gmresr_sumr(ov1, synth.point_source(dims1), TOL, 1e-3)
+    c1 = time.perf_counter() - t0
     return {"value": 1.0 / (per_iter * mscg_iters_per_solve), "unit": "solves/s", "cores": threads,
+            "c1_solve_seconds": c1,
             "kind": "oracle",
             "sample": f"{iters} multi-shift CG iterations (20 shifts active) of the oracle on the "
                       f"16^3x32 field in {dt:.1f} s, scaled by the {mscg_iters_per_solve} multi-shift "
@@ -542,6 +581,8 @@ def main():
     if not args.no_extras:
         out["uneven_instances"] = uneven_leg(torch, ovl)
         print("[bench] uneven instances done", file=sys.stderr, flush=True)
+        out["c1_plain_4c4"] = c1_leg(torch, ovl)
+        print("[bench] 4^4 plain-method solves done", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_leg(torch, ovl)
         print("[bench] adjoint done", file=sys.stderr, flush=True)
         out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
