@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--eig", action="store_true",
                     help="add the eigSUMR leg on 24^3x48 (12 point sources, calculating solves then a "
                          "deflated batch; several minutes)")
+    ap.add_argument("--eig-calc", type=int, default=3, help="eigSUMR leg: calculating solves")
+    ap.add_argument("--eig-n", type=int, default=20, help="eigSUMR leg: eigenvectors kept (n)")
+    ap.add_argument("--eig-m", type=int, default=60, help="eigSUMR leg: basis size of Alg. 6 (m)")
     ap.add_argument("--tuning", default=None,
                     help="JSON of stencil launch choices to install instead of autotuning (the 'tuning' "
                          "object an earlier run printed), so that profiler runs see the same kernels")
@@ -267,9 +270,9 @@ def uneven_leg(torch, ovl):
             "status": [r[2] for r in res]}
 
 
-def eig_leg(torch, ovl, n_calc=3):
+def eig_leg(torch, ovl, n_calc=3, n_eig=20, m_eig=60):
     """eigSUMR on 24^3 x 48 (links eps 0.25, seed 3; rho 1.4, mu 0.01, N_Z 20
-    with 10 exact kernel modes; n_eig 20, m 60): n_calc calculating solves
+    with 10 exact kernel modes; by default n_eig 20, m 60): n_calc calculating solves
     (Alg. 5 collection, Alg. 6 Rayleigh-Ritz) on the first spin-colour point
     sources at site 0, the eigenspace's D psi' recomputed in FP64, then all 12
     sources in one deflated batched solve; for comparison one undeflated mixed
@@ -289,10 +292,11 @@ def eig_leg(torch, ovl, n_calc=3):
         return ovl.solver_defaults(rho=RHO, mu=mu, tol=TOL, eta_tilde=1e-3, relax_floor=1e-2,
                                    f32_threshold=(1e-6 if mixed else 10.0),
                                    half_threshold=(3e-3 if mixed else 10.0), max_outer=16, max_middle=6000,
-                                   max_mscg=20000, use_deflation=defl, eig_calc=calc, n_eig=20, m_eig=60,
+                                   max_mscg=20000, use_deflation=defl, eig_calc=calc, n_eig=n_eig, m_eig=m_eig,
                                    verbose=1)   # one line per GMRESR step (progress of long solves)
 
-    out = {"lattice": "24x24x24x48", "mu": mu, "n_eig": 20, "m_eig": 60, "setup_lowmodes_s": setup_lowmodes}
+    out = {"lattice": "24x24x24x48", "mu": mu, "n_eig": n_eig, "m_eig": m_eig, "calculating_solves_n": n_calc,
+           "setup_lowmodes_s": setup_lowmodes}
     calc = []
     t0 = time.perf_counter()
     for i in range(n_calc):
@@ -589,7 +593,7 @@ def main():
         out["tuning"].update(out["dslash_hbm"].pop("tuning"))
         print("[bench] stand-alone stencil done", file=sys.stderr, flush=True)
     if args.eig:
-        out["eigsumr_24c48"] = eig_leg(torch, ovl)
+        out["eigsumr_24c48"] = eig_leg(torch, ovl, args.eig_calc, args.eig_n, args.eig_m)
         print("[bench] eigSUMR leg done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(st_64[-1]["mscg_iters"])
