@@ -1,14 +1,17 @@
 // Wilson hopping stencil H and kernel K = gamma_5 [(4 - rho) - H/2]
 // (paper Sec. 1, eq. 2) on gfx950, plus layout conversions.
 //
-// One thread per lattice site, 256 threads (four wave64) per block, one
-// right-hand side per grid row.  Each thread gathers the eight neighbour
-// spinors, spin-projects them to half spinors (6 complex), multiplies by the
-// link (or its adjoint) and reconstructs the lower spin components, so a
-// direction costs one 12-complex spinor load, one 9-complex link load and
+// The basic scheme: one lane per lattice site, 256 threads (four wave64) per
+// block, one right-hand side per grid row.  A lane gathers the eight
+// neighbour spinors, spin-projects them to half spinors (6 complex),
+// multiplies by the link (or its adjoint) and reconstructs the lower spin
+// components, so a direction costs one spinor load, one link load and
 // 2 x 3 x 3 complex multiply-adds per half spinor.  Neighbour indices are
 // computed arithmetically (no index table).  Spinor and link planes are
-// site-major, so consecutive lanes issue consecutive 16-byte loads.
+// site-major, so consecutive lanes issue consecutive 16-byte loads.  The
+// launch variants below change who does what (two lanes per site, XCD-aware
+// block orders, lanes walking time columns, LDS-shared spatial tiles); an
+// autotuner picks one per precision, epilogue and field count.
 #include <algorithm>
 #include <type_traits>
 
