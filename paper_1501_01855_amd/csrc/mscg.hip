@@ -283,28 +283,51 @@ __global__ __launch_bounds__(256) void k_low_dots(const ST *__restrict__ basis, 
                                                   const ST *__restrict__ x, int64_t V, double *partial)
 {
     using R = typename Planes<ST>::R;
+    constexpr int NB = 8;   // basis vectors per pass: their loads are issued together
     const int f = blockIdx.y;
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    __shared__ double lds[4];
+    __shared__ double lds[2 * NB][4];   // [value][wave]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     cplx<R> xv[12];
     if (s < V) ld_sp(x + f * fstride<ST>(V), V, s, xv);
-    for (int j = 0; j < n; ++j) {
-        double dr = 0.0, di = 0.0;
-        if (s < V) {
-            cplx<R> b[12];
-            ld_sp(basis + (int64_t)j * fstride<ST>(V), V, s, b);
+    for (int j0 = 0; j0 < n; j0 += NB) {
+        double d[2 * NB];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const double xr = xv[c].re, xi = xv[c].im, br = b[c].re, bi = b[c].im;
-                dr += br * xr + bi * xi;
-                di += br * xi - bi * xr;
+        for (int q = 0; q < 2 * NB; ++q) d[q] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int j = j0 + q;
+            if (s < V && j < n) {
+                cplx<R> b[12];
+                ld_sp(basis + (int64_t)j * fstride<ST>(V), V, s, b);
+                double dr = 0.0, di = 0.0;
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const double xr = xv[c].re, xi = xv[c].im, br = b[c].re, bi = b[c].im;
+                    dr += br * xr + bi * xi;
+                    di += br * xi - bi * xr;
+                }
+                d[2 * q] = dr;
+                d[2 * q + 1] = di;
             }
         }
-        const double tr = block_sum<256>(dr, lds);
-        const double ti = block_sum<256>(di, lds);
-        if (threadIdx.x == 0) {
-            partial[(((int64_t)f * n + j) * 2 + 0) * gridDim.x + blockIdx.x] = tr;
-            partial[(((int64_t)f * n + j) * 2 + 1) * gridDim.x + blockIdx.x] = ti;
+        // block sums of the 2 NB values (fixed order, one LDS pass)
+#pragma unroll
+        for (int q = 0; q < 2 * NB; ++q)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) d[q] += __shfl_xor(d[q], off, 64);
+        __syncthreads();   // the previous pass has read lds
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 2 * NB; ++q) lds[q][wave] = d[q];
+        __syncthreads();
+        const int q = threadIdx.x;
+        if (q < 2 * NB && j0 + q / 2 < n) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) t += lds[q][w];
+            const int j = j0 + q / 2;
+            partial[(((int64_t)f * n + j) * 2 + (q & 1)) * gridDim.x + blockIdx.x] = t;
         }
     }
 }
