@@ -4,7 +4,7 @@ Workload (one "step" = one complete GMRESR(relSUMR) solve of D[mu] x = b):
 16^3 x 32 lattice, links exp(i 0.25 A) (seed 2), K = gamma_5 D_W(-1.4),
 mu = 0.02, order-20 Zolotarev sign function with the 10 lowest kernel modes
 treated exactly, one complex Gaussian source (seed 102), target
-||b - D x|| <= 1e-10 ||b||.  Set-up (gauge field, low modes, coefficients)
+||b - D x|| <= 1e-10 ||b||, middle-solve accuracy eta~ = 3e-3.  Set-up (gauge field, low modes, coefficients)
 is outside the timed region.  The headline value is the mixed-precision
 solver (FP16-storage sign function while the accuracy asked for is >= 3e-3,
 FP32 while >= 1e-6, FP64 below); the same solve with an all-FP64 sign function
@@ -40,6 +40,9 @@ METRIC = "overlap solves/s at 1e-10 resid (mixed vs FP64) + Dslash HBM GB/s % pe
 HBM_PEAK_GBS = 8000.0
 DIMS = (16, 16, 16, 32)
 RHO, MU, NZ, NLOW, TOL = 1.4, 0.02, 20, 10, 1e-10
+# middle-solve accuracy of GMRESR for the 16^3 x 32 workload, tuned as Alg. 3
+# asks (a sweep over 3e-4 .. 1e-2 on this workload: 3e-3 fastest)
+ETA_TILDE_C2 = 3e-3
 PREC_NAMES = ("f64", "f32", "f16")
 KERN_NAMES = ("stencil", "shift_update")
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_overlap_solve_16c32.txt")
@@ -135,7 +138,7 @@ def profile_run(torch, ovl, tuning):
 
 
 def solve_params(ovl, mixed, half_threshold=2.0):
-    return ovl.solver_defaults(rho=RHO, mu=MU, tol=TOL, eta_tilde=1e-3, relax_floor=1e-2,
+    return ovl.solver_defaults(rho=RHO, mu=MU, tol=TOL, eta_tilde=ETA_TILDE_C2, relax_floor=1e-2,
                                f32_threshold=(1e-6 if mixed else 10.0),
                                half_threshold=(half_threshold if mixed else 10.0), max_outer=16,
                                max_middle=4000, max_mscg=20000)
@@ -541,7 +544,7 @@ def main():
         "dtype": "f16-storage/f32/f64",
         "data": "synthetic",
         "config": {"workload": "overlap solve 16^3x32, rho=1.4, mu=0.02, N_Z=20, 10 exact kernel modes, "
-                               "Gaussian source, GMRESR(relSUMR) to 1e-10",
+                               "Gaussian source, GMRESR(relSUMR) to 1e-10 (middle solves to 3e-3)",
                    "global_batch": 1, "lattice": "16x16x16x32", "parallelism": "single GPU"},
         "fp64_solves_per_s": 1.0 / dt_64,
         "mixed_over_fp64": (args.steps / dt_mix) * dt_64,
