@@ -1,5 +1,6 @@
-"""Oracle: deflation of the middle solve (Sec. 4) and eigSUMR (Sec. 5,
-Algs. 5 and 6, the relaxation bound of Sec. 5.1).
+"""Oracle: deflation of the middle solve (Sec. 4), eigSUMR (Sec. 5,
+Algs. 5 and 6, the relaxation bound of Sec. 5.1) and eigCG (Sec. 5) on the
+relCG middle solve with the spectral preconditioner of Sec. 4.
 
 TEST INFRASTRUCTURE ONLY.
 
@@ -21,6 +22,18 @@ Readings where the paper is silent or garbled (also listed in the design notes):
 * The subspace size m is not given for the inversions: m = n + 40 unless
   set; v^D is recomputed accurately every k diagonalisations and when the
   eigenvector phase ends.
+* eigCG (Sec. 5 describes it in words only): every CG iteration adds two
+  basis vectors, the preconditioned direction w = Hhat^{-1} p and H w (the
+  paper keeps both p and gamma_5 D p), each scaled to unit norm, with their
+  images D w = gamma_5 (H w) and D (H w) = gamma_5 (H H w) taken from the
+  two H applications the iteration makes anyway; Alg. 6 (with the same
+  pair-splitting M) diagonalises them, at k = m and at the end of each
+  middle solve, and the Sec. 5.1 bound caps the CG's sign accuracy as for
+  eigSUMR.  The spectral preconditioner of a middle solve is built from the
+  eigenvectors held when it starts and stays fixed until it ends (a CG needs
+  a fixed operator; GMRESR absorbs the change between middle solves).  Its
+  vectors are the Rayleigh-Ritz vectors of H^2 = D^+ D in the span of the n
+  held eigenvectors, so that they are orthonormal as Sec. 4's formula needs.
 """
 import numpy as np
 
@@ -176,6 +189,78 @@ def gmresr_eigsumr(overlap, b, eps, eta_tilde, eig, calc=True, floor=1e-2, maxit
 
         res = krylov.sumr(overlap.U, rho, bp, eta_tilde, x0=x0, maxiter=maxiter, eta_fn=eta_fn,
                           on_step=(eig.collect if calc else None))
+        if calc:
+            eig.diagonalise()
+            if eig.ndiag and eig.ndiag % eig.krecalc == 0:
+                eig.recompute(overlap)
+        return res.x, res.iters
+
+    return krylov.gmresr(apply_A, middle, b, 0.5 * eps)
+
+
+def spectral_preconditioner(V, VD):
+    """Sec. 4's Hhat^{-1} from held vectors V with images VD = D V: the
+    Rayleigh-Ritz pairs (m_i, s_i) of H^2 = D^+ D in span(V), found from
+    V^H V = R^H R and the eigenpairs (m_i, y_i) of R^{-H} VD^H VD R^{-1}
+    (since (H v, H w) = (D v, D w)), with s_i = V R^{-1} y_i orthonormal."""
+    from . import krylov
+    shape = V[0].shape
+    Vm, VDm = _mat(V), _mat(VD)
+    E = Vm.conj().T @ Vm
+    E = 0.5 * (E + E.conj().T)
+    Rinv = np.linalg.inv(np.linalg.cholesky(E).conj().T)
+    G = Rinv.conj().T @ (VDm.conj().T @ VDm) @ Rinv
+    m, Y = np.linalg.eigh(0.5 * (G + G.conj().T))
+    S = Vm @ (Rinv @ Y)
+    return krylov.SpectralPreconditioner([S[:, i].reshape(shape) for i in range(S.shape[1])], m)
+
+
+class EigCG(EigSUMR):
+    """eigCG collection on the relCG middle solve (module notes): the two
+    unit-norm basis vectors of each CG iteration with their images under D,
+    Alg. 6 at k = m; the relaxation bound, recomputation and deflation data
+    are those of EigSUMR."""
+
+    def collect_cg(self, w, hw, hhw):
+        for v, dv in ((w, g5(hw)), (hw, g5(hhw))):
+            s = 1.0 / norm(v)
+            self.shape = v.shape
+            self.V.append(s * v)
+            self.VD.append(s * dv)
+            if len(self.V) == self.m:
+                self.diagonalise()
+
+    def preconditioner(self):
+        """The spectral preconditioner of the n held eigenvectors, or None
+        before the first diagonalisation."""
+        if self.theta is None:
+            return None
+        n = min(self.n, len(self.V))
+        return spectral_preconditioner(self.V[:n], self.VD[:n])
+
+
+def gmresr_eigcg(overlap, b, eps, eta_tilde, eig, calc=True, floor=1e-2, maxiter=10000):
+    """GMRESR(eigCG): Alg. 3 whose middle solves are the Sec. 4 CGNE for
+    H u = gamma_5 r, spectrally preconditioned with the eigenvectors held
+    when each middle solve starts; while calc is true each CG iteration's
+    vectors are collected (EigCG.collect_cg) at the stricter of the CG and
+    eigenvector sign accuracies, and Alg. 6 closes every middle solve."""
+    from . import krylov
+    mu = overlap.mu
+    bnorm = norm(b)
+
+    def apply_A(u):
+        e = min(1e-2, eps * bnorm / (2.0 * (1.0 - mu) * norm(u)))
+        return overlap(u, e)
+
+    def H(v, eta):
+        return g5(overlap(v, eta))
+
+    def middle(r):
+        pre = eig.preconditioner()
+        res = krylov.cgne(H, g5(r), eta_tilde, precond=pre, eps_A=eta_tilde, floor=floor, maxiter=maxiter,
+                          eta_cap=(eig.sign_accuracy if calc else None),
+                          on_iter=(eig.collect_cg if calc else None))
         if calc:
             eig.diagonalise()
             if eig.ndiag and eig.ndiag % eig.krecalc == 0:

@@ -421,13 +421,18 @@ class CGResult:
         self.x, self.iters, self.resid = x, iters, resid
 
 
-def cgne(apply_H, b, tol, precond=None, eps_A=None, floor=1e-2, maxiter=10000):
+def cgne(apply_H, b, tol, precond=None, eps_A=None, floor=1e-2, maxiter=10000, eta_cap=None, on_iter=None):
     """The preconditioned CGNE of Sec. 4 for H x = b (H Hermitian):
     r_0 = p_0 = Hhat^{-1} b, x_0 = 0; per iteration z = Hhat^{-1} H^2
     Hhat^{-1} p, alpha = (r, r) / (r, z), r -= alpha z, x += alpha p,
     beta = (r', r') / (r, r), p = r' + beta p; until ||r|| < tol ||b||; then
     x = H Hhat^{-1} x.  apply_H(v, eta) applies H with sign accuracy eta,
-    relaxed as in Sec. 3 for CG (module notes)."""
+    relaxed as in Sec. 3 for CG (module notes).
+
+    eigCG (Sec. 5) hooks: eta_cap() bounds each iteration's sign accuracy
+    from above (the eigenvector bound of Sec. 5.1), and on_iter(w, Hw, HHw)
+    receives the preconditioned direction w = Hhat^{-1} p with its two
+    images under H."""
     P = precond if precond is not None else (lambda v: v)
     eps_A = tol if eps_A is None else eps_A
     bn = norm(b)
@@ -440,7 +445,14 @@ def cgne(apply_H, b, tol, precond=None, eps_A=None, floor=1e-2, maxiter=10000):
     it = 0
     while np.sqrt(rr) >= tol * bn and it < maxiter:
         eta = min(floor, eps_A * r0n * np.sqrt(zeta))
-        z = P(apply_H(apply_H(P(p), eta), eta))
+        if eta_cap is not None:
+            eta = min(eta, eta_cap())
+        w = P(p)
+        hw = apply_H(w, eta)
+        hhw = apply_H(hw, eta)
+        if on_iter is not None:
+            on_iter(w, hw, hhw)
+        z = P(hhw)
         alpha = rr / dot(r, z)
         r = r - alpha * z
         x = x + alpha * p
