@@ -102,7 +102,8 @@ typedef struct {
     int32_t max_middle;    /* SUMR or CG iterations per middle solve                */
     int32_t max_mscg;      /* multi-shift CG iterations per sign call               */
     int32_t use_deflation; /* 1: start middle solves from the eigenspace projection (Sec. 4) */
-    int32_t eig_calc;      /* 1: collect eigSUMR vectors during this solve (Alg. 5)  */
+    int32_t eig_calc;      /* 1: collect eigenvectors during this solve: eigSUMR
+                              (Alg. 5) or, with middle_cg, eigCG (Sec. 5)          */
     int32_t n_eig;         /* eigSUMR: eigenvectors kept (n)                         */
     int32_t m_eig;         /* eigSUMR: basis size at which Alg. 6 runs (m > n)       */
     int32_t k_recalc;      /* eigSUMR: recompute v^D = D v every k diagonalisations   */
@@ -116,9 +117,13 @@ typedef struct {
                               built from the held eigenspace (Rayleigh-Ritz vectors
                               of H^2 in its span, c = sqrt(3)/2).  Its sign calls
                               use FP32 at most (FP16 rounding swamps the lowest
-                              eigenvalues of H^2, ~mu^2).  eig_calc needs
-                              the SUMR middle solve (collecting eigenvectors during
-                              CG is not provided).                               */
+                              eigenvalues of H^2, ~mu^2).  With eig_calc (eigCG,
+                              Sec. 5) each CG iteration adds its direction
+                              w = Hhat^{-1} p and H w, unit-normed, with images
+                              gamma_5 H w and gamma_5 H H w, to the eigenspace; Alg. 6
+                              diagonalises at m and after each middle solve, the
+                              Sec. 5.1 bound caps the sign accuracy, and each middle
+                              solve keeps the preconditioner it started with. */
 } ovl_solver_params;
 
 typedef struct ovl_context ovl_context;

@@ -37,6 +37,7 @@ struct EigSpace {
     // spectral preconditioner (Sec. 4): orthonormal vectors S and the factors
     // c / sqrt(m_i) - 1 of their Ritz values m_i of H^2
     bool spec_ready = false;
+    bool spec_hold = false;   // keep S fixed (a CG middle solve is running)
     int nspec = 0;
     double2 *S = nullptr;
     std::vector<double> spec_f;

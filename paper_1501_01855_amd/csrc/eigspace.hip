@@ -78,6 +78,28 @@ void eig_collect(Context &c, const double2 *q, const double2 *u)
     if (e.k == e.m) eig_diagonalise(c);
 }
 
+// eigCG (Sec. 5) on the CG middle solve: the iteration's direction w and H w,
+// each scaled to unit norm, with images D w = gamma_5 H w and
+// D (H w) = gamma_5 H H w taken from the iteration's own two H products.
+void eig_collect_cg(Context &c, const double2 *w, const double2 *hw, const double2 *hhw)
+{
+    EigSpace &e = c.eig;
+    if (e.m == 0) return;
+    const double2 *pairs[2][2] = {{w, hw}, {hw, hhw}};
+    for (auto &pr : pairs) {
+        std::vector<double> nv;
+        norm2_f64(c, pr[0], 1, nv);
+        const double nrm = std::sqrt(nv[0]);
+        OVL_REQUIRE(nrm > 0.0 && std::isfinite(nrm), OVL_ERR_BREAKDOWN, "eigCG: zero or non-finite basis vector");
+        const double s = 1.0 / nrm;
+        const size_t off = (size_t)e.k * 12 * c.g.V;
+        lincomb3_f64(c, s, pr[0], 0.0, pr[0], 0.0, nullptr, e.V + off, 1);
+        lincomb3_f64(c, s, pr[1], 0.0, pr[1], 0.0, nullptr, e.VD + off, 1);
+        gamma5_f64(c, e.VD + off, 1);
+        e.k += 1;
+        if (e.k == e.m) eig_diagonalise(c);
+    }
+}
 // Alg. 6 on the k held vectors; keeps the n lowest Ritz pairs.
 void eig_diagonalise(Context &c)
 {
@@ -259,7 +281,7 @@ bool spectral_available(const Context &c)
 void spectral_apply(Context &c, const double2 *v, double2 *out, int nf)
 {
     EigSpace &e = c.eig;
-    if (!e.spec_ready) spectral_prepare(c);
+    if (!e.spec_ready && !(e.spec_hold && e.nspec > 0)) spectral_prepare(c);
     const int n = e.nspec;
     std::vector<cplx<double>> d;
     multidot_f64(c, e.S, n, v, nf, d);   // d[f][i] = (s_i, v_f)

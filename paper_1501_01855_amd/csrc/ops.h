@@ -45,6 +45,7 @@ void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *eva
 // eigSUMR and deflation (eigspace.hip).
 void eig_configure(Context &c, int n, int m, double mu, double delta, double eps, int krecalc);
 void eig_collect(Context &c, const double2 *q, const double2 *u);
+void eig_collect_cg(Context &c, const double2 *w, const double2 *hw, const double2 *hhw);
 void eig_diagonalise(Context &c);
 double eig_sign_accuracy(const Context &c);
 void eig_recompute(Context &c, double rho, const ovl_zolo &z, double eta, ovl_stats *st);

@@ -453,8 +453,12 @@ static void apply_H(Context &c, const ovl_zolo &z, const ovl_solver_params &prm,
 // Each H is applied with the CG relaxation of Sec. 3,
 // eta_j = min(floor, epsA ||r_0|| sqrt(sum_{i<=j} ||r_i||^-2)); the closing H
 // with accuracy epsA.  Hhat^{-1} is the identity unless precond.
+// collect (eigCG, Sec. 5; one field only): every iteration hands w = Hhat^{-1} p,
+// H w and H H w to the eigenspace, and the Sec. 5.1 bound caps eta_j.  The
+// preconditioner stays the one built when the CG starts, even where the
+// collection diagonalises the eigenspace meanwhile (CG needs a fixed operator).
 static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *b, double2 *x, int nf,
-                 const std::vector<int> &mask, double tol, double epsA, bool precond, ovl_stats *st)
+                 const std::vector<int> &mask, double tol, double epsA, bool precond, bool collect, ovl_stats *st)
 {
     const size_t FB = field_bytes(c.g, OVL_F64);
     double2 *r = (double2 *)c.buf("cg_r", FB * nf);
@@ -462,6 +466,11 @@ static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, co
     double2 *xj = (double2 *)c.buf("cg_x", FB * nf);
     double2 *w = (double2 *)c.buf("cg_w", FB * nf);
     double2 *t = (double2 *)c.buf("cg_t", FB * nf);
+    double2 *hh = collect ? (double2 *)c.buf("cg_hh", FB * nf) : w;
+    struct Hold {
+        EigSpace &e;
+        ~Hold() { e.spec_hold = false; }
+    } hold{c.eig};
     auto P = [&](const double2 *in, double2 *out) {
         if (precond)
             spectral_apply(c, in, out, nf);
@@ -471,6 +480,7 @@ static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, co
     std::vector<double> bn, rr(nf, 0.0), r0n(nf, 0.0), zeta(nf, 0.0);
     norms(c, b, nf, bn);
     P(b, r);
+    if (precond) c.eig.spec_hold = true;
     copy_fields(c, r, p, nf, OVL_F64);
     zero_fields(c, xj, nf, OVL_F64);
     std::vector<int> act(nf, 0), its(nf, 0);
@@ -493,12 +503,14 @@ static void cgne(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, co
             nact += act[f];
         }
         if (nact == 0) break;
+        const double cap = collect ? eig_sign_accuracy(c) : 1.0;
         for (int f = 0; f < nf; ++f)
-            eta[f] = act[f] ? std::fmin(prm.relax_floor, epsA * r0n[f] * std::sqrt(zeta[f])) : 0.0;
+            eta[f] = act[f] ? std::fmin(cap, std::fmin(prm.relax_floor, epsA * r0n[f] * std::sqrt(zeta[f]))) : 0.0;
         P(p, w);
         apply_H(c, z, prm, w, t, nf, eta.data(), st);
-        apply_H(c, z, prm, t, w, nf, eta.data(), st);
-        P(w, t);   // t = Hhat^{-1} H^2 Hhat^{-1} p
+        apply_H(c, z, prm, t, hh, nf, eta.data(), st);
+        if (collect) eig_collect_cg(c, w, t, hh);
+        P(hh, t);   // t = Hhat^{-1} H^2 Hhat^{-1} p
         std::vector<zc> rz;
         dots(c, r, t, nf, rz);
         std::vector<zc> ma(nf, 0.0), pa(nf, 0.0), one(nf, 1.0);
@@ -554,8 +566,6 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
     OVL_REQUIRE(nf >= 1 && nf <= MAXF, OVL_ERR_ARG, "too many right-hand sides in one batch");
     OVL_REQUIRE(!(prm.eig_calc && nf > 1), OVL_ERR_ARG,
                 "eigSUMR collects from one right-hand side at a time (solve calculating right-hand sides singly)");
-    OVL_REQUIRE(!(prm.eig_calc && prm.middle_cg), OVL_ERR_UNSUPPORTED,
-                "collecting eigenvectors during a CG middle solve (eigCG) is not provided; use the SUMR middle solve");
     const auto t0 = std::chrono::steady_clock::now();
     const double mu = prm.mu;
     const double rhoK = prm.rho;
@@ -596,8 +606,14 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
             copy_fields(c, r, bp, nf, OVL_F64);
             gamma5_f64(c, bp, nf);
             const bool pre = prm.use_deflation && spectral_available(c);
+            const bool collect = prm.eig_calc != 0;
             zero_fields(c, uu, nf, OVL_F64);
-            cgne(c, z, prm, bp, uu, nf, active, prm.eta_tilde, prm.eta_tilde, pre, st);
+            cgne(c, z, prm, bp, uu, nf, active, prm.eta_tilde, prm.eta_tilde, pre, collect, st);
+            if (collect) {
+                eig_diagonalise(c);   // Alg. 6 closes each calculating middle solve
+                if (c.eig.ndiag > 0 && prm.k_recalc > 0 && c.eig.ndiag % prm.k_recalc == 0)
+                    eig_recompute(c, rhoK, z, 1e-12, nullptr);
+            }
         } else {
         // middle solve D u = r to relative accuracy eta_tilde: (1 + rho U) u = 2 r/(1 + mu)
         {
