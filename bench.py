@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--eig-calc", type=int, default=3, help="eigSUMR leg: calculating solves")
     ap.add_argument("--eig-n", type=int, default=20, help="eigSUMR leg: eigenvectors kept (n)")
     ap.add_argument("--eig-m", type=int, default=60, help="eigSUMR leg: basis size of Alg. 6 (m)")
+    ap.add_argument("--eigcg", action="store_true",
+                    help="add the GMRESR(eigCG) leg on 16^3x32 (calculating solves, then deflated solves)")
+    ap.add_argument("--eigcg-calc", type=int, default=5, help="eigCG leg: calculating solves")
     ap.add_argument("--tuning", default=None,
                     help="JSON of stencil launch choices to install instead of autotuning (the 'tuning' "
                          "object an earlier run printed), so that profiler runs see the same kernels")
@@ -356,6 +359,51 @@ def eig_leg(torch, ovl, n_calc=3, n_eig=20, m_eig=60):
     return out
 
 
+def eigcg_leg(torch, ovl, n_calc=5, n_eig=20, m_eig=60):
+    """GMRESR(eigCG) on the 16^3 x 32 workload (Sec. 5 collection on the relCG
+    middle solve, the Sec. 4 spectral preconditioner from the vectors held):
+    n_calc calculating solves on spin-colour point sources at site 0, then a
+    fresh point source solved four ways -- relCG preconditioned with the
+    eigCG vectors, relCG undeflated, relSUMR started from the same vectors'
+    deflation projection, relSUMR undeflated -- all mixed precision to 1e-10."""
+    ctx, zolo, _ = setup_c2(ovl)
+    B = torch.stack([ctx.source(ovl.SRC_POINT, site=0, spin=i % 4, colour=i % 3) for i in range(n_calc + 1)])
+
+    def params(cg, calc, defl):
+        p = solve_params(ovl, True, 3e-3)
+        p.middle_cg, p.eig_calc, p.use_deflation = cg, calc, defl
+        p.n_eig, p.m_eig, p.eta_tilde, p.verbose = n_eig, m_eig, 1e-3, 1
+        return p
+
+    def run(b, p):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, code = ctx.solve(b, zolo, p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        Dx, _ = ctx.overlap(x, RHO, MU, zolo, 1e-13)
+        res = float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b))
+        d = st[0].as_dict()
+        return {"status": code, "seconds": dt, "true_relres": res, "cg_or_sumr_iters": d["sumr_iters"],
+                "sign_calls": d["sign_calls"], "mscg_iters": d["mscg_iters"], "gmresr_steps": d["gmresr_steps"]}
+
+    out = {"lattice": "16x16x16x32", "mu": MU, "n_eig": n_eig, "m_eig": m_eig, "calculating": []}
+    for i in range(n_calc):
+        out["calculating"].append(run(B[i:i + 1], params(1, 1, 1)))
+        print(f"[bench] eigCG calculating solve {i} done", file=sys.stderr, flush=True)
+    info = ctx.eigspace_info()
+    out["eigenspace"] = {"held": info["held"], "diagonalisations": info["ndiag"],
+                         "ritz": info["ritz"], "resid": info["resid"]}
+    b = B[n_calc:n_calc + 1]
+    out["relcg_preconditioned"] = run(b, params(1, 0, 1))
+    out["relcg_undeflated"] = run(b, params(1, 0, 0))
+    out["relsumr_deflated_start"] = run(b, params(0, 0, 1))
+    out["relsumr_undeflated"] = run(b, params(0, 0, 0))
+    print("[bench] eigCG comparison solves done", file=sys.stderr, flush=True)
+    ctx.close()
+    return out
+
+
 def c1_leg(torch, ovl, reps=10):
     """The plain method on 4^4 (links eps 0.3 seed 1, rho 1.4, N_Z = 16 on
     [lambda_min, lambda_max] of |K| from the GPU's Lanczos, no exact modes,
@@ -595,6 +643,9 @@ def main():
         out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
         out["tuning"].update(out["dslash_hbm"].pop("tuning"))
         print("[bench] stand-alone stencil done", file=sys.stderr, flush=True)
+    if args.eigcg:
+        out["eigcg_16c32"] = eigcg_leg(torch, ovl, args.eigcg_calc)
+        print("[bench] eigCG leg done", file=sys.stderr, flush=True)
     if args.eig:
         out["eigsumr_24c48"] = eig_leg(torch, ovl, args.eig_calc, args.eig_n, args.eig_m)
         print("[bench] eigSUMR leg done", file=sys.stderr, flush=True)
