@@ -22,6 +22,21 @@ Readings where the paper is silent or garbled (also listed in the design notes):
 * The subspace size m is not given for the inversions: m = n + 40 unless
   set; v^D is recomputed accurately every k diagonalisations and when the
   eigenvector phase ends.
+* Standalone eigSUMR eigensolver (Sec. 6, eigenvector calculation): each
+  run generates the Alg. 1 basis from its start vector with Alg. 5
+  collection, and ends after 24 diagonalisations, when | ||q|| - 1 | > 0.1 or
+  |gamma| >= 1, or when every held eigenvector's residual is at most the
+  run's target; at the end of a run Alg. 6 closes it, v^D is recomputed
+  accurately, and one more Rayleigh-Ritz runs over the current eigenvectors
+  and those kept at the previous two restarts (the three-set
+  re-diagonalisation of Sec. 5).  Those sets overlap more and more as the
+  vectors converge, so that Rayleigh-Ritz orthonormalises canonically
+  (eigenvectors of V^H V with eigenvalues below 1e-10 of the largest are
+  dropped) instead of by Cholesky.  The next run starts from the last q,
+  orthogonalised (twice) against the eigenvectors and normalised; its target
+  is the larger of the final accuracy and a tenth of the largest residual at
+  the restart (the paper sets each run's tolerance below the residual it
+  expects next, without a rule).
 * eigCG (Sec. 5 describes it in words only): every CG iteration adds two
   basis vectors, the preconditioned direction w = Hhat^{-1} p and H w (the
   paper keeps both p and gamma_5 D p), each scaled to unit norm, with their
@@ -268,3 +283,81 @@ def gmresr_eigcg(overlap, b, eps, eta_tilde, eig, calc=True, floor=1e-2, maxiter
         return res.x, res.iters
 
     return krylov.gmresr(apply_A, middle, b, 0.5 * eps)
+
+
+def rediagonalise_sets(sets, n, mu, delta, cut=1e-10):
+    """Rayleigh-Ritz of Alg. 6 (same pair-splitting M) over the union of the
+    eigenvector sets [(V, VD), ...], orthonormalised canonically: with
+    V^H V = W diag(l) W^H and B = W_k diag(l_k^{-1/2}) over l_k > cut max(l),
+    the eigenpairs (theta, Y) of B^H M B give v = V B Y[:, :n]."""
+    V = _mat([v for vs, _ in sets for v in vs])
+    VD = _mat([d for _, ds in sets for d in ds])
+    N = V.shape[0]
+    E = V.conj().T @ V
+    lam, W = np.linalg.eigh(0.5 * (E + E.conj().T))
+    keep = lam > cut * lam.max()
+    B = W[:, keep] / np.sqrt(lam[keep])
+    G5VD = (g5(VD.T.reshape((VD.shape[1], N // 12, 4, 3))).reshape(VD.shape[1], -1)).T
+    M = VD.conj().T @ VD + 2.0 * mu * delta * (V.conj().T @ G5VD)
+    G = B.conj().T @ (0.5 * (M + M.conj().T)) @ B
+    theta, Y = np.linalg.eigh(0.5 * (G + G.conj().T))
+    C = B @ Y[:, :n]
+    return V @ C, VD @ C, theta[:n]
+
+
+class EigensolverRun:
+    def __init__(self, applies, ritz, resid, ndiag, rank):
+        self.applies, self.ritz, self.resid, self.ndiag, self.rank = applies, ritz, resid, ndiag, rank
+
+
+def eigsumr_eigensolver(overlap, q0, eig, restarts=10, diag_per_restart=24, relaxed=True, eta_full=1e-12,
+                        recompute_eta=1e-13):
+    """The standalone eigSUMR eigensolver (module notes): runs of the Alg. 1
+    basis with Alg. 5 collection at the Sec. 5.1 sign accuracy (relaxed) or
+    at eta_full, each closed by Alg. 6, an accurate v^D and the three-set
+    re-diagonalisation; stops when every residual is at most eig.eps as
+    given.  Returns one EigensolverRun per restart (U applications so far,
+    Ritz values and residuals after it)."""
+    n = eig.n
+    eps_final = eig.eps
+    q = q0 / norm(q0)
+    kept = []
+    runs = []
+    applies = 0
+    for _ in range(restarts):
+        q_t = q.copy()
+        nd0 = eig.ndiag
+        while eig.ndiag - nd0 < diag_per_restart:
+            u = overlap.U(q, eig.sign_accuracy() if relaxed else eta_full)
+            applies += 1
+            eig.collect(q, u)
+            gamma = dot(q_t, u)
+            if abs(gamma) >= 1.0:
+                break
+            sigma = np.sqrt(1.0 - abs(gamma) ** 2)
+            gamma = -gamma
+            q = (gamma * q_t + u) / sigma
+            q_t = sigma * q_t + np.conj(gamma) * q
+            if abs(norm(q) - 1.0) > 0.1:
+                break
+            if eig.theta is not None and eig.ritz()[1].max() <= eig.eps:
+                break
+        eig.diagonalise()
+        eig.recompute(overlap, recompute_eta)
+        cur = ([v.copy() for v in eig.V[:n]], [d.copy() for d in eig.VD[:n]])
+        v, vD, theta = rediagonalise_sets([cur] + kept[::-1], n, eig.mu, eig.delta)
+        eig.V = [v[:, i].reshape(eig.shape) for i in range(n)]
+        eig.VD = [vD[:, i].reshape(eig.shape) for i in range(n)]
+        eig.theta = theta
+        kept = (kept + [(list(eig.V), list(eig.VD))])[-2:]
+        vals, res = eig.ritz()
+        runs.append(EigensolverRun(applies, vals, res, eig.ndiag, None))
+        if res.max() <= eps_final:
+            break
+        eig.eps = max(eps_final, 0.1 * res.max())
+        for _ in range(2):
+            for vi in eig.V:
+                q = q - dot(vi, q) * vi
+        q = q / norm(q)
+    eig.eps = eps_final
+    return runs
