@@ -267,6 +267,34 @@ ovl_status ovl_eigspace_set(ovl_context *ctx, int32_t n, int32_t m, double mu, d
 ovl_status ovl_eigspace_diagonalise(ovl_context *ctx);
 /* Recompute v^D = D v for the held vectors with FP64 sign accuracy eta. */
 ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *zolo, double eta);
+/* The standalone eigSUMR eigensolver (Sec. 6, eigenvector calculation; Algs.
+ * 1, 5, 6, the Sec. 5.1 relaxation, the three-set re-diagonalisation of Sec. 5)
+ * for the n_eig lowest eigenvectors of gamma_5 D[mu] (lowest in
+ * D^+ D + 2 mu delta gamma_5 D), from the start vector q0_dev (canonical
+ * complex128 [V][4][3], device, one field, not modified).  Used from params:
+ * rho, mu, n_eig (3 n_eig <= 512), m_eig (> n_eig), eig_eps (target residual),
+ * delta_split, norm_restart, k_recalc, f32_threshold / half_threshold (the
+ * precision of each sign call), max_mscg, verbose (one line per run).
+ * Runs: each generates the Alg. 1 basis of U = gamma_5 sign(K) from its start
+ * vector, collecting every (q, U q); it ends after diag_per_run
+ * diagonalisations, when | ||q|| - 1 | > norm_restart or |gamma| >= 1, or when
+ * every residual is at most the run's target; then Alg. 6, v^D recomputed to
+ * 1e-12, and one Rayleigh-Ritz over the eigenvectors and those kept at the
+ * previous two runs (canonically orthonormalised, directions below 1e-10 of
+ * the largest Gram eigenvalue dropped).  The next run starts from the last q
+ * orthogonalised against the eigenvectors, with the target max(eig_eps, 0.1 x
+ * the largest residual).  Sign accuracy per application: the Sec. 5.1 bound
+ * when eta_fixed <= 0, else eta_fixed.  The eigenvectors are left in the
+ * context's eigenspace (ovl_eigspace_info / _get; usable for deflation).
+ * Host outputs (each may be null): runs_out; applies_hist[max_runs] and
+ * maxres_hist[max_runs], the U applications so far and the largest residual
+ * after each run; stats (one entry; sumr_iters = U applications).  Returns
+ * OVL_OK when every residual reached eig_eps, OVL_ERR_NOT_CONVERGED after
+ * max_runs runs, OVL_ERR_BREAKDOWN on a non-finite basis vector. */
+ovl_status ovl_eigsumr_eigensolve(ovl_context *ctx, const ovl_zolo *zolo, const ovl_solver_params *params,
+                                  const double *q0_dev, int32_t max_runs, int32_t diag_per_run, double eta_fixed,
+                                  int32_t *runs_out, int64_t *applies_hist, double *maxres_hist,
+                                  ovl_stats *stats);
 /* Sec. 4 deflated start: x0 = sum_j alpha_j psi'_j and D x0 = sum_j alpha_j D psi'_j,
  * alpha_j = (D psi'_j, b)/(D psi'_j, D psi'_j), over the held vectors rotated
  * so that (psi'_i, gamma_5 D psi'_j) is diagonal; nrhs fields (canonical). */

@@ -79,7 +79,7 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
            "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option",
-           "ovl_sumr_gmresr_solve_many"]
+           "ovl_sumr_gmresr_solve_many", "ovl_eigsumr_eigensolve"]
 
 _lib = None
 
@@ -124,6 +124,7 @@ def lib():
         "ovl_eigspace_diagonalise": ([P], I32),
         "ovl_eigspace_recompute": ([P, D, P, D], I32),
         "ovl_deflate_project": ([P, P, P, P, I32], I32),
+        "ovl_eigsumr_eigensolve": ([P, P, P, P, I32, I32, D, P, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -333,6 +334,21 @@ class Context:
 
     def eigspace_recompute(self, rho, zolo, eta=1e-12):
         _check(lib().ovl_eigspace_recompute(self._h, float(rho), ctypes.byref(zolo), float(eta)))
+
+    def eigensolve(self, q0, zolo, params, max_runs=10, diag_per_run=24, eta_fixed=0.0):
+        """Standalone eigSUMR eigensolver from the start vector q0 [V,4,3]; the
+        eigenvectors stay in the eigenspace.  Returns (status, per-run list of
+        (U applications so far, largest residual), Stats); status -4 when the
+        residual target was not reached within max_runs runs."""
+        runs = ctypes.c_int32()
+        ap = (ctypes.c_int64 * max_runs)()
+        mr = (ctypes.c_double * max_runs)()
+        st = Stats()
+        code = _check(lib().ovl_eigsumr_eigensolve(self._h, ctypes.byref(zolo), ctypes.byref(params),
+                                                   _dev(q0, (self.V, 4, 3), "q0"), int(max_runs), int(diag_per_run),
+                                                   float(eta_fixed), ctypes.byref(runs), ap, mr,
+                                                   ctypes.byref(st)), (-4,))
+        return code, [(ap[i], mr[i]) for i in range(runs.value)], st
 
     def deflate_project(self, b):
         x0 = torch.empty_like(b)

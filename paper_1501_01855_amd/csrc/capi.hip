@@ -428,6 +428,33 @@ ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *
     });
 }
 
+ovl_status ovl_eigsumr_eigensolve(ovl_context *ctx, const ovl_zolo *zolo, const ovl_solver_params *params,
+                                  const double *q0_dev, int32_t max_runs, int32_t diag_per_run, double eta_fixed,
+                                  int32_t *runs_out, int64_t *applies_hist, double *maxres_hist, ovl_stats *stats)
+{
+    ovl_status res = OVL_OK;
+    ovl_status st = guard([&] {
+        check_ctx(ctx);
+        check_zolo(zolo);
+        OVL_REQUIRE(params != nullptr && q0_dev != nullptr, OVL_ERR_ARG, "bad eigensolver arguments");
+        const ovl_solver_params &p = *params;
+        OVL_REQUIRE(p.mu >= 0.0 && p.mu < 1.0 && p.eig_eps > 0.0 && p.norm_restart > 0.0 && p.max_mscg >= 1 &&
+                        p.m_eig > p.n_eig && p.n_eig >= 1 && p.delta_split >= 0.0 && p.delta_split < 0.5,
+                    OVL_ERR_ARG, "invalid eigensolver parameters");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        if (stats) std::memset(stats, 0, sizeof(ovl_stats));
+        double2 *q0 = (double2 *)ctx->buf("api_q0", field_bytes(ctx->g, OVL_F64));
+        pack_spinor(*ctx, q0_dev, q0, 1, OVL_F64);
+        int runs = 0;
+        res = eig_eigensolve(*ctx, *zolo, p, q0, max_runs, diag_per_run, eta_fixed, &runs, applies_hist,
+                             maxres_hist, stats);
+        if (runs_out) *runs_out = runs;
+        ctx->prof_collect();
+        if (res != OVL_OK) set_error("eigensolver: residual target not reached within max_runs runs");
+    });
+    return st != OVL_OK ? st : res;
+}
+
 ovl_status ovl_deflate_project(ovl_context *ctx, const double *b_dev, double *x0_dev, double *Dx0_dev, int32_t nrhs)
 {
     return guard([&] {

@@ -29,6 +29,7 @@ struct EigSpace {
     int krecalc = 25;
     double2 *V = nullptr, *VD = nullptr;   // [m] packed FP64 fields each
     int ndiag = 0;
+    int nsets = 0;   // eigenvector sets kept from earlier eigensolver restarts (0..2)
     std::vector<double> uv_hist, ritz, resid;
     bool defl_ready = false;
     int ndefl = 0;

@@ -52,6 +52,7 @@ void eig_configure(Context &c, int n, int m, double mu, double delta, double eps
         e.VD = (double2 *)c.buf("eig_VD", FB * (size_t)m);
         e.k = 0;
         e.ndiag = 0;
+        e.nsets = 0;
         e.uv_hist.clear();
         e.ritz.clear();
         e.resid.clear();
@@ -163,6 +164,80 @@ void eig_diagonalise(Context &c)
     e.spec_ready = false;
 }
 
+// The three-set re-diagonalisation of Sec. 5 at an eigensolver restart:
+// Rayleigh-Ritz with Alg. 6's M over the n held eigenvectors and the sets
+// kept at the previous two restarts.  The sets converge towards each other, so
+// the basis is orthonormalised canonically (V^H V = W diag(l) W^H, directions
+// with l <= 1e-10 max(l) dropped, B = W_k diag(l_k^{-1/2})) instead of by
+// Cholesky.  The result replaces the held eigenvectors and becomes the newest
+// kept set.  Needs accurate v^D for every set.
+void eig_rediagonalise_sets(Context &c)
+{
+    EigSpace &e = c.eig;
+    const int n = e.n;
+    OVL_REQUIRE(e.k >= n && e.ndiag > 0, OVL_ERR_STATE, "re-diagonalisation needs n held eigenvectors");
+    const size_t FB = field_bytes(c.g, OVL_F64);
+    const size_t fs = (size_t)12 * c.g.V;
+    double2 *SV = (double2 *)c.buf("eig_setsV", FB * 3 * n);
+    double2 *SD = (double2 *)c.buf("eig_setsD", FB * 3 * n);
+    // slot 0 takes the current eigenvectors; slots 1, 2 hold the kept sets
+    copy_fields(c, e.V, SV, n, OVL_F64);
+    copy_fields(c, e.VD, SD, n, OVL_F64);
+    const int k = n * (1 + e.nsets);
+    std::vector<cplx<double>> g;
+    gram_f64(c, SV, k, SV, k, false, g);
+    const std::vector<zc> E = to_z(g);
+    gram_f64(c, SD, k, SD, k, false, g);
+    const std::vector<zc> MD = to_z(g);
+    gram_f64(c, SV, k, SD, k, true, g);
+    const std::vector<zc> G5M = to_z(g);
+    std::vector<double> lam;
+    std::vector<zc> W;
+    dense::eigh(k, E, lam, W);
+    const double lmax = lam.back();
+    std::vector<int> keep;
+    for (int j = 0; j < k; ++j)
+        if (lam[j] > 1e-10 * lmax) keep.push_back(j);
+    const int r = (int)keep.size();
+    OVL_REQUIRE(r >= n, OVL_ERR_BREAKDOWN, "re-diagonalisation: the sets span fewer than n directions");
+    std::vector<zc> B((size_t)k * r);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < r; ++j) B[(size_t)i * r + j] = W[(size_t)i * k + keep[j]] / std::sqrt(lam[keep[j]]);
+    std::vector<zc> M((size_t)k * k);
+    const double sp = 2.0 * e.mu * e.delta;
+    for (size_t i = 0; i < M.size(); ++i) M[i] = MD[i] + sp * G5M[i];
+    const std::vector<zc> G = dense::matmul_ah(k, r, r, B, dense::matmul(k, k, r, M, B));
+    std::vector<double> th;
+    std::vector<zc> Y;
+    dense::eigh(r, G, th, Y);
+    std::vector<zc> Yn((size_t)r * n);
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < n; ++j) Yn[(size_t)i * n + j] = Y[(size_t)i * r + j];
+    const std::vector<zc> C = dense::matmul(k, r, n, B, Yn);
+    const std::vector<zc> A1 = dense::matmul_ah(k, n, n, C, dense::matmul(k, k, n, G5M, C));
+    const std::vector<zc> A2 = dense::matmul_ah(k, n, n, C, dense::matmul(k, k, n, MD, C));
+    e.ritz.assign(n, 0.0);
+    e.resid.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        const double h = A1[(size_t)i * n + i].real();
+        e.ritz[i] = h;
+        e.resid[i] = std::sqrt(std::max(0.0, A2[(size_t)i * n + i].real() - h * h));
+    }
+    const std::vector<cplx<double>> Cc = from_z(C);
+    rotate_f64(c, SV, k, Cc, n, e.V, 0.0);
+    rotate_f64(c, SD, k, Cc, n, e.VD, 0.0);
+    // kept sets: slot 2 <- slot 1, slot 1 <- the new eigenvectors
+    if (e.nsets >= 1) {
+        copy_fields(c, SV + (size_t)n * fs, SV + (size_t)2 * n * fs, n, OVL_F64);
+        copy_fields(c, SD + (size_t)n * fs, SD + (size_t)2 * n * fs, n, OVL_F64);
+    }
+    copy_fields(c, e.V, SV + (size_t)n * fs, n, OVL_F64);
+    copy_fields(c, e.VD, SD + (size_t)n * fs, n, OVL_F64);
+    e.nsets = std::min(2, e.nsets + 1);
+    e.k = n;
+    e.defl_ready = false;
+    e.spec_ready = false;
+}
 // Eq. (bound) of Sec. 5.1 as a sign-function accuracy.
 double eig_sign_accuracy(const Context &c)
 {

@@ -47,6 +47,10 @@ void eig_configure(Context &c, int n, int m, double mu, double delta, double eps
 void eig_collect(Context &c, const double2 *q, const double2 *u);
 void eig_collect_cg(Context &c, const double2 *w, const double2 *hw, const double2 *hhw);
 void eig_diagonalise(Context &c);
+void eig_rediagonalise_sets(Context &c);
+ovl_status eig_eigensolve(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *q0,
+                          int max_runs, int diag_per_run, double eta_fixed, int *runs_out, int64_t *applies_hist,
+                          double *maxres_hist, ovl_stats *st);
 double eig_sign_accuracy(const Context &c);
 void eig_recompute(Context &c, double rho, const ovl_zolo &z, double eta, ovl_stats *st);
 void eig_project(Context &c, const double2 *b, double2 *x0, double2 *Dx0);

@@ -704,4 +704,102 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
     return status;
 }
 
+// The standalone eigSUMR eigensolver (Sec. 6, eigenvector calculation).
+// Each run generates the Alg. 1 basis of U = gamma_5 sign(K) from its start
+// vector and feeds every (q, U q) to Alg. 5; it ends after diag_per_run
+// diagonalisations, when | ||q|| - 1 | > norm_restart or |gamma| >= 1, or when
+// every held eigenvector's residual is at most the run's target.  Alg. 6
+// closes the run, v^D is recomputed to 1e-12, and the three-set
+// re-diagonalisation follows.  Sign accuracy: the Sec. 5.1 bound (eta_fixed
+// <= 0) or eta_fixed.  The next run starts from the last q, orthogonalised
+// twice against the eigenvectors and normalised, with the target
+// max(eig_eps, 0.1 x the largest residual).  Stops when every residual is
+// at most eig_eps (OVL_OK) or after max_runs runs (OVL_ERR_NOT_CONVERGED).
+ovl_status eig_eigensolve(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *q0,
+                          int max_runs, int diag_per_run, double eta_fixed, int *runs_out, int64_t *applies_hist,
+                          double *maxres_hist, ovl_stats *st)
+{
+    OVL_REQUIRE(max_runs >= 1 && diag_per_run >= 1, OVL_ERR_ARG, "eigensolver: bad run limits");
+    OVL_REQUIRE(prm.n_eig >= 1 && 3 * prm.n_eig <= 512, OVL_ERR_ARG,
+                "eigensolver: n_eig must be at most 170 (three sets of n are diagonalised together)");
+    const auto t0 = std::chrono::steady_clock::now();
+    eig_configure(c, prm.n_eig, prm.m_eig, prm.mu, prm.delta_split, prm.eig_eps, prm.k_recalc);
+    EigSpace &e = c.eig;
+    const int n = e.n;
+    e.nsets = 0;
+    const double eps_final = prm.eig_eps;
+    struct EpsRestore {
+        EigSpace &e;
+        double v;
+        ~EpsRestore() { e.eps = v; }
+    } restore{e, eps_final};
+    const size_t FB = field_bytes(c.g, OVL_F64);
+    double2 *q = (double2 *)c.buf("es_q", FB);
+    double2 *qt = (double2 *)c.buf("es_qt", FB);
+    double2 *u = (double2 *)c.buf("es_u", FB);
+    std::vector<double> nn;
+    norms(c, q0, 1, nn);
+    OVL_REQUIRE(nn[0] > 0.0 && std::isfinite(nn[0]), OVL_ERR_ARG, "eigensolver: zero or non-finite start vector");
+    lincomb3_f64(c, 1.0 / nn[0], q0, 0.0, q0, 0.0, nullptr, q, 1);
+    int64_t applies = 0;
+    ovl_status status = OVL_ERR_NOT_CONVERGED;
+    int runs = 0;
+    for (int run = 0; run < max_runs; ++run) {
+        copy_fields(c, q, qt, 1, OVL_F64);
+        const int nd0 = e.ndiag;
+        while (e.ndiag - nd0 < diag_per_run) {
+            double eta = eta_fixed > 0.0 ? eta_fixed : eig_sign_accuracy(c);
+            unitary_f64(c, prm.rho, z, q, u, 1, &eta, prm, st);
+            applies += 1;
+            eig_collect(c, q, u);
+            std::vector<zc> g;
+            dots(c, qt, u, 1, g);
+            zc gamma = g[0];
+            if (!(std::abs(gamma) < 1.0)) break;
+            const double sigma = std::sqrt(1.0 - std::norm(gamma));
+            gamma = -gamma;
+            // Alg. 1: q = (gamma q~ + U q) / sigma, q~ = sigma q~ + conj(gamma) q
+            axpby(c, {gamma / sigma}, qt, {0.0}, q, 1);
+            axpby(c, {1.0 / sigma}, u, {1.0}, q, 1);
+            axpby(c, {std::conj(gamma)}, q, {sigma}, qt, 1);
+            std::vector<double> qn;
+            norms(c, q, 1, qn);
+            if (!std::isfinite(qn[0])) throw Error{OVL_ERR_BREAKDOWN, "eigensolver: non-finite basis vector"};
+            if (std::fabs(qn[0] - 1.0) > prm.norm_restart) break;
+            if (!e.resid.empty() && *std::max_element(e.resid.begin(), e.resid.end()) <= e.eps) break;
+        }
+        eig_diagonalise(c);
+        eig_recompute(c, prm.rho, z, 1e-12, st);
+        eig_rediagonalise_sets(c);
+        runs = run + 1;
+        const double mr = *std::max_element(e.resid.begin(), e.resid.end());
+        if (applies_hist) applies_hist[run] = applies;
+        if (maxres_hist) maxres_hist[run] = mr;
+        if (prm.verbose)
+            std::fprintf(stderr, "[ovl] eigensolver run %d: %lld applications of U, largest residual %.3e\n", run + 1,
+                         (long long)applies, mr);
+        if (mr <= eps_final) {
+            status = OVL_OK;
+            break;
+        }
+        e.eps = std::max(eps_final, 0.1 * mr);
+        for (int pass = 0; pass < 2; ++pass) {   // q -= V (V^H q)
+            std::vector<cplx<double>> a;
+            gram_f64(c, e.V, n, q, 1, false, a);
+            for (auto &x : a) x = {-x.re, -x.im};
+            rotate_f64(c, e.V, n, a, 1, q, 1.0);
+        }
+        norms(c, q, 1, nn);
+        OVL_REQUIRE(nn[0] > 0.0 && std::isfinite(nn[0]), OVL_ERR_BREAKDOWN,
+                    "eigensolver: the restart vector lies in the eigenspace");
+        lincomb3_f64(c, 1.0 / nn[0], q, 0.0, q, 0.0, nullptr, u, 1);
+        copy_fields(c, u, q, 1, OVL_F64);
+    }
+    OVL_HIP(hipStreamSynchronize(c.stream));
+    if (runs_out) *runs_out = runs;
+    if (st) st->sumr_iters += applies;
+    if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
 }  // namespace ovl

@@ -139,3 +139,67 @@ def test_eigsumr_trajectory_matches_oracle(lat):
     # (within its residual; not necessarily the six smallest)
     for th, r in zip(info["ritz"], info["resid"]):
         assert np.min(np.abs(lat["h"] - th)) <= min(1e-4, r)
+
+
+def test_eigensolver_matches_oracle(lat):
+    """The standalone eigensolver (Sec. 6: Alg. 1 basis, Alg. 5 collection,
+    Alg. 6, v^D recomputed, three-set re-diagonalisation, restarts) at sign
+    accuracy 1e-10 on the GPU and in the oracle from the same Z2 start.  The
+    Alg. 1 recurrence amplifies rounding geometrically, so a run that ends at
+    | ||q|| - 1 | > 0.1 ends an iteration earlier or later on either side.
+    With two diagonalisations per run every run ends by count, well before
+    that: three runs then agree (same U applications, largest residuals
+    within 1 %, Ritz values within 1e-5).  With 24 per run (each run ends by
+    the norm test) both sides reduce the largest residual at least twofold
+    over four runs, to within a factor four of each other.  Every Ritz value
+    lies within its residual of an eigenvalue of gamma_5 D (dense)."""
+    ovl = require_gpu()
+    p = ovl.solver_defaults(rho=1.4, mu=MU, n_eig=6, m_eig=30, eig_eps=1e-6, f32_threshold=10.0,
+                            half_threshold=10.0)
+    q0 = synth.z2_source(lat["dims"], 5)
+    ov = krylov.Overlap(krylov.SignFunction(lat["k"], lat["z"]), MU)
+    results = {}
+    for nruns, per in ((3, 2), (4, 24)):
+        ctx, zg = _ctx(ovl, lat)
+        code, hist, st = ctx.eigensolve(to_dev(q0), zg, p, max_runs=nruns, diag_per_run=per, eta_fixed=1e-10)
+        assert code == -4 and len(hist) == nruns and st.sumr_iters == hist[-1][0]
+        E = eig.EigSUMR(6, 30, MU, eps=1e-6)
+        runs = eig.eigsumr_eigensolver(ov, q0, E, restarts=nruns, diag_per_restart=per, relaxed=False,
+                                       eta_full=1e-10)
+        info = ctx.eigspace_info()
+        print("runs", nruns, "gpu", hist, "oracle", [(r.applies, r.resid.max()) for r in runs])
+        print("  ritz gpu", np.round(np.sort(info["ritz"]), 7), "oracle", np.round(np.sort(runs[-1].ritz), 7))
+        for th, r in zip(info["ritz"], info["resid"]):
+            assert np.min(np.abs(lat["h"] - th)) <= r + 1e-12
+        results[per] = (hist, runs, info)
+    hist, runs, info = results[2]
+    for (a, m), r in zip(hist, runs):
+        assert a == r.applies
+        assert abs(m - r.resid.max()) <= 0.01 * r.resid.max()
+    assert np.abs(np.sort(info["ritz"]) - np.sort(runs[-1].ritz)).max() < 1e-5
+    hist, runs, info = results[24]
+    g_last, o_last = hist[-1][1], runs[-1].resid.max()
+    assert g_last < 0.5 * hist[0][1] and o_last < 0.5 * runs[0].resid.max()
+    assert 0.25 * o_last <= g_last <= 4.0 * o_last
+
+
+def test_eigensolver_relaxed_runs_and_deflates(lat):
+    """With the Sec. 5.1 relaxation: three runs finish with a smaller largest
+    residual than the first, Ritz values are valid (within their residuals
+    of dense eigenvalues), and a solve deflated with the result reaches
+    1e-10 with the dense D."""
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, lat)
+    p = ovl.solver_defaults(rho=1.4, mu=MU, n_eig=6, m_eig=30, eig_eps=1e-6, f32_threshold=1e-6,
+                            half_threshold=10.0)
+    code, hist, _ = ctx.eigensolve(to_dev(synth.z2_source(lat["dims"], 6)), zg, p, max_runs=3)
+    assert code == -4 and len(hist) == 3 and hist[-1][1] < hist[0][1]
+    info = ctx.eigspace_info()
+    for th, r in zip(info["ritz"], info["resid"]):
+        assert np.min(np.abs(lat["h"] - th)) <= r + 1e-12
+    ps = ovl.solver_defaults(rho=1.4, mu=MU, tol=1e-10, eta_tilde=1e-3, use_deflation=1, n_eig=6, m_eig=30,
+                             f32_threshold=1e-6)
+    b = synth.z2_source(lat["dims"], 71)
+    x, _, code = ctx.solve(to_dev(b), zg, ps)
+    assert code == 0
+    assert norm(b.reshape(-1) - lat["D"] @ to_host(x).reshape(-1)) <= 1e-10 * norm(b)
