@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--eigcg", action="store_true",
                     help="add the GMRESR(eigCG) leg on 16^3x32 (calculating solves, then deflated solves)")
     ap.add_argument("--eigcg-calc", type=int, default=5, help="eigCG leg: calculating solves")
+    ap.add_argument("--eigsolve", action="store_true",
+                    help="add the standalone eigSUMR eigensolver leg on 16^3x32 (relaxed and full accuracy)")
     ap.add_argument("--tuning", default=None,
                     help="JSON of stencil launch choices to install instead of autotuning (the 'tuning' "
                          "object an earlier run printed), so that profiler runs see the same kernels")
@@ -404,6 +406,34 @@ def eigcg_leg(torch, ovl, n_calc=5, n_eig=20, m_eig=60):
     return out
 
 
+def eigsolve_leg(torch, ovl, n_eig=30, m_eig=110, runs=8):
+    """The standalone eigSUMR eigensolver on the 16^3 x 32 workload (Sec. 6's
+    set-up: 30 eigenvectors and 80 further basis vectors, restart after 24
+    diagonalisations, target residual 1e-4), from a Z2 start, once with the
+    Sec. 5.1 relaxation (mixed-precision sign calls) and once at sign accuracy
+    1e-10 (FP64): U applications, seconds and the largest residual after
+    each run."""
+    out = {"lattice": "16x16x16x32", "mu": MU, "n_eig": n_eig, "m_eig": m_eig}
+    for name, eta in (("relaxed", 0.0), ("full_accuracy", 1e-10)):
+        ctx, zolo, _ = setup_c2(ovl)
+        q0 = ctx.source(ovl.SRC_Z2, seed=103)
+        p = solve_params(ovl, eta == 0.0, 3e-3)
+        p.n_eig, p.m_eig, p.eig_eps, p.verbose = n_eig, m_eig, 1e-4, 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, hist, st = ctx.eigensolve(q0, zolo, p, max_runs=runs, diag_per_run=24, eta_fixed=eta)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info = ctx.eigspace_info()
+        d = st.as_dict()
+        out[name] = {"status": code, "seconds": dt, "runs": [{"u_applications": a, "max_residual": m} for a, m in hist],
+                     "sign_calls": d["sign_calls"], "mscg_iters": d["mscg_iters"],
+                     "ritz": sorted(info["ritz"]), "residuals": info["resid"]}
+        print(f"[bench] eigensolver ({name}) done in {dt:.1f} s", file=sys.stderr, flush=True)
+        ctx.close()
+    return out
+
+
 def c1_leg(torch, ovl, reps=10):
     """The plain method on 4^4 (links eps 0.3 seed 1, rho 1.4, N_Z = 16 on
     [lambda_min, lambda_max] of |K| from the GPU's Lanczos, no exact modes,
@@ -646,6 +676,9 @@ def main():
     if args.eigcg:
         out["eigcg_16c32"] = eigcg_leg(torch, ovl, args.eigcg_calc)
         print("[bench] eigCG leg done", file=sys.stderr, flush=True)
+    if args.eigsolve:
+        out["eigsolve_16c32"] = eigsolve_leg(torch, ovl)
+        print("[bench] eigensolver leg done", file=sys.stderr, flush=True)
     if args.eig:
         out["eigsumr_24c48"] = eig_leg(torch, ovl, args.eig_calc, args.eig_n, args.eig_m)
         print("[bench] eigSUMR leg done", file=sys.stderr, flush=True)
