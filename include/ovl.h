@@ -103,7 +103,10 @@ typedef struct {
     int32_t max_mscg;      /* multi-shift CG iterations per sign call               */
     int32_t use_deflation; /* 1: start middle solves from the eigenspace projection (Sec. 4) */
     int32_t eig_calc;      /* 1: collect eigenvectors during this solve: eigSUMR
-                              (Alg. 5) or, with middle_cg, eigCG (Sec. 5)          */
+                              (Alg. 5) or, with middle_cg, eigCG (Sec. 5); the solve
+                              ends with the three-set re-diagonalisation of Sec. 5
+                              (its eigenvectors and those kept at the end of the
+                              previous two calculating solves)                    */
     int32_t n_eig;         /* eigSUMR: eigenvectors kept (n)                         */
     int32_t m_eig;         /* eigSUMR: basis size at which Alg. 6 runs (m > n)       */
     int32_t k_recalc;      /* eigSUMR: recompute v^D = D v every k diagonalisations   */

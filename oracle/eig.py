@@ -29,7 +29,9 @@ Readings where the paper is silent or garbled (also listed in the design notes):
   run's target; at the end of a run Alg. 6 closes it, v^D is recomputed
   accurately, and one more Rayleigh-Ritz runs over the current eigenvectors
   and those kept at the previous two restarts (the three-set
-  re-diagonalisation of Sec. 5).  Those sets overlap more and more as the
+  re-diagonalisation of Sec. 5, which the calculating solves of the
+  inverters also run once each, at the end of the solve, since every new
+  right-hand side restarts the Krylov space).  Those sets overlap more and more as the
   vectors converge, so that Rayleigh-Ritz orthonormalises canonically
   (eigenvectors of V^H V with eigenvalues below 1e-10 of the largest are
   dropped) instead of by Cholesky.  The next run starts from the last q,
@@ -124,6 +126,7 @@ class EigSUMR:
         self.uv_hist = []
         self.theta = None
         self.shape = None
+        self.kept = []   # eigenvector sets (V, VD) kept at the last two restarts
 
     def collect(self, q, u):
         self.shape = q.shape
@@ -154,6 +157,20 @@ class EigSUMR:
             vals.append(h)
             res.append(norm(g - h * v))
         return np.array(vals), np.array(res)
+
+    def rediagonalise_kept(self):
+        """The three-set re-diagonalisation of Sec. 5 (module notes): Alg. 6's
+        Rayleigh-Ritz over the n held eigenvectors and the sets kept at the
+        last two restarts; the result is held and kept."""
+        if self.theta is None or len(self.V) < self.n:
+            return
+        n = self.n
+        cur = ([v.copy() for v in self.V[:n]], [d.copy() for d in self.VD[:n]])
+        v, vD, theta = rediagonalise_sets([cur] + self.kept[::-1], n, self.mu, self.delta)
+        self.V = [v[:, i].reshape(self.shape) for i in range(n)]
+        self.VD = [vD[:, i].reshape(self.shape) for i in range(n)]
+        self.theta = theta
+        self.kept = (self.kept + [(list(self.V), list(self.VD))])[-2:]
 
     def recompute(self, apply_D, eta=1e-13):
         """v^D = D v to high accuracy (after the eigenvector phase / every k)."""
@@ -210,7 +227,10 @@ def gmresr_eigsumr(overlap, b, eps, eta_tilde, eig, calc=True, floor=1e-2, maxit
                 eig.recompute(overlap)
         return res.x, res.iters
 
-    return krylov.gmresr(apply_A, middle, b, 0.5 * eps)
+    res = krylov.gmresr(apply_A, middle, b, 0.5 * eps)
+    if calc:
+        eig.rediagonalise_kept()   # each new right-hand side restarts the Krylov space (Sec. 5)
+    return res
 
 
 def spectral_preconditioner(V, VD):
@@ -282,7 +302,10 @@ def gmresr_eigcg(overlap, b, eps, eta_tilde, eig, calc=True, floor=1e-2, maxiter
                 eig.recompute(overlap)
         return res.x, res.iters
 
-    return krylov.gmresr(apply_A, middle, b, 0.5 * eps)
+    res = krylov.gmresr(apply_A, middle, b, 0.5 * eps)
+    if calc:
+        eig.rediagonalise_kept()
+    return res
 
 
 def rediagonalise_sets(sets, n, mu, delta, cut=1e-10):
@@ -321,7 +344,7 @@ def eigsumr_eigensolver(overlap, q0, eig, restarts=10, diag_per_restart=24, rela
     n = eig.n
     eps_final = eig.eps
     q = q0 / norm(q0)
-    kept = []
+    eig.kept = []
     runs = []
     applies = 0
     for _ in range(restarts):
@@ -344,12 +367,7 @@ def eigsumr_eigensolver(overlap, q0, eig, restarts=10, diag_per_restart=24, rela
                 break
         eig.diagonalise()
         eig.recompute(overlap, recompute_eta)
-        cur = ([v.copy() for v in eig.V[:n]], [d.copy() for d in eig.VD[:n]])
-        v, vD, theta = rediagonalise_sets([cur] + kept[::-1], n, eig.mu, eig.delta)
-        eig.V = [v[:, i].reshape(eig.shape) for i in range(n)]
-        eig.VD = [vD[:, i].reshape(eig.shape) for i in range(n)]
-        eig.theta = theta
-        kept = (kept + [(list(eig.V), list(eig.VD))])[-2:]
+        eig.rediagonalise_kept()
         vals, res = eig.ritz()
         runs.append(EigensolverRun(applies, vals, res, eig.ndiag, None))
         if res.max() <= eps_final:

@@ -694,6 +694,8 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
             std::fprintf(stderr, "[ovl] GMRESR step %d: ||r||/||b|| of field 0 = %.3e (sign calls redone one precision up so far: %lld)\n",
                          i + 1, rn[0] / bn[0], (long long)c.precision_retries);
     }
+    // a calculating solve ends a Krylov space: the three-set re-diagonalisation (Sec. 5)
+    if (prm.eig_calc && c.eig.ndiag > 0 && c.eig.k >= c.eig.n) eig_rediagonalise_sets(c);
     OVL_HIP(hipStreamSynchronize(c.stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st)
