@@ -2,7 +2,7 @@
 configurations: empty and oversized batches, the largest accepted batch, the
 reduced-precision K at 16^3 x 32 on sampled sites against the oracle, and
 sign(K)^2 = 1 at 16^3 x 32 in every storage precision (a property that holds
-at any size, Sec. 1)."""
+at any size, Sec. 1), and the eigensolver's argument checks."""
 import numpy as np
 import pytest
 
@@ -96,3 +96,25 @@ def test_sign_squared_16c32(c2, prec, eta, tol):
     err = rel(to_host(s2), to_host(psi))
     print("case", prec, "sign^2 error", err, "mscg iterations", st.mscg_iters, flush=True)
     assert err < tol
+
+
+def test_eigensolver_arguments_rejected():
+    """The standalone eigensolver refuses a zero start vector, more than 170
+    eigenvectors (three sets must fit one 512-vector Rayleigh-Ritz), m <= n
+    and a zero run limit, each with OVL_ERR_ARG and no work done."""
+    ovl = require_gpu()
+    import torch
+    dims = (4, 4, 4, 4)
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(synth.gauge_field(dims, 1, 0.3)))
+    z = ovl.zolotarev_coeffs(8, 0.5, 6.6)
+    q0 = to_dev(synth.z2_source(dims, 1))
+    zero = torch.zeros_like(q0)
+    cases = [(zero, dict(n_eig=4, m_eig=10), 2), (q0, dict(n_eig=171, m_eig=200), 2),
+             (q0, dict(n_eig=8, m_eig=8), 2), (q0, dict(n_eig=4, m_eig=10), 0)]
+    for q, kw, runs in cases:
+        p = ovl.solver_defaults(rho=1.4, mu=0.05, **kw)
+        with pytest.raises(ovl.OvlError) as e:
+            ctx.eigensolve(q, z, p, max_runs=runs)
+        assert e.value.code == -1, (kw, runs)
+    ctx.close()
