@@ -276,7 +276,8 @@ ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *
  * D^+ D + 2 mu delta gamma_5 D), from the start vector q0_dev (canonical
  * complex128 [V][4][3], device, one field, not modified).  Used from params:
  * rho, mu, n_eig (3 n_eig <= 512), m_eig (> n_eig), eig_eps (target residual),
- * delta_split, norm_restart, k_recalc, f32_threshold / half_threshold (the
+ * delta_split, norm_restart, k_recalc (in the Sec. 5.1 bound), relax_floor,
+ * f32_threshold / half_threshold (the
  * precision of each sign call), max_mscg, verbose (one line per run).
  * Runs: each generates the Alg. 1 basis of U = gamma_5 sign(K) from its start
  * vector, collecting every (q, U q); it ends after diag_per_run
@@ -286,8 +287,8 @@ ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *
  * previous two runs (canonically orthonormalised, directions below 1e-10 of
  * the largest Gram eigenvalue dropped).  The next run starts from the last q
  * orthogonalised against the eigenvectors, with the target max(eig_eps, 0.1 x
- * the largest residual).  Sign accuracy per application: the Sec. 5.1 bound
- * when eta_fixed <= 0, else eta_fixed.  The eigenvectors are left in the
+ * the largest residual).  Sign accuracy per application: the Sec. 5.1 bound,
+ * never looser than relax_floor, when eta_fixed <= 0; else eta_fixed.  The eigenvectors are left in the
  * context's eigenspace (ovl_eigspace_info / _get; usable for deflation).
  * Host outputs (each may be null): runs_out; applies_hist[max_runs] and
  * maxres_hist[max_runs], the U applications so far and the largest residual

@@ -334,10 +334,10 @@ class EigensolverRun:
 
 
 def eigsumr_eigensolver(overlap, q0, eig, restarts=10, diag_per_restart=24, relaxed=True, eta_full=1e-12,
-                        recompute_eta=1e-13):
+                        recompute_eta=1e-13, floor=1e-2):
     """The standalone eigSUMR eigensolver (module notes): runs of the Alg. 1
-    basis with Alg. 5 collection at the Sec. 5.1 sign accuracy (relaxed) or
-    at eta_full, each closed by Alg. 6, an accurate v^D and the three-set
+    basis with Alg. 5 collection at the Sec. 5.1 sign accuracy, never looser
+    than floor (relaxed), or at eta_full, each closed by Alg. 6, an accurate v^D and the three-set
     re-diagonalisation; stops when every residual is at most eig.eps as
     given.  Returns one EigensolverRun per restart (U applications so far,
     Ritz values and residuals after it)."""
@@ -351,7 +351,7 @@ def eigsumr_eigensolver(overlap, q0, eig, restarts=10, diag_per_restart=24, rela
         q_t = q.copy()
         nd0 = eig.ndiag
         while eig.ndiag - nd0 < diag_per_restart:
-            u = overlap.U(q, eig.sign_accuracy() if relaxed else eta_full)
+            u = overlap.U(q, min(floor, eig.sign_accuracy()) if relaxed else eta_full)
             applies += 1
             eig.collect(q, u)
             gamma = dot(q_t, u)

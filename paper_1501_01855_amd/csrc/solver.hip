@@ -712,8 +712,8 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
 // diagonalisations, when | ||q|| - 1 | > norm_restart or |gamma| >= 1, or when
 // every held eigenvector's residual is at most the run's target.  Alg. 6
 // closes the run, v^D is recomputed to 1e-12, and the three-set
-// re-diagonalisation follows.  Sign accuracy: the Sec. 5.1 bound (eta_fixed
-// <= 0) or eta_fixed.  The next run starts from the last q, orthogonalised
+// re-diagonalisation follows.  Sign accuracy: the Sec. 5.1 bound, never
+// looser than relax_floor (eta_fixed <= 0), or eta_fixed.  The next run starts from the last q, orthogonalised
 // twice against the eigenvectors and normalised, with the target
 // max(eig_eps, 0.1 x the largest residual).  Stops when every residual is
 // at most eig_eps (OVL_OK) or after max_runs runs (OVL_ERR_NOT_CONVERGED).
@@ -750,7 +750,7 @@ ovl_status eig_eigensolve(Context &c, const ovl_zolo &z, const ovl_solver_params
         copy_fields(c, q, qt, 1, OVL_F64);
         const int nd0 = e.ndiag;
         while (e.ndiag - nd0 < diag_per_run) {
-            double eta = eta_fixed > 0.0 ? eta_fixed : eig_sign_accuracy(c);
+            double eta = eta_fixed > 0.0 ? eta_fixed : std::fmin(prm.relax_floor, eig_sign_accuracy(c));
             unitary_f64(c, prm.rho, z, q, u, 1, &eta, prm, st);
             applies += 1;
             eig_collect(c, q, u);
