@@ -533,7 +533,29 @@ def dslash_alone(torch, ovl, tuning=None, reps=50):
     res["fields12_24c48"] = _stencil_rates(torch, ovl, ctx, B, 20)
     res["tuning"]["24x24x24x48"] = ctx.tuning()
     ctx.close()
+    res["copy_reference"] = copy_reference(torch)
     return res
+
+
+def copy_reference(torch, reps=20):
+    """What a plain device copy reaches on this GPU (context for the stencil's
+    rate): 1 GiB read and 1 GiB written per copy (torch's copy kernel), timed
+    with events around reps back-to-back copies."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    return {"bytes_per_copy": nbytes, "avg_us": 1e3 * ms, "GBps": nbytes / (ms * 1e6),
+            "frac_of_peak": nbytes / (ms * 1e6) / HBM_PEAK_GBS}
 
 
 def cpu_baseline(mscg_iters_per_solve):
