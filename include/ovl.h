@@ -294,7 +294,11 @@ ovl_status ovl_eigspace_recompute(ovl_context *ctx, double rho, const ovl_zolo *
  * maxres_hist[max_runs], the U applications so far and the largest residual
  * after each run; stats (one entry; sumr_iters = U applications).  Returns
  * OVL_OK when every residual reached eig_eps, OVL_ERR_NOT_CONVERGED after
- * max_runs runs, OVL_ERR_BREAKDOWN on a non-finite basis vector. */
+ * max_runs runs, OVL_ERR_BREAKDOWN on a non-finite basis vector or when a run
+ * ends before the first diagonalisation (fewer than n_eig + 1 vectors before
+ * the norm test: lower n_eig).  Collection continues from the vectors the
+ * eigenspace holds when n_eig, m_eig and mu match its configuration, else it
+ * starts from an empty space. */
 ovl_status ovl_eigsumr_eigensolve(ovl_context *ctx, const ovl_zolo *zolo, const ovl_solver_params *params,
                                   const double *q0_dev, int32_t max_runs, int32_t diag_per_run, double eta_fixed,
                                   int32_t *runs_out, int64_t *applies_hist, double *maxres_hist,

@@ -366,6 +366,8 @@ def eigsumr_eigensolver(overlap, q0, eig, restarts=10, diag_per_restart=24, rela
             if eig.theta is not None and eig.ritz()[1].max() <= eig.eps:
                 break
         eig.diagonalise()
+        if eig.theta is None or len(eig.V) < n:
+            raise RuntimeError("eigensolver: a run ended before the first diagonalisation")
         eig.recompute(overlap, recompute_eta)
         eig.rediagonalise_kept()
         vals, res = eig.ritz()

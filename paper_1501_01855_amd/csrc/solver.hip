@@ -716,7 +716,10 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
 // looser than relax_floor (eta_fixed <= 0), or eta_fixed.  The next run starts from the last q, orthogonalised
 // twice against the eigenvectors and normalised, with the target
 // max(eig_eps, 0.1 x the largest residual).  Stops when every residual is
-// at most eig_eps (OVL_OK) or after max_runs runs (OVL_ERR_NOT_CONVERGED).
+// at most eig_eps (OVL_OK) or after max_runs runs (OVL_ERR_NOT_CONVERGED);
+// OVL_ERR_BREAKDOWN if a run ends before any diagonalisation has happened.
+// Collection continues from what the eigenspace holds when its n, m and mu
+// are unchanged (eig_configure), else starts from an empty space.
 ovl_status eig_eigensolve(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, const double2 *q0,
                           int max_runs, int diag_per_run, double eta_fixed, int *runs_out, int64_t *applies_hist,
                           double *maxres_hist, ovl_stats *st)
@@ -771,6 +774,9 @@ ovl_status eig_eigensolve(Context &c, const ovl_zolo &z, const ovl_solver_params
             if (!e.resid.empty() && *std::max_element(e.resid.begin(), e.resid.end()) <= e.eps) break;
         }
         eig_diagonalise(c);
+        OVL_REQUIRE(e.ndiag > 0 && e.k >= n, OVL_ERR_BREAKDOWN,
+                    "eigensolver: a run ended before the first diagonalisation (fewer than n_eig + 1 basis "
+                    "vectors before the norm test); lower n_eig");
         eig_recompute(c, prm.rho, z, 1e-12, st);
         eig_rediagonalise_sets(c);
         runs = run + 1;

@@ -118,3 +118,19 @@ def test_eigensolver_arguments_rejected():
             ctx.eigensolve(q, z, p, max_runs=runs)
         assert e.value.code == -1, (kw, runs)
     ctx.close()
+
+
+def test_eigensolver_run_too_short_for_n():
+    """A run that ends at the norm test before n_eig + 1 vectors are held (no
+    diagonalisation yet) is reported as OVL_ERR_BREAKDOWN, not continued: on
+    4^4 the Alg. 1 basis loses its normalisation well before 151 steps."""
+    ovl = require_gpu()
+    dims = (4, 4, 4, 4)
+    ctx = ovl.Context(dims)
+    ctx.gauge_load(to_dev(synth.gauge_field(dims, 1, 0.3)))
+    z = ovl.zolotarev_coeffs(8, 0.5, 6.6)
+    p = ovl.solver_defaults(rho=1.4, mu=0.05, n_eig=150, m_eig=200, f32_threshold=10.0, half_threshold=10.0)
+    with pytest.raises(ovl.OvlError) as e:
+        ctx.eigensolve(to_dev(synth.z2_source(dims, 1)), z, p, max_runs=2, eta_fixed=1e-6)
+    assert e.value.code == -5
+    ctx.close()
