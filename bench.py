@@ -622,7 +622,7 @@ def cpu_baseline(mscg_iters_per_solve):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (no multi-GPU path); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1501_01855_amd as ovl

@@ -54,7 +54,7 @@ typedef enum {
     OVL_ERR_NOMEM = -3,         /* device allocation failed                    */
     OVL_ERR_NOT_CONVERGED = -4, /* iteration limit reached; best iterate written */
     OVL_ERR_BREAKDOWN = -5,     /* NaN / Inf or a breakdown of a recurrence    */
-    OVL_ERR_UNSUPPORTED = -6,   /* valid request this build does not provide   */
+    OVL_ERR_UNSUPPORTED = -6,   /* valid request the library does not provide  */
     OVL_ERR_STATE = -7          /* missing set-up (no gauge field loaded, ...) */
 } ovl_status;
 
