@@ -133,6 +133,32 @@ def test_eigensolver_16c32_pairs_and_deflation(c2):
     assert code == 0 and res <= 1e-10
 
 
+def test_eigcg_16c32_solve_and_pairs(c2):
+    """One calculating GMRESR(eigCG) solve at the benchmark's full size
+    (n = 8, m = 30, mixed precision): the solution reaches 1e-10 against the
+    FP64 operator, and every held pair has a unit v and v^D within 1e-3 of
+    D v (FP64 operator at 1e-12): v^D comes from the CG's own relaxed H
+    products, held to the Sec. 5.1 bound."""
+    import torch
+    ovl, ctx, z = c2["ovl"], c2["ctx"], c2["z"]
+    p = ovl.solver_defaults(rho=1.4, mu=0.02, tol=1e-10, eta_tilde=1e-3, middle_cg=1, eig_calc=1, use_deflation=1,
+                            n_eig=8, m_eig=30, f32_threshold=1e-6, half_threshold=3e-3)
+    ctx.eigspace_set(8, 30, 0.02)   # start from an empty eigenspace
+    b = ctx.source(ovl.SRC_POINT, site=0, spin=0, colour=0)
+    x, st, code = ctx.solve(b, z, p)
+    Dx, _ = ctx.overlap(x, 1.4, 0.02, z, 1e-13)
+    res = float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b))
+    info = ctx.eigspace_info()
+    print("case eigCG 16^3x32: CG iterations", st[0].sumr_iters, "diagonalisations", info["ndiag"],
+          "true residual", res, flush=True)
+    assert code == 0 and res <= 1e-10 and info["held"] == 8 and info["ndiag"] >= 1
+    v, vd = ctx.eigspace_get()
+    Dv, _ = ctx.overlap(v, 1.4, 0.02, z, 1e-12)
+    for i in range(8):
+        assert abs(float(torch.linalg.vector_norm(v[i])) - 1.0) < 1e-10
+        assert float(torch.linalg.vector_norm(Dv[i] - vd[i])) < 1e-3
+
+
 def test_eigensolver_arguments_rejected():
     """The standalone eigensolver refuses a zero start vector, more than 170
     eigenvectors (three sets must fit one 512-vector Rayleigh-Ritz), m <= n
