@@ -94,7 +94,6 @@ struct Context {
     int64_t precision_retries = 0;   // sign calls redone one precision up after a breakdown
     std::vector<int64_t> last_field_iters;   // per field, last sign call
 
-    unsigned *grid_counters = nullptr;   // zero between launches (reset by the last block)
 
     // stencil launch variant per (precision, epilogue, nf), chosen by timing
     std::map<int, int> tuned;
@@ -114,7 +113,6 @@ struct Context {
     std::map<std::string, hipGraphExec_t> graphs;
 
     void *buf(const std::string &name, size_t bytes);
-    void *counters();
     void *host_stage(size_t bytes);
     // small results that kernels write straight into host memory (pinned,
     // mapped, coherent): host address, and the device address of the same

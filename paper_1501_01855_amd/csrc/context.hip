@@ -36,16 +36,6 @@ void *Context::buf(const std::string &name, size_t bytes)
     return b.p;
 }
 
-void *Context::counters()
-{
-    if (!grid_counters) {
-        OVL_HIP(hipMalloc(&grid_counters, 64 * sizeof(unsigned)));
-        OVL_HIP(hipMemsetAsync(grid_counters, 0, 64 * sizeof(unsigned), stream));
-        OVL_HIP(hipStreamSynchronize(stream));
-    }
-    return grid_counters;
-}
-
 double *Context::host_results(size_t n, double **dev)
 {
     if (hres_n < n) {
@@ -199,7 +189,6 @@ Context::~Context()
     for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
     if (pinned) hipHostFree(pinned);
     if (hres) hipHostFree(hres);
-    if (grid_counters) hipFree(grid_counters);
 }
 
 }  // namespace ovl

@@ -83,13 +83,198 @@ def test_eigsumr_ritz_pairs_are_eigenpairs(tiny):
     assert norm(b.reshape(-1) - tiny["D"] @ res.x.reshape(-1)) <= 1e-10 * norm(b)
 
 
-def test_sign_accuracy_bound_shape():
-    """Eq. (bound): chi = 1 for the first two diagonalisations, sqrt(n) after;
-    the bound shrinks as (m - n) k grows."""
-    E = eig.EigSUMR(4, 12, MU, eps=1e-4, krecalc=25)
-    e0 = E.sign_accuracy()
-    assert e0 == pytest.approx(2 * 1e-4 / (np.sqrt(8 * 25) * (1 - MU)))
-    E2 = eig.EigSUMR(4, 44, MU, eps=1e-4, krecalc=25)
-    assert E2.sign_accuracy() < e0
-    E.ndiag = 2
-    assert E.sign_accuracy() == pytest.approx(2 * e0)
+# --- eq. (bound) of Sec. 5.1 as a sign accuracy -------------------------------
+
+
+def _held_state(tiny, E, ts, ndiag, uv_hist):
+    """Put n held pairs (v_i, D v_i) into E, each v_i an exact eigenvector of
+    gamma_5 D mixed with a second one by t_i, so that its residual is known
+    only through the dense operator; returns the true residuals."""
+    h, Y, D, G5 = tiny["h"], tiny["Y"], tiny["D"], tiny["G5"]
+    order = np.argsort(np.abs(h))
+    vs, vds, res = [], [], []
+    for i, t in enumerate(ts):
+        v = (Y[:, order[i]] + t * Y[:, order[10 + i]]) / np.sqrt(1.0 + t * t)
+        hv = G5 @ (D @ v)
+        res.append(np.linalg.norm(hv - v * np.vdot(v, hv).real))
+        vs.append(v.reshape(tiny["shape"]))
+        vds.append((D @ v).reshape(tiny["shape"]))
+    E.V, E.VD, E.shape = vs, vds, tiny["shape"]
+    E.theta = np.zeros(len(ts))
+    E.ndiag = ndiag
+    E.uv_hist = list(uv_hist)
+    return np.array(res)
+
+
+def _target(eps, r0):
+    """Eq. (targetdelta): the largest v^D error that keeps the residual gap below eps^2."""
+    return np.sqrt(eps * eps + r0 * r0) - r0
+
+
+def _unrelaxed_limit_ok(tiny, accuracy):
+    """With one new vector per cycle, k = 1 and rotation entries of modulus one
+    nothing in eq. (bound) is relaxed, so for the first two diagonalisations it
+    is eq. (targetdelta) at the residual of the best converged eigenvector, and
+    the sign accuracy is 2 ||delta^D|| / (1 - mu) (v^D = ((1+mu) v + (1-mu) U v)/2).
+    The relaxation factors scale it by 1/sqrt((m - n) k) and by the inverse
+    mean of max|UV| over the recent diagonalisations."""
+    eps, n = 1e-3, 4
+    ok = True
+    E = eig.EigSUMR(n, n + 1, MU, eps=eps, krecalc=1)
+    ok &= accuracy(E) == pytest.approx(2 * eps / (1 - MU), rel=1e-12)      # nothing held: r0 = 0
+    for ndiag in (1, 2):
+        E = eig.EigSUMR(n, n + 1, MU, eps=eps, krecalc=1)
+        res = _held_state(tiny, E, [0.2, 0.05, 0.1, 0.3], ndiag - 1, [1.0])
+        ok &= accuracy(E) == pytest.approx(2 * _target(eps, res.min()) / (1 - MU), rel=1e-10)
+        E = eig.EigSUMR(n, n + 4, MU, eps=eps, krecalc=9)
+        res = _held_state(tiny, E, [0.2, 0.05, 0.1, 0.3], ndiag - 1, [0.5, 2.0])
+        ok &= accuracy(E) == pytest.approx(2 * _target(eps, res.min()) / (1 - MU) / 6.0 / 1.25, rel=1e-10)
+    return bool(ok)
+
+
+def test_sign_accuracy_unrelaxed_limit_is_targetdelta(tiny):
+    assert _unrelaxed_limit_ok(tiny, lambda E: E.sign_accuracy())
+
+
+def _planted(chi_always=False, worst_residual=False, no_gamma5=False):
+    def acc(E):
+        if len(E.V) < E.n or E.theta is None:
+            r0 = 0.0
+        else:
+            rs = []
+            for v, vD in zip(E.V[:E.n], E.VD[:E.n]):
+                g = vD if no_gamma5 else g5(vD)
+                rs.append(norm(g - np.vdot(v.reshape(-1), g.reshape(-1)).real * v))
+            r0 = max(rs) if worst_residual else min(rs)
+        chi = np.sqrt(E.n) if (chi_always or E.ndiag >= 2) else 1.0
+        uv = np.mean(E.uv_hist) if E.uv_hist else 1.0
+        dd = chi * _target(E.eps, r0) / (np.sqrt((E.m - E.n) * E.krecalc) * uv)
+        return 2.0 * dd / (1.0 - E.mu)
+    return acc
+
+
+@pytest.mark.parametrize("mistake", ["chi_always", "worst_residual", "no_gamma5"])
+def test_sign_accuracy_limit_rejects_planted(tiny, mistake):
+    """The limit check fails for sqrt(n) applied from the start, for the worst
+    instead of the best converged residual, and for a residual without gamma_5."""
+    assert not _unrelaxed_limit_ok(tiny, _planted(**{mistake: True}))
+
+
+def _rotation_blocks(tiny, E, solves=2, block=None):
+    """Run calculating solves; at every diagonalisation measure the rotation
+    C (new eigenvectors = old basis x C) by least squares and return pairs
+    (recorded max|UV|, measured max over new eigenvectors i < n and new Krylov
+    vectors j >= n')."""
+    out = []
+    orig = E.diagonalise
+
+    def diag():
+        if len(E.V) <= E.n:
+            return orig()
+        nprev = E.n if E.ndiag > 0 else 0
+        B = eig._mat(E.V)
+        nd = E.ndiag
+        orig()
+        if E.ndiag > nd:
+            C = np.linalg.lstsq(B, eig._mat(E.V[:E.n]), rcond=None)[0]
+            out.append((E.uv_hist[-1], np.abs(C[nprev:, :]).max()))
+    E.diagonalise = diag
+    for s in range(solves):
+        eig.gmresr_eigsumr(tiny["ov"], synth.z2_source(tiny["dims"], 60 + s), 1e-10, 1e-3, E, calc=True)
+    return out
+
+
+def test_uv_block_is_new_krylov_vectors(tiny):
+    """max|UV| of eq. (bound) is taken over the rotation entries that carry the
+    new Krylov vectors (j >= n') into the new eigenvectors (i < n)."""
+    pairs = _rotation_blocks(tiny, eig.EigSUMR(6, 24, MU))
+    assert len(pairs) >= 3
+    for rec, meas in pairs:
+        assert rec == pytest.approx(meas, rel=1e-6)
+
+
+class _OldBlock(eig.EigSUMR):
+    """Planted mistake: max|UV| over the held (old) rows instead of the new ones."""
+    def diagonalise(self):
+        if len(self.V) <= self.n:
+            return
+        nprev = self.n if self.ndiag > 0 else 0
+        v, vD, theta, C = eig.rayleigh_ritz(eig._mat(self.V), eig._mat(self.VD), self.n, self.mu, self.delta)
+        self.V = [v[:, i].reshape(self.shape) for i in range(self.n)]
+        self.VD = [vD[:, i].reshape(self.shape) for i in range(self.n)]
+        self.theta = theta
+        self.ndiag += 1
+        self.uv_hist = (self.uv_hist + [float(np.abs(C[: max(nprev, 1), :]).max())])[-10:]
+
+
+def test_uv_block_rejects_planted(tiny):
+    pairs = _rotation_blocks(tiny, _OldBlock(6, 24, MU))
+    assert any(abs(rec - meas) > 1e-3 * meas for rec, meas in pairs)
+
+
+class _Injected:
+    """D[mu] whose sign function errs by exactly eta ||psi|| in a random
+    direction: the worst error a sign call at accuracy eta may make."""
+    def __init__(self, tiny, seed):
+        self.mu, self.t = MU, tiny
+        self.S = tiny["G5"] @ (2.0 * tiny["D"] - (1 + MU) * np.eye(tiny["D"].shape[0])) / (1 - MU)
+        self.rng = np.random.default_rng(seed)
+
+    def U(self, psi, eta):
+        e = self.rng.normal(size=psi.size) + 1j * self.rng.normal(size=psi.size)
+        e *= eta * norm(psi) / np.linalg.norm(e)
+        return g5((self.S @ psi.reshape(-1) + e).reshape(psi.shape))
+
+    def __call__(self, psi, eta):
+        return 0.5 * (1 + self.mu) * psi + 0.5 * (1 - self.mu) * self.U(psi, eta)
+
+
+def _new_vector_error(tiny, E, seed=7, solves=2):
+    """For the first two diagonalisations: sqrt(k) times the largest error the
+    new Krylov vectors of the cycle carry into a held v^D, over the target of
+    eq. (targetdelta) at the residual the bound used (k cycles of such errors
+    adding up as a random walk, the relaxation argument of Sec. 5.1)."""
+    D = tiny["D"]
+    ratios = []
+    orig = E.diagonalise
+
+    def diag():
+        if len(E.V) <= E.n:
+            return orig()
+        r0 = 0.0 if (E.theta is None or len(E.V) < E.n) else float(E.ritz()[1].min())
+        nprev = E.n if E.ndiag > 0 else 0
+        B, BD = eig._mat(E.V), eig._mat(E.VD)
+        err = BD - D @ B
+        nd = E.ndiag
+        orig()
+        if E.ndiag > nd and E.ndiag <= 2:
+            C = np.linalg.lstsq(B, eig._mat(E.V[:E.n]), rcond=None)[0]
+            new = err[:, nprev:] @ C[nprev:, :]
+            ratios.append(np.sqrt(E.krecalc) * np.linalg.norm(new, axis=0).max() / _target(E.eps, r0))
+    E.diagonalise = diag
+    ov = _Injected(tiny, seed)
+    for s in range(solves):
+        eig.gmresr_eigsumr(ov, synth.z2_source(tiny["dims"], 40 + s), 1e-10, 1e-3, E, calc=True)
+    return ratios
+
+
+@pytest.mark.parametrize("cfg", [dict(n=6, m=24, krecalc=25), dict(n=6, m=24, krecalc=4),
+                                 dict(n=4, m=16, krecalc=25)])
+def test_bound_keeps_new_vector_errors_within_targetdelta(tiny, cfg):
+    """With every sign call erring by as much as its accuracy allows, the
+    error that a cycle's new vectors bring into the eigenvectors stays within
+    eq. (targetdelta) over the first two diagonalisations (chi = 1)."""
+    ratios = _new_vector_error(tiny, eig.EigSUMR(cfg["n"], cfg["m"], MU, eps=1e-4, krecalc=cfg["krecalc"]))
+    assert len(ratios) == 2
+    assert max(ratios) < 0.7
+
+
+class _NoRelaxDivisor(eig.EigSUMR):
+    """Planted mistake: the sqrt((m - n) k) divisor left out."""
+    def sign_accuracy(self):
+        return eig.EigSUMR.sign_accuracy(self) * np.sqrt((self.m - self.n) * self.krecalc)
+
+
+def test_new_vector_errors_reject_planted(tiny):
+    ratios = _new_vector_error(tiny, _NoRelaxDivisor(6, 24, MU, eps=1e-4, krecalc=25))
+    assert max(ratios) > 1.0

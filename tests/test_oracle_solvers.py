@@ -155,3 +155,63 @@ def test_gmresr_vs_dense_solve(mid):
         assert true <= 1e-10
         assert norm(res.x.reshape(-1) - xd) / norm(xd) <= 2e-10 / mu
         assert 1 <= res.steps <= 10
+
+
+# --- the sign accuracy -> multi-shift stopping rule (Sec. 3, eq. 7 and the
+# text after it: the sign error is the larger of Delta and the inversion
+# error of x^2 + sigma_l) --------------------------------------------------------
+
+SHIFT_ETAS = (1e-2, 1e-4, 1e-6)
+
+
+def _per_shift_worst(d, z, psi, eta, tol):
+    """max_l  omega_l ||K (x_l - x_l*)|| N_Z / (eta ||psi||), x_l* from the dense
+    eigendecomposition: the share of each pole in the inversion error of
+    eps(K) psi = K sum_l omega_l x_l, in units of its budget eta ||psi|| / N_Z."""
+    res = krylov.multishift_cg(d.k.K2s, z.sigma, psi, tol)
+    pv = d.Q.conj().T @ psi.reshape(-1)
+    worst = 0.0
+    for l in range(z.nz):
+        xs = (d.Q @ (pv / (d.w * d.w + z.sigma[l]))).reshape(psi.shape)
+        e = z.omega[l] * norm(d.k.K(res.x[l] - xs))
+        worst = max(worst, e * z.nz / (eta * norm(psi)))
+    return worst
+
+
+@pytest.mark.parametrize("fixture", ["small", "mid"])
+@pytest.mark.parametrize("nz", [12, 20])
+def test_sign_accuracy_bounds_inversion_error(fixture, nz, request):
+    """A sign call at accuracy eta keeps the error of the rational function
+    within eta ||psi|| (against the dense Q eps(Lambda) Q^dagger psi), and each
+    pole's share within eta ||psi|| / N_Z, for eta from the relaxed 1e-2 down
+    to 1e-6, on 2^4 and 4x4x2x2."""
+    d = request.getfixturevalue(fixture)
+    z = Zolotarev(nz, np.abs(d.w).min(), np.abs(d.w).max())
+    psi = synth.gaussian_source(d.dims, 4)
+    exact = d.fn(z, psi)
+    for eta in SHIFT_ETAS:
+        out = krylov.SignFunction(d.k, z)(psi, eta)
+        assert norm(out - exact) <= eta * norm(psi)
+        assert _per_shift_worst(d, z, psi, eta, krylov.shift_tolerances(z, eta)) <= 1.0
+
+
+PLANTED_SHIFT_RULES = {
+    "budget not split over the poles": lambda z, eta: eta * 2.0 * np.sqrt(z.sigma) / z.omega,
+    "sigma for sqrt(sigma)": lambda z, eta: eta * 2.0 * z.sigma / (z.nz * z.omega),
+    "four times looser": lambda z, eta: eta * 8.0 * np.sqrt(z.sigma) / (z.nz * z.omega),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PLANTED_SHIFT_RULES))
+def test_sign_accuracy_pin_rejects_planted_rules(name, small, mid):
+    """The per-pole budget check above fails for plausible mistakes in the
+    stopping rule, on at least one lattice and accuracy."""
+    rule = PLANTED_SHIFT_RULES[name]
+    worst = 0.0
+    for d in (small, mid):
+        for nz in (12, 20):
+            z = Zolotarev(nz, np.abs(d.w).min(), np.abs(d.w).max())
+            psi = synth.gaussian_source(d.dims, 4)
+            for eta in SHIFT_ETAS:
+                worst = max(worst, _per_shift_worst(d, z, psi, eta, rule(z, eta)))
+    assert worst > 1.2, f"planted rule '{name}' not detected ({worst:.2f})"
