@@ -358,6 +358,29 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
 ovl_status ovl_tuning_get(ovl_context *ctx, int32_t *keys, int32_t *variants, int32_t cap, int32_t *n);
 ovl_status ovl_tuning_set(ovl_context *ctx, const int32_t *keys, const int32_t *variants, int32_t n);
 
+/* ---- allocation-free variant --------------------------------------------- */
+
+/* Bytes of the library's fixed device scratch array: one per GPU, held from
+ * the first ovl_create on that GPU until the process ends. */
+#define OVL_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * operation as ovl_wilson_dslash (out = H in, nrhs canonical fields, device
+ * in/out owned by the caller), with no hipMalloc, hipFree or other allocating
+ * call.  The packed copies of in and out (and, for OVL_F32 / OVL_HALF, an FP64
+ * staging field) live in the fixed scratch array, so
+ *   2 * round256(S_prec * V * nrhs) + (prec != OVL_F64 ? round256(192 * V * nrhs) : 0)
+ * must not exceed OVL_NOALLOC_SCRATCH_BYTES (S_prec = 192, 96, 52 bytes per
+ * site for OVL_F64, OVL_F32, OVL_HALF), else OVL_ERR_ARG and no work.  The
+ * context must hold a gauge field (ovl_gauge_load / _generate, which do
+ * allocate, at set-up).  A stencil launch shape not yet timed by the context
+ * is not timed here: the fixed shape is used (same values).  The array is
+ * shared by every call on the GPU and keeps the last call's contents; calls
+ * that overlap in time on one GPU race.  Asynchronous on the context's stream. */
+ovl_status ovl_wilson_dslash_noalloc(ovl_context *ctx, const double *in_dev, double *out_dev, int32_t nrhs,
+                                     int32_t prec);
+
 #ifdef __cplusplus
 }
 #endif

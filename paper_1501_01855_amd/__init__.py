@@ -79,7 +79,7 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
            "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option",
-           "ovl_sumr_gmresr_solve_many", "ovl_eigsumr_eigensolve"]
+           "ovl_sumr_gmresr_solve_many", "ovl_eigsumr_eigensolve", "ovl_wilson_dslash_noalloc"]
 
 _lib = None
 
@@ -103,6 +103,7 @@ def lib():
         "ovl_gauge_generate": ([P, ctypes.c_uint64, D, P], I32),
         "ovl_source_generate": ([P, I32, ctypes.c_uint64, I64, I32, I32, P], I32),
         "ovl_wilson_dslash": ([P, P, P, I32, I32], I32),
+        "ovl_wilson_dslash_noalloc": ([P, P, P, I32, I32], I32),
         "ovl_kernel_K_apply": ([P, D, P, P, I32, I32], I32),
         "ovl_zolotarev_coeffs": ([I32, D, D, P], I32),
         "ovl_lowmodes_compute": ([P, D, I32, D, P, P], I32),
@@ -230,6 +231,13 @@ class Context:
         _check(lib().ovl_wilson_dslash(self._h, _dev(psi, (self.V, 4, 3), "psi"),
                                        _dev(out, (self.V, 4, 3), "out"), self._nrhs(psi), prec))
         return out
+
+    def wilson_dslash_noalloc(self, psi, out, prec=F64):
+        """H psi into the caller's out, with no device allocation by the library
+        (packed copies in its fixed scratch array); returns the status."""
+        return _check(lib().ovl_wilson_dslash_noalloc(self._h, _dev(psi, (self.V, 4, 3), "psi"),
+                                                      _dev(out, (self.V, 4, 3), "out"), self._nrhs(psi), prec),
+                      allow=(-1,))
 
     def kernel_K_apply(self, psi, rho, prec=F64):
         out = torch.empty_like(psi)

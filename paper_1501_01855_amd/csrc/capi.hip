@@ -110,6 +110,7 @@ ovl_status ovl_create(const int32_t dims[4], void *hip_stream, ovl_context **out
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
             c->num_cu = ncu;
+        noalloc_scratch_init(c->device);   // once per device, with it current
         *out = c;
     });
 }
@@ -171,6 +172,36 @@ ovl_status ovl_wilson_dslash(ovl_context *ctx, const double *in_dev, double *out
         launch_hop(*ctx, a, b, nrhs, prec);
         unpack_spinor(*ctx, b, out_dev, nrhs, prec);
         ctx->prof_collect();
+    });
+}
+
+ovl_status ovl_wilson_dslash_noalloc(ovl_context *ctx, const double *in_dev, double *out_dev, int32_t nrhs,
+                                     int32_t prec)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        check_prec(prec, true);
+        OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t FB = up(field_bytes(ctx->g, prec) * nrhs);
+        const size_t TB = prec == OVL_F64 ? 0 : up(field_bytes(ctx->g, OVL_F64) * nrhs);
+        OVL_REQUIRE(2 * FB + TB <= (size_t)OVL_NOALLOC_SCRATCH_BYTES, OVL_ERR_ARG,
+                    "fields too large for the fixed scratch: " + std::to_string(2 * FB + TB) + " bytes needed, " +
+                        std::to_string((size_t)OVL_NOALLOC_SCRATCH_BYTES) + " available");
+        unsigned char *base = (unsigned char *)noalloc_scratch(ctx->device);
+        void *a = base;
+        void *b = base + FB;
+        double2 *tmp = TB ? (double2 *)(base + 2 * FB) : nullptr;
+        struct Scope {
+            Context &c;
+            bool prev;
+            explicit Scope(Context &cc) : c(cc), prev(cc.no_alloc) { c.no_alloc = true; }
+            ~Scope() { c.no_alloc = prev; }
+        } scope(*ctx);
+        pack_spinor(*ctx, in_dev, a, nrhs, prec, tmp);
+        launch_hop(*ctx, a, b, nrhs, prec);
+        unpack_spinor(*ctx, b, out_dev, nrhs, prec, tmp);
     });
 }
 

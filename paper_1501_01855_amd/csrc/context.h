@@ -98,6 +98,10 @@ struct Context {
     // stencil launch variant per (precision, epilogue, nf), chosen by timing
     std::map<int, int> tuned;
     int autotune = 1;
+    // set while an allocation-free entry point runs: no autotuning (a launch
+    // shape not yet tuned takes the fixed variant without recording it), no
+    // profiling events, no workspace growth
+    bool no_alloc = false;
 
     // sign calls inside the solvers take as few Zolotarev poles as their
     // accuracy allows (coefficients per pole count for the interval zolo_ab)
@@ -144,10 +148,18 @@ inline unsigned site_blocks(const Geom &g, int nt = 256) { return (unsigned)((g.
 
 // ---- entry points implemented in the .hip files (host side) -------------
 // pack / unpack between canonical complex128 [nf][V][12] and packed fields.
-void pack_spinor(Context &c, const double *canon, void *packed, int nf, int prec);
-void unpack_spinor(Context &c, const void *packed, double *canon, int nf, int prec);
+// FP32 / FP16 packing goes through an FP64 staging field: tmp (nf FP64 fields)
+// if given, else the context's workspace.
+void pack_spinor(Context &c, const double *canon, void *packed, int nf, int prec, double2 *tmp = nullptr);
+void unpack_spinor(Context &c, const void *packed, double *canon, int nf, int prec, double2 *tmp = nullptr);
 void convert_spinor(Context &c, const void *src, int sprec, void *dst, int dprec, int nf);
 void pack_gauge(Context &c, const double *canon);
+
+// The library's fixed device scratch array (noalloc.hip): its address on the
+// current device, looked up once per device at context creation.  Callers
+// that may not allocate work in it.
+void noalloc_scratch_init(int device);
+void *noalloc_scratch(int device);
 
 // stencil: out = H in / K in; nf fields in packed layout of precision prec
 void launch_hop(Context &c, const void *in, void *out, int nf, int prec);

@@ -128,36 +128,34 @@ __global__ void k_h8_to_f64(const h8 *__restrict__ in, double2 *__restrict__ out
     st_sp(out + (int64_t)f * 12 * V, V, s, w);
 }
 
-void pack_spinor(Context &c, const double *canon, void *packed, int nf, int prec)
+void pack_spinor(Context &c, const double *canon, void *packed, int nf, int prec, double2 *tmp)
 {
     const Geom &g = c.g;
     dim3 grid(site_blocks(g), nf);
+    if (prec != OVL_F64 && tmp == nullptr) tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
     if (prec == OVL_F64) {
         k_pack_f64<<<grid, 256, 0, c.stream>>>((const double2 *)canon, (double2 *)packed, g.V);
     } else if (prec == OVL_F32) {
-        double2 *tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
         k_pack_f64<<<grid, 256, 0, c.stream>>>((const double2 *)canon, tmp, g.V);
         k_f64_to_f32<<<grid, 256, 0, c.stream>>>(tmp, (float4 *)packed, g.V);
     } else {
-        double2 *tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
         k_pack_f64<<<grid, 256, 0, c.stream>>>((const double2 *)canon, tmp, g.V);
         k_f64_to_h8<<<grid, 256, 0, c.stream>>>(tmp, (h8 *)packed, g.V);
     }
     OVL_HIP(hipGetLastError());
 }
 
-void unpack_spinor(Context &c, const void *packed, double *canon, int nf, int prec)
+void unpack_spinor(Context &c, const void *packed, double *canon, int nf, int prec, double2 *tmp)
 {
     const Geom &g = c.g;
     dim3 grid(site_blocks(g), nf);
+    if (prec != OVL_F64 && tmp == nullptr) tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
     if (prec == OVL_F64) {
         k_unpack_f64<<<grid, 256, 0, c.stream>>>((const double2 *)packed, (double2 *)canon, g.V);
     } else if (prec == OVL_F32) {
-        double2 *tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
         k_f32_to_f64<<<grid, 256, 0, c.stream>>>((const float4 *)packed, tmp, g.V);
         k_unpack_f64<<<grid, 256, 0, c.stream>>>(tmp, (double2 *)canon, g.V);
     } else {
-        double2 *tmp = (double2 *)c.buf("pack_tmp", field_bytes(g, OVL_F64) * nf);
         k_h8_to_f64<<<grid, 256, 0, c.stream>>>((const h8 *)packed, tmp, g.V);
         k_unpack_f64<<<grid, 256, 0, c.stream>>>(tmp, (double2 *)canon, g.V);
     }
@@ -962,6 +960,7 @@ static int tuned_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int 
     const int key = (prec * 8 + EPI) * 64 + (nf < 63 ? nf : 63);
     auto it = c.tuned.find(key);
     if (it != c.tuned.end()) return it->second;
+    if (c.no_alloc) return 1;   // timing would need workspace and events: fixed shape, not recorded
     if (c.autotune == 0) return c.tuned[key] = 1;
     // time every variant on scratch output
     StencilArgs<ST> t = a;
@@ -1003,7 +1002,7 @@ static void launch_stencil_t(Context &c, const StencilArgs<ST> &a, const GT *U, 
     // nf fields in one launch share one read of the links
     const double G = stencil_link_bytes(c.g, prec);
     const double bytes = a.stop ? 0.0 : (stencil_bytes(c.g, prec, EPI) - G) * nf + G;
-    const bool prof = profile && c.prof;
+    const bool prof = profile && c.prof && !c.no_alloc;
     if (prof) c.prof_begin(pe, KERN_STENCIL, prec, bytes);
     launch_by_id<ST, GT, EPI>(c, v, a, U, nf, prof ? &pe : nullptr);
     OVL_HIP(hipGetLastError());
