@@ -1,28 +1,28 @@
 """Benchmark: overlap solves per second at a 1e-10 residual on one MI355X.
 
-Workload (one "step" = one complete GMRESR(relSUMR) solve of D[mu] x = b):
-16^3 x 32 lattice, links exp(i 0.25 A) (seed 2), K = gamma_5 D_W(-1.4),
-mu = 0.02, order-20 Zolotarev sign function with the 10 lowest kernel modes
-treated exactly, one complex Gaussian source (seed 102), target
-||b - D x|| <= 1e-10 ||b||, middle-solve accuracy eta~ = 3e-3.  Set-up (gauge field, low modes, coefficients)
-is outside the timed region.  The headline value is the mixed-precision
-solver (FP16-storage sign function while the accuracy asked for is >= 3e-3,
-FP32 while >= 1e-6, FP64 below); the same solve with an all-FP64 sign function
-is timed beside it.
-
-Beside the headline (not part of it):
-* the same solver on twelve spin-colour point sources in one batched call;
-* twenty-four independent lattice instances of four sizes solved together
-  (one context and stream each) and one after another;
-* the adjoint (dS/dpsi and dS/dU of S = Re(chi^H D psi)) on 8^3 x 16 in FP64
-  and on 32^3 x 64 in FP32;
-* the Wilson stencil alone on 32^3 x 64 (working set beyond the 256 MB
-  Infinity Cache) for its HBM bandwidth;
-* the CPU oracle on a bounded sample of the headline workload.
+Headline workload (one "step" = one complete mixed-precision, eigSUMR-deflated
+GMRESR(relSUMR) solve of D[mu] x = b for one spin-colour point source):
+24^3 x 48 lattice, links exp(i 0.25 A) (seed 3), K = gamma_5 D_W(-1.4),
+mu = 0.01, order-20 Zolotarev sign function on the Lanczos interval of |K|
+(no kernel modes need exact treatment there: the spectrum of |K| starts at
+0.62), eigSUMR deflation with 20 eigenvectors (Secs. 4-5), target
+||b - D x|| <= 1e-10 ||b||.  The steps cycle through the twelve spin-colour
+point sources at the origin.  Set-up (gauge field, interval, Zolotarev
+coefficients, the eigSUMR calculating solves that build the eigenspace and
+its FP64 recomputation) is outside the timed region and reported separately,
+with the rate including it and the number of sources at which it pays.
+Precision ladder: FP16-storage sign function while the accuracy asked for is
+>= 3e-3, FP32 while >= 1e-6, FP64 below; FP64 outer GMRESR, Gram/Rayleigh-Ritz
+and projection.  Beside it (not timed steps): the same sources solved
+undeflated and with an all-FP64 sign function (medians of three), the
+deflation gain in SUMR iterations and time, the eigenvalue ratio of the
+deflated space, the 16^3 x 32 plain method (mixed and FP64), the stencil alone
+beyond the Infinity Cache, the library's streaming kernels, and the CPU oracle
+on a bounded sample of the headline workload.
 
 The timed steps run with profiling off.  Kernel times come from HIP events
 attached to each launch's dispatch packet (see ovl_profile_enable), collected
-over one replica of the timed solve run right after it.
+over one replica of a timed solve run right after them.
 
 Prints one JSON line.
 """
@@ -45,7 +45,6 @@ RHO, MU, NZ, NLOW, TOL = 1.4, 0.02, 20, 10, 1e-10
 ETA_TILDE_C2 = 3e-3
 PREC_NAMES = ("f64", "f32", "f16")
 KERN_NAMES = ("stencil", "shift_update")
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "traffic_overlap_solve_16c32.txt")
 # sources whose kernels the hardware-counter traffic figures describe
 KERNEL_SOURCES = ["dslash.hip", "mscg.hip", "fields.h", "kernels.h", "mscg_state.h"]
 
@@ -53,26 +52,31 @@ KERNEL_SOURCES = ["dslash.hip", "mscg.hip", "fields.h", "kernels.h", "mscg_state
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="only the headline solve (no batch, adjoint or stand-alone stencil legs)")
-    ap.add_argument("--half-threshold", type=float, default=3e-3,
-                    help="sign accuracies at or above this use FP16 storage (> 1 disables)")
-    ap.add_argument("--profile-run", action="store_true",
-                    help="short run for hardware counters: a 1 GiB elementwise copy (calibration), "
-                         "one sign-function call per precision on the 16^3x32 workload, the "
-                         "stand-alone 32^3x64 stencil and the 12-field 24^3x48 stencil")
-    ap.add_argument("--eig", action="store_true",
-                    help="add the eigSUMR leg on 24^3x48 (12 point sources, calculating solves then a "
-                         "deflated batch; several minutes)")
-    ap.add_argument("--eig-calc", type=int, default=3, help="eigSUMR leg: calculating solves")
-    ap.add_argument("--eig-n", type=int, default=20, help="eigSUMR leg: eigenvectors kept (n)")
-    ap.add_argument("--eig-m", type=int, default=60, help="eigSUMR leg: basis size of Alg. 6 (m)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison solves on 24^3x48")
     ap.add_argument("--headline-only", action="store_true",
-                    help="only the headline mixed and FP64 solves (no adaptive-pole or relCG solves, no extras): "
-                         "for kernel traces whose averages cover exactly the benchmark's solves")
+                    help="only the 24^3x48 headline and its comparison solves (for kernel traces)")
+    ap.add_argument("--extras", action="store_true",
+                    help="add the 24 uneven instances, the 4^4 plain method and the adjoint legs")
+    ap.add_argument("--batch12", action="store_true",
+                    help="add the twelve 24^3x48 point sources deflated in one batched call")
+    ap.add_argument("--half-threshold", type=float, default=3e-3,
+                    help="16^3x32 leg: sign accuracies at or above this use FP16 storage (> 1 disables)")
+    ap.add_argument("--c3-eta", type=float, default=1e-3, help="24^3x48: middle-solve accuracy eta~ of GMRESR")
+    ap.add_argument("--eig-calc", type=int, default=3, help="24^3x48: eigSUMR calculating solves")
+    ap.add_argument("--eig-n", type=int, default=20, help="24^3x48: eigenvectors kept (n)")
+    ap.add_argument("--eig-m", type=int, default=60, help="24^3x48: basis size of Alg. 6 (m)")
+    ap.add_argument("--eig-eps", type=float, default=1e-4, help="24^3x48: target eigenvector accuracy (Sec. 6)")
+    ap.add_argument("--adaptive-nz", action="store_true",
+                    help="24^3x48: Zolotarev order per sign call from its accuracy (Sec. 3)")
+    ap.add_argument("--bound-printed", action="store_true",
+                    help="24^3x48: eq. (bound) with chi on the square root only (as printed)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for hardware counters: a 1 GiB elementwise copy (calibration), one "
+                         "sign-function call per precision on the 24^3x48 workload, the stand-alone 32^3x64 "
+                         "stencil and the 12-field 24^3x48 stencil")
     ap.add_argument("--eigcg", action="store_true",
                     help="add the GMRESR(eigCG) leg on 16^3x32 (calculating solves, then deflated solves)")
     ap.add_argument("--eigcg-calc", type=int, default=5, help="eigCG leg: calculating solves")
@@ -103,7 +107,7 @@ def setup_c2(ovl, tuning=None):
     return ctx, zolo, b
 
 
-def profile_run(torch, ovl, tuning):
+def profile_run(torch, ovl, tuning, args):
     """Hardware-counter run (rocprofv3 --pmc): every kernel here is a kernel
     the benchmark times, launched in the same configuration (tuning: the
     benchmark's launch choices, installed before any launch)."""
@@ -114,32 +118,26 @@ def profile_run(torch, ovl, tuning):
     torch.mul(src, 1.0, out=dst)   # reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
     del src, dst
-    ctx, zolo, b = setup_c2(ovl, tuning)
+    ctx, zolo, B, _ = c3_setup(torch, ovl, tuning)
     out = {"calibration_bytes_each_way": 1 << 30}
     for prec in (ovl.HALF, ovl.F32, ovl.F64):
-        _, st = ctx.sign(b, RHO, zolo, 1e-2, prec=prec)
+        _, st = ctx.sign(B[0], RHO, zolo, 1e-2, prec=prec)
         out[f"mscg_iters_{PREC_NAMES[prec]}"] = st.mscg_iters
+    torch.cuda.synchronize()
+    Bs = torch.stack(B)
+    for prec in (ovl.F32, ovl.HALF):   # the 12-field stencil of the batched form
+        for _ in range(10):
+            ctx.wilson_dslash(Bs, prec)
     torch.cuda.synchronize()
     ctx.close()
     ctx = ovl.Context((32, 32, 32, 64))
     ctx.gauge_generate(5, 0.25)
-    if tuning:
+    if tuning and "32x32x32x64" in tuning:
         ctx.set_tuning(tuning["32x32x32x64"])
     psi = ctx.source(ovl.SRC_GAUSS, seed=7)
     for prec in (ovl.F32, ovl.HALF):
         for _ in range(10):
             ctx.wilson_dslash(psi, prec)
-    torch.cuda.synchronize()
-    ctx.close()
-    # the 12-field stencil of the eigSUMR workload (24^3 x 48, links seed 3)
-    ctx = ovl.Context((24, 24, 24, 48))
-    ctx.gauge_generate(3, 0.25)
-    if tuning and "24x24x24x48" in tuning:
-        ctx.set_tuning(tuning["24x24x24x48"])
-    B = torch.stack([ctx.source(ovl.SRC_GAUSS, seed=300 + f) for f in range(12)])
-    for prec in (ovl.F32, ovl.HALF):
-        for _ in range(10):
-            ctx.wilson_dslash(B, prec)
     torch.cuda.synchronize()
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -199,11 +197,11 @@ def kernel_summary(prof):
     return out
 
 
-def read_traffic(name):
+def read_traffic(name, path):
     """HBM bytes per launch of kernel slot `name` from the committed
     hardware-counter summary, if it was taken on the current kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None, "no counter summary"
@@ -218,31 +216,14 @@ def read_traffic(name):
     return None, "slot not in the counter summary"
 
 
-def batch12(torch, ovl, ctx, zolo):
-    """Twelve spin-colour point sources at site 0 in one batched solve."""
-    B = torch.stack([ctx.source(ovl.SRC_POINT, site=0, spin=s, colour=c) for s in range(4) for c in range(3)])
-    p = solve_params(ovl, True, 3e-3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x, st, code = ctx.solve(B, zolo, p)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    Dx, _ = ctx.overlap(x, RHO, MU, zolo, 1e-13)
-    res = [float(torch.linalg.vector_norm(B[f] - Dx[f]) / torch.linalg.vector_norm(B[f])) for f in range(12)]
-    return {"sources": "12 spin-colour point sources at site 0, one call", "status": code,
-            "seconds": dt, "solves_per_s": 12 / dt, "max_true_relres": max(res),
-            "mscg_iters_per_field": [s.mscg_iters for s in st],
-            "sumr_iters_per_field": [s.sumr_iters for s in st]}
-
-
 def uneven_leg(torch, ovl):
     """Twenty-four independent instances, six each of 8^4, 8^3x16, 12^3x24 and
     16^4 (links exp(i eps A), eps uniform in [0.2, 0.35] from seed 4, gauge seed
     400 + i), Z2 sources (seed 104 + i), mu = 0.03, N_Z = 20 with 10 exact kernel
     modes, mixed precision, 1e-10: solved together (one context and stream
     each) and, for comparison, one after another."""
-    import numpy as np
-    eps = np.random.default_rng(4).uniform(0.2, 0.35, 24)
+    import synth
+    eps = synth.instance_eps(24, 4)
     sizes = [(8, 8, 8, 8), (8, 8, 8, 16), (12, 12, 12, 24), (16, 16, 16, 16)]
     t0 = time.perf_counter()
     items = []
@@ -279,89 +260,6 @@ def uneven_leg(torch, ovl):
             "one_after_another_s": alone, "solves_per_s_one_after_another": 24 / alone,
             "speedup": alone / together, "max_true_relres": worst,
             "status": [r[2] for r in res]}
-
-
-def eig_leg(torch, ovl, n_calc=3, n_eig=20, m_eig=60):
-    """eigSUMR on 24^3 x 48 (links eps 0.25, seed 3; rho 1.4, mu 0.01, N_Z 20
-    with 10 exact kernel modes; by default n_eig 20, m 60): n_calc calculating solves
-    (Alg. 5 collection, Alg. 6 Rayleigh-Ritz) on the first spin-colour point
-    sources at site 0, the eigenspace's D psi' recomputed in FP64, then all 12
-    sources in one deflated batched solve; for comparison one undeflated mixed
-    solve and one deflated FP64 solve of the first source, and the 12-field
-    stencil's algorithmic GB/s."""
-    dims, mu = (24, 24, 24, 48), 0.01
-    ctx = ovl.Context(dims)
-    t0 = time.perf_counter()
-    ctx.gauge_generate(3, 0.25)
-    ev, lmax = ctx.lowmodes_compute(RHO, NLOW, tol=1e-10)
-    zolo = ovl.zolotarev_coeffs(NZ, max(abs(e) for e in ev), lmax)
-    B = torch.stack([ctx.source(ovl.SRC_POINT, site=0, spin=s, colour=c) for s in range(4) for c in range(3)])
-    torch.cuda.synchronize()
-    setup_lowmodes = time.perf_counter() - t0
-
-    def params(mixed, calc, defl):
-        return ovl.solver_defaults(rho=RHO, mu=mu, tol=TOL, eta_tilde=1e-3, relax_floor=1e-2,
-                                   f32_threshold=(1e-6 if mixed else 10.0),
-                                   half_threshold=(3e-3 if mixed else 10.0), max_outer=16, max_middle=6000,
-                                   max_mscg=20000, use_deflation=defl, eig_calc=calc, n_eig=n_eig, m_eig=m_eig,
-                                   verbose=1)   # one line per GMRESR step (progress of long solves)
-
-    out = {"lattice": "24x24x24x48", "mu": mu, "n_eig": n_eig, "m_eig": m_eig, "calculating_solves_n": n_calc,
-           "setup_lowmodes_s": setup_lowmodes}
-    calc = []
-    t0 = time.perf_counter()
-    for i in range(n_calc):
-        t1 = time.perf_counter()
-        _, st, code = ctx.solve(B[i:i + 1], zolo, params(True, 1, 1))
-        torch.cuda.synchronize()
-        calc.append({"seconds": time.perf_counter() - t1, "status": code, **st[0].as_dict()})
-        print(f"[bench] eigSUMR calculating solve {i} done", file=sys.stderr, flush=True)
-    ctx.eigspace_recompute(RHO, zolo, 1e-12)
-    torch.cuda.synchronize()
-    out["calculating_solves"] = calc
-    out["eig_setup_s"] = time.perf_counter() - t0
-    info = ctx.eigspace_info()
-    out["eigenspace"] = {"held": info["held"], "diagonalisations": info["ndiag"], "ritz": info["ritz"],
-                         "max_ritz_residual": max(info["resid"]) if info["resid"] else None}
-    t0 = time.perf_counter()
-    X, st, code = ctx.solve(B, zolo, params(True, 0, 1))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    print("[bench] eigSUMR deflated batch done", file=sys.stderr, flush=True)
-    DX, _ = ctx.overlap(X, RHO, mu, zolo, 1e-13)
-    res = [float(torch.linalg.vector_norm(B[f] - DX[f]) / torch.linalg.vector_norm(B[f])) for f in range(12)]
-    del DX
-    out["deflated_batch12"] = {"status": code, "seconds": dt, "solves_per_s": 12 / dt,
-                               "max_true_relres": max(res),
-                               "sumr_iters_per_field": [s.sumr_iters for s in st],
-                               "mscg_iters_per_field": [s.mscg_iters for s in st]}
-    out["solves_per_s_including_eig_setup"] = (12 + 0) / (dt + out["eig_setup_s"])
-    t0 = time.perf_counter()
-    _, st, code = ctx.solve(B[0:1], zolo, params(True, 0, 0))
-    torch.cuda.synchronize()
-    out["undeflated_mixed_single"] = {"status": code, "seconds": time.perf_counter() - t0, **st[0].as_dict()}
-    t0 = time.perf_counter()
-    _, st, code = ctx.solve(B[0:1], zolo, params(False, 0, 1))
-    torch.cuda.synchronize()
-    out["deflated_fp64_single"] = {"status": code, "seconds": time.perf_counter() - t0, **st[0].as_dict()}
-    print("[bench] eigSUMR comparison solves done", file=sys.stderr, flush=True)
-    sten = {}
-    for prec in (ovl.HALF, ovl.F32):
-        ctx.wilson_dslash(B, prec)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        for _ in range(10):
-            ctx.wilson_dslash(B, prec)
-        torch.cuda.synchronize()
-        pr = ctx.profile_read(ovl.KERN_STENCIL, prec)
-        ctx.profile(False)
-        sten[PREC_NAMES[prec]] = {"avg_us": 1e3 * pr["ms"] / pr["launches"],
-                                  "bytes_per_launch": pr["bytes"] / pr["launches"],
-                                  "GBps": pr["bytes"] / (pr["ms"] * 1e6)}
-    out["stencil_12rhs"] = sten
-    out["tuning"] = ctx.tuning()
-    ctx.close()
-    return out
 
 
 def eigcg_leg(torch, ovl, n_calc=5, n_eig=20, m_eig=60):
@@ -619,6 +517,226 @@ def cpu_baseline(mscg_iters_per_solve):
                       f"shifts stay active in a real solve)"}
 
 
+C3_DIMS, C3_MU, C3_EPS, C3_SEED = (24, 24, 24, 48), 0.01, 0.25, 3
+C3_NAME = "24x24x24x48"
+TRAFFIC_C3 = os.path.join(HERE, "profiles", "traffic_overlap_solve_24c48.txt")
+
+
+def c3_setup(torch, ovl, tuning=None):
+    """The 24^3 x 48 workload: links, the Zolotarev interval from Lanczos on
+    K^2 (a = 0.95 x its smallest Ritz value, b = 8 - rho, a rigorous bound),
+    the coefficients and the twelve spin-colour point sources at the origin."""
+    ctx = ovl.Context(C3_DIMS)
+    if tuning and C3_NAME in tuning:
+        ctx.set_tuning(tuning[C3_NAME])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.gauge_generate(C3_SEED, C3_EPS)
+    lo, err, hi = ctx.kernel_interval(RHO)
+    a, b = 0.95 * lo, 8.0 - RHO
+    zolo = ovl.zolotarev_coeffs(NZ, a, b)
+    B = [ctx.source(ovl.SRC_POINT, site=0, spin=s, colour=c) for s in range(4) for c in range(3)]
+    torch.cuda.synchronize()
+    info = {"seconds": time.perf_counter() - t0, "interval": [a, b], "lanczos_lmin": lo, "lanczos_lmin_err": err,
+            "lanczos_lmax": hi, "zolotarev_delta": zolo.delta, "n_z": NZ}
+    return ctx, zolo, B, info
+
+
+def c3_params(ovl, args, mixed=True, calc=0, defl=1):
+    return ovl.solver_defaults(rho=RHO, mu=C3_MU, tol=TOL, eta_tilde=args.c3_eta, relax_floor=1e-2,
+                               f32_threshold=(1e-6 if mixed else 10.0), half_threshold=(3e-3 if mixed else 10.0),
+                               max_outer=16, max_middle=6000, max_mscg=20000, use_deflation=defl, eig_calc=calc,
+                               n_eig=args.eig_n, m_eig=args.eig_m, eig_eps=args.eig_eps)
+
+
+def timed_solve(torch, ctx, b, zolo, p):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st, code = ctx.solve(b, zolo, p)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, st[0].as_dict(), code, x
+
+
+def true_relres(torch, ctx, b, x, mu, zolo):
+    """||b - D x|| / ||b|| with the FP64 operator at sign accuracy 1e-13 (not timed)."""
+    Dx, _ = ctx.overlap(x, RHO, mu, zolo, 1e-13)
+    return float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b))
+
+
+def median(xs):
+    ys = sorted(xs)
+    return ys[len(ys) // 2] if len(ys) % 2 else 0.5 * (ys[len(ys) // 2 - 1] + ys[len(ys) // 2])
+
+
+def c3_headline(torch, ovl, args, tuning):
+    """Set-up, eigSUMR calculating solves, the timed deflated solves, the
+    profiled replica and the comparison solves on 24^3 x 48."""
+    ctx, zolo, B, setup = c3_setup(torch, ovl, tuning)
+    ctx.set_option(ovl.OPT_ADAPTIVE_NZ, 1 if args.adaptive_nz else 0)
+    ctx.set_option(ovl.OPT_BOUND_PRINTED, 1 if args.bound_printed else 0)
+    n_calc = args.eig_calc
+    # eigSUMR calculating solves (Alg. 5 collection at the stricter of the
+    # inversion and Sec. 5.1 accuracies, Alg. 6, the three-set step at the end
+    # of each) on the first sources, then v^D recomputed in FP64
+    ctx.eigspace_set(args.eig_n, args.eig_m, C3_MU)
+    calc = []
+    for i in range(n_calc):
+        dt, st, code, _ = timed_solve(torch, ctx, B[i], zolo, c3_params(ovl, args, True, 1, 1))
+        calc.append({"seconds": dt, "status": code, **st})
+        print(f"[bench] C3 calculating solve {i}: {dt:.1f} s, {st['sumr_iters']} SUMR iterations",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.eigspace_recompute(RHO, zolo, 1e-12)
+    torch.cuda.synchronize()
+    t_recompute = time.perf_counter() - t0
+    info = ctx.eigspace_info()
+    ritz = info["ritz"]
+    absr = sorted(abs(h) for h in ritz)
+    # timed deflated solves: step i solves source (n_calc + i) mod 12
+    src = lambda i: B[(n_calc + i) % 12]
+    pd = c3_params(ovl, args, True, 0, 1)
+    for w in range(args.warmup):
+        timed_solve(torch, ctx, src(w), zolo, pd)
+    ctx.profile(False)
+    steps, x = [], None
+    for k in range(args.steps):
+        dt, st, code, x = timed_solve(torch, ctx, src(args.warmup + k), zolo, pd)
+        steps.append({"seconds": dt, "status": code, **st})
+    t_total = sum(s["seconds"] for s in steps)
+    last = src(args.warmup + args.steps - 1)
+    res_last = true_relres(torch, ctx, last, x, C3_MU, zolo)
+    print(f"[bench] C3 deflated mixed: {args.steps} solves in {t_total:.2f} s", file=sys.stderr, flush=True)
+    # profiled replica of one timed solve (events on every stencil and shift-update launch)
+    ctx.profile(True)
+    dtp, stp, _, _ = timed_solve(torch, ctx, src(args.warmup + args.steps), zolo, pd)
+    prof = read_prof(ctx, ovl)
+    ctx.profile(False)
+    # comparisons on the first three timed sources: undeflated mixed, deflated FP64
+    cmp_src = [src(args.warmup + k) for k in range(3)]
+    defl_t = [s["seconds"] for s in steps[:3]] if len(steps) >= 3 else [s["seconds"] for s in steps]
+    defl_it = [s["sumr_iters"] for s in steps[:3]]
+    und = [timed_solve(torch, ctx, b, zolo, c3_params(ovl, args, True, 0, 0)) for b in cmp_src]
+    print("[bench] C3 undeflated mixed comparison done", file=sys.stderr, flush=True)
+    f64 = [] if args.no_fp64 else [timed_solve(torch, ctx, b, zolo, c3_params(ovl, args, False, 0, 1))
+                                   for b in cmp_src]
+    print("[bench] C3 FP64 comparison done", file=sys.stderr, flush=True)
+    res_f64 = true_relres(torch, ctx, cmp_src[-1], f64[-1][3], C3_MU, zolo) if f64 else None
+    res_und = true_relres(torch, ctx, cmp_src[-1], und[-1][3], C3_MU, zolo)
+    t_und, t_def = median([u[0] for u in und]), median(defl_t)
+    it_und, it_def = median([u[1]["sumr_iters"] for u in und]), median(defl_it)
+    t_calc = sum(c["seconds"] for c in calc)
+    extra = t_calc + t_recompute - n_calc * t_und   # the calculating solves solved n_calc sources too
+    gain = t_und - t_def
+    out = {
+        "setup": setup,
+        "eigsumr": {"n_eig": args.eig_n, "m_eig": args.eig_m, "eig_eps": args.eig_eps, "calculating_solves": calc,
+                    "calculating_seconds": t_calc, "recompute_fp64_seconds": t_recompute,
+                    "diagonalisations": info["ndiag"], "ritz": ritz, "residuals": info["resid"],
+                    "bound": "printed (chi on the square root)" if args.bound_printed else "chi scales the bound"},
+        "steps": steps, "seconds_timed": t_total, "true_relres_last_step": res_last,
+        "profiled_replica_seconds": dtp, "profiled_replica_stats": stp,
+        "undeflated_mixed": {"median_seconds": t_und, "solves_per_s": 1.0 / t_und, "median_sumr_iters": it_und,
+                             "runs": [{"seconds": u[0], "status": u[2], **u[1]} for u in und],
+                             "true_relres_last": res_und},
+        "deflated_fp64": ({"median_seconds": median([f[0] for f in f64]), "solves_per_s": 1.0 / median([f[0] for f in f64]),
+                           "runs": [{"seconds": f[0], "status": f[2], **f[1]} for f in f64],
+                           "true_relres_last": res_f64} if f64 else None),
+        "deflation": {"sumr_iteration_gain": it_und / it_def if it_def else None,
+                      "time_gain": t_und / t_def if t_def else None,
+                      "eigenvalue_ratio": absr[-1] / absr[0] if absr and absr[0] > 0 else None,
+                      "abs_ritz_min_max": [absr[0], absr[-1]] if absr else None,
+                      "setup_beyond_plain_solves_s": extra,
+                      "break_even_sources": (extra / gain) if gain > 0 else None,
+                      "solves_per_s_including_setup_12_sources":
+                          12.0 / (setup["seconds"] + t_calc + t_recompute + (12 - n_calc) * t_def)},
+        "tuning": ctx.tuning(),
+    }
+    if args.batch12:
+        # the twelve sources deflated in one batched call (right-hand sides
+        # grouped by the precision their sign calls need)
+        Bs = torch.stack(B)
+        dt, _, code, X = timed_solve(torch, ctx, Bs, zolo, pd)
+        res = [true_relres(torch, ctx, Bs[f], X[f], C3_MU, zolo) for f in range(12)]
+        out["batch12_deflated"] = {"status": code, "seconds": dt, "solves_per_s": 12 / dt,
+                                   "single_solves_per_s": 1.0 / t_def, "max_true_relres": max(res)}
+        print("[bench] C3 batch of 12 done", file=sys.stderr, flush=True)
+    return ctx, zolo, out, prof
+
+
+def c2_secondary(torch, ovl, args, tuning):
+    """The 16^3 x 32 plain method (the paper's inverter without deflation):
+    mixed ladder (steps 3, warm-up 1) and all-FP64 (median of three)."""
+    ctx, zolo, b = setup_c2(ovl, tuning)
+    dt_mix, st_mix, prof_mix, x_mix, _ = time_solves(torch, ctx, ovl, b, zolo,
+                                                    solve_params(ovl, True, args.half_threshold), 3, 1)
+    f64 = [timed_solve(torch, ctx, b, zolo, solve_params(ovl, False)) for _ in range(3)]
+    t64 = median([f[0] for f in f64])
+    ks = kernel_summary(prof_mix)
+    dom = max(ks, key=lambda k: ks[k]["ms"])
+    out = {"workload": "overlap solve 16^3x32, rho=1.4, mu=0.02, N_Z=20, 10 exact kernel modes, Gaussian "
+                       "source, GMRESR(relSUMR) to 1e-10 (middle solves to 3e-3)",
+           "mixed_solves_per_s": 3 / dt_mix, "fp64_solves_per_s": 1.0 / t64, "mixed_over_fp64": (3 / dt_mix) * t64,
+           "true_relres": {"mixed": true_relres(torch, ctx, b, x_mix, MU, zolo),
+                           "fp64": true_relres(torch, ctx, b, f64[-1][3], MU, zolo)},
+           "solve_stats": {"mixed": st_mix[-1], "fp64": f64[-1][1]},
+           "kernels_mixed": ks,
+           "dominant_kernel": {"kernel": dom, "achieved_GBps": ks[dom]["GBps"], "avg_us": ks[dom]["avg_us"],
+                               "bound": "mall",
+                               "note": "16^3x32: fields and links fit in the 256 MB Infinity Cache"},
+           "tuning": ctx.tuning()}
+    ctx.close()
+    return out
+
+
+def stream_ceiling(torch, ovl):
+    """The library's own streaming kernels on 1 GiB buffers: copy (1 GiB
+    read + 1 GiB written per launch) and read-only."""
+    ctx = ovl.Context((4, 4, 4, 4))
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms_c = ctx.stream_bench(0, src, dst, 20)
+    ms_r = ctx.stream_bench(1, src, dst, 20)
+    nb = src.numel() * 8
+    del src, dst
+    ctx.close()
+    return {"copy": {"bytes_per_launch": 2 * nb, "avg_us": 1e3 * ms_c, "GBps": 2 * nb / (ms_c * 1e6),
+                     "frac_of_peak": 2 * nb / (ms_c * 1e6) / HBM_PEAK_GBS},
+            "read": {"bytes_per_launch": nb, "avg_us": 1e3 * ms_r, "GBps": nb / (ms_r * 1e6),
+                     "frac_of_peak": nb / (ms_r * 1e6) / HBM_PEAK_GBS}}
+
+
+def cpu_baseline_c3(mscg_iters_per_solve, samples=3, iters=6):
+    """The oracle (FP64, C stencil and vector updates, numpy) on a bounded
+    sample of the headline workload: `iters` multi-shift CG iterations with
+    all 20 shifts active on the 24^3 x 48 field, three times (the median),
+    scaled by the multi-shift iteration count of the GPU's FP64 deflated solve
+    of the same workload (an upper bound on the oracle's rate: fewer shifts
+    stay active in a real solve)."""
+    import numpy as np
+    import synth
+    from oracle import krylov
+    from oracle.lattice import WilsonKernel
+    from oracle.zolotarev import Zolotarev
+    U = synth.gauge_field(C3_DIMS, C3_SEED, C3_EPS)
+    k = WilsonKernel(C3_DIMS, U, RHO)
+    z = Zolotarev(NZ, 0.588, 8.0 - RHO)
+    b = synth.point_source(C3_DIMS)
+    per = []
+    for _ in range(samples):
+        t0 = time.perf_counter()
+        krylov.multishift_cg(k.K2s, z.sigma, b, np.full(NZ, 1e-300), maxiter=iters)
+        per.append((time.perf_counter() - t0) / iters)
+    per_iter = median(per)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / (per_iter * mscg_iters_per_solve), "unit": "solves/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{iters} multi-shift CG iterations (20 shifts active) of the oracle on the 24^3x48 "
+                      f"field, median of {samples} runs: {per_iter:.3f} s per iteration, scaled by the "
+                      f"{mscg_iters_per_solve} multi-shift iterations of the GPU's FP64 deflated solve "
+                      f"(an upper bound on the oracle's rate: fewer shifts stay active in a real solve)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -629,110 +747,73 @@ def main():
 
     tuning = json.loads(args.tuning) if args.tuning else None
     if args.profile_run:
-        profile_run(torch, ovl, tuning)
+        profile_run(torch, ovl, tuning, args)
         return
-    ctx, zolo, b = setup_c2(ovl, tuning)
-    dt_mix, st_mix, prof_mix, x_mix, dtp_mix = time_solves(torch, ctx, ovl, b, zolo,
-                                                           solve_params(ovl, True, args.half_threshold),
-                                                           args.steps, args.warmup)
-    print(f"[bench] mixed: {args.steps} solves in {dt_mix:.2f} s", file=sys.stderr, flush=True)
-    dt_64, st_64, prof_64, x_64, dtp_64 = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, False), 1, 0)
-    print(f"[bench] fp64: 1 solve in {dt_64:.2f} s", file=sys.stderr, flush=True)
-
-    def true_res(x):   # FP64 operator at full accuracy (not timed)
-        Dx, _ = ctx.overlap(x, RHO, MU, zolo, 1e-13)
-        return float(torch.linalg.vector_norm(b - Dx) / torch.linalg.vector_norm(b))
-    res_mix, res_64 = true_res(x_mix), true_res(x_64)
-
-    ks = kernel_summary(prof_mix)
+    ctx, zolo, c3, prof = c3_headline(torch, ovl, args, tuning)
+    ks = kernel_summary(prof)
     dom = max(ks, key=lambda k: ks[k]["ms"])
     d = ks[dom]
-    traffic, traffic_note = read_traffic(dom)
+    traffic, traffic_note = read_traffic(dom, TRAFFIC_C3)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": d["bytes_per_launch"], "avg_us": d["avg_us"],
                 "traffic_note": traffic_note,
-                "working_set": "16^3x32: fields and links fit in the 256 MB Infinity Cache"}
+                "working_set": "24^3x48: the multi-shift CG's fields (25 x 34.5 MB in FP16 storage) and links "
+                               "exceed the 256 MB Infinity Cache"}
+    t_total = c3.pop("seconds_timed")
+    f64 = c3.get("deflated_fp64")
+    value = args.steps / t_total
     out = {
         "metric": METRIC,
-        "value": args.steps / dt_mix,
+        "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt_mix / args.steps,
+        "ms_per_step": 1e3 * t_total / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f16-storage/f32/f64",
         "data": "synthetic",
-        "config": {"workload": "overlap solve 16^3x32, rho=1.4, mu=0.02, N_Z=20, 10 exact kernel modes, "
-                               "Gaussian source, GMRESR(relSUMR) to 1e-10 (middle solves to 3e-3)",
-                   "global_batch": 1, "lattice": "16x16x16x32", "parallelism": "single GPU"},
-        "fp64_solves_per_s": 1.0 / dt_64,
-        "mixed_over_fp64": (args.steps / dt_mix) * dt_64,
-        "true_relres": {"mixed": res_mix, "fp64": res_64},
-        "solve_stats": {"mixed": st_mix[-1], "fp64": st_64[-1]},
+        "config": {"workload": "overlap solve 24^3x48 (links exp(i 0.25 A), seed 3), rho=1.4, mu=0.01, N_Z=20 on "
+                               "the Lanczos interval of |K|, eigSUMR deflation with 20 eigenvectors, one spin-colour "
+                               "point source per step (cycling over the 12), mixed precision, GMRESR(relSUMR) to "
+                               "1e-10",
+                   "global_batch": 1, "lattice": C3_NAME, "parallelism": "single GPU"},
+        "fp64_solves_per_s": f64["solves_per_s"] if f64 else None,
+        "mixed_over_fp64": (value / f64["solves_per_s"]) if f64 else None,
         "kernels_mixed": ks,
-        "kernels_fp64": kernel_summary(prof_64),
-        "kernel_timing": "HIP events on each launch's dispatch packet, in one profiled replica of the "
-                         "timed solve (same kernels, launch shapes and iteration counts); wall time of "
-                         f"the profiled replica: mixed {dtp_mix:.3f} s, fp64 {dtp_64:.3f} s",
+        "kernel_timing": "HIP events on each launch's dispatch packet, in one profiled replica of a timed "
+                         "solve (same kernels and launch shapes)",
         "roofline": roofline,
+        "c3": c3,
     }
-    out["tuning"] = {"16x16x16x32": ctx.tuning()}
+    out["tuning"] = {C3_NAME: c3.pop("tuning")}
+    ctx.close()
     if args.headline_only:
-        ctx.close()
         print(json.dumps(out), flush=True)
         return
-    # the same workload with the number of Zolotarev poles per sign call
-    # chosen from its accuracy (not the headline: the headline keeps N_Z = 20)
-    ctx.set_option(ovl.OPT_ADAPTIVE_NZ, 1)
-    dt_ad, st_ad, _, x_ad, _ = time_solves(torch, ctx, ovl, b, zolo, solve_params(ovl, True, args.half_threshold),
-                                           args.steps, 1)
-    ctx.set_option(ovl.OPT_ADAPTIVE_NZ, 0)
-    out["adaptive_poles"] = {"solves_per_s": args.steps / dt_ad, "ms_per_solve": 1e3 * dt_ad / args.steps,
-                             "true_relres": true_res(x_ad), "solve_stats": st_ad[-1],
-                             "rule": "each sign call inside the solver uses the fewest poles n <= 20 with "
-                                     "Delta(n) <= eta / 4 and gives the multi-shift CG eta - Delta(n)"}
-    print(f"[bench] adaptive poles: {args.steps} solves in {dt_ad:.2f} s", file=sys.stderr, flush=True)
-    # the paper's other middle solver on the same workload: GMRESR(relCG), no deflation
-    pcg = solve_params(ovl, True, args.half_threshold)
-    pcg.middle_cg = 1
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x_cg, st_cg, code_cg = ctx.solve(b, zolo, pcg)
-    torch.cuda.synchronize()
-    dt_cg = time.perf_counter() - t0
-    out["relcg"] = {"status": code_cg, "solves_per_s": 1.0 / dt_cg, "ms_per_solve": 1e3 * dt_cg,
-                    "true_relres": true_res(x_cg), "solve_stats": st_cg[0].as_dict(),
-                    "note": "GMRESR(relCG): CGNE on H^2 (two sign calls per iteration), Sec. 3 CG relaxation"}
-    print(f"[bench] relCG: 1 solve in {dt_cg:.2f} s", file=sys.stderr, flush=True)
-    if not args.no_extras:
-        out["batch12"] = batch12(torch, ovl, ctx, zolo)
-        print("[bench] batch of 12 done", file=sys.stderr, flush=True)
-    ctx.close()
-    if not args.no_extras:
+    out["c2_16c32"] = c2_secondary(torch, ovl, args, tuning)
+    out["tuning"]["16x16x16x32"] = out["c2_16c32"].pop("tuning")
+    print("[bench] 16^3x32 plain method done", file=sys.stderr, flush=True)
+    out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
+    out["tuning"].update(out["dslash_hbm"].pop("tuning"))
+    out["dslash_hbm"]["stream_ceiling"] = stream_ceiling(torch, ovl)
+    print("[bench] stand-alone stencil and streaming ceiling done", file=sys.stderr, flush=True)
+    if args.extras:
         out["uneven_instances"] = uneven_leg(torch, ovl)
         print("[bench] uneven instances done", file=sys.stderr, flush=True)
         out["c1_plain_4c4"] = c1_leg(torch, ovl)
-        print("[bench] 4^4 plain-method solves done", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_leg(torch, ovl)
-        print("[bench] adjoint done", file=sys.stderr, flush=True)
-        out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
-        out["tuning"].update(out["dslash_hbm"].pop("tuning"))
-        print("[bench] stand-alone stencil done", file=sys.stderr, flush=True)
+        print("[bench] 4^4 and adjoint legs done", file=sys.stderr, flush=True)
     if args.eigcg:
         out["eigcg_16c32"] = eigcg_leg(torch, ovl, args.eigcg_calc)
-        print("[bench] eigCG leg done", file=sys.stderr, flush=True)
     if args.eigsolve:
         out["eigsolve_16c32"] = eigsolve_leg(torch, ovl)
-        print("[bench] eigensolver leg done", file=sys.stderr, flush=True)
-    if args.eig:
-        out["eigsumr_24c48"] = eig_leg(torch, ovl, args.eig_calc, args.eig_n, args.eig_m)
-        print("[bench] eigSUMR leg done", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(st_64[-1]["mscg_iters"])
+        it = f64["runs"][len(f64["runs"]) // 2]["mscg_iters"] if f64 else c3["undeflated_mixed"]["runs"][0]["mscg_iters"]
+        out["cpu_baseline"] = cpu_baseline_c3(it)
     print(json.dumps(out), flush=True)
 
 

@@ -184,6 +184,19 @@ ovl_status ovl_zolotarev_coeffs(int32_t n_z, double a, double b, ovl_zolo *out_h
  * ||K v - lambda v|| <= tol. */
 ovl_status ovl_lowmodes_compute(ovl_context *ctx, double rho, int32_t n_low, double tol,
                                 double *evals_host, double *lmax_host);
+/* Spectral interval of K for the Zolotarev approximation when no kernel
+ * modes are treated exactly (Sec. 3: a^2 and b^2 are the smallest and largest
+ * eigenvalues of K^2): Lanczos on K^2 in FP64 from a fixed Gaussian start,
+ * at most max_iter steps (2 .. 2000), stopping once the smallest Ritz value
+ * has moved by less than 1e-10 (relative) over two checks ten steps apart.
+ * lmin_host: square root of the smallest Ritz value of K^2, which lies above
+ * min |lambda|^2 (Ritz values of a Hermitian matrix lie inside its spectrum),
+ * so callers take a margin below it; lmin_err_host (may be null): the Lanczos
+ * residual bound |beta_k y_k| of that Ritz value of K^2 (some eigenvalue of
+ * K^2 is within it); lmax_host (may be null): square root of the largest Ritz
+ * value (a lower estimate of max |lambda|; 8 - rho bounds it from above). */
+ovl_status ovl_kernel_interval(ovl_context *ctx, double rho, int32_t max_iter, double *lmin_host,
+                               double *lmin_err_host, double *lmax_host);
 /* Install caller-provided low modes instead (n vectors, canonical, device;
  * orthonormal).  n = 0 removes them. */
 ovl_status ovl_lowmodes_set(ovl_context *ctx, int32_t n, const double *evals_host,
@@ -235,12 +248,15 @@ ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo,
 
 /* Several independent solves at once: lattice instances of any sizes, each
  * with its own context (and so its own stream, gauge field, low modes and
- * workspace).  One host thread drives each instance, so the GPU runs the
+ * workspace).  A pool of at most 32 host threads takes the instances in
+ * index order, one solve per thread at a time, so the GPU runs up to 32
  * instances' kernels side by side (small lattices alone cannot fill it).
  * Contexts must be distinct, and their streams should be distinct for the
  * work to overlap.  params apply to every instance.  inst[i].status receives
- * each solve's status; the return value is the first failure in index order
- * (OVL_OK if none).  Blocks until every solve has finished. */
+ * each solve's status and inst[i].message its error text (empty on success);
+ * the return value is the first failure in index order (OVL_OK if none), and
+ * ovl_last_error() then names that instance.  Blocks until every solve has
+ * finished. */
 typedef struct {
     ovl_context *ctx;
     const ovl_zolo *zolo;
@@ -249,6 +265,7 @@ typedef struct {
     int32_t nrhs;
     ovl_stats *stats;      /* nrhs entries, may be null */
     int32_t status;        /* out */
+    char message[160];     /* out: error text of this instance's solve */
 } ovl_instance;
 ovl_status ovl_sumr_gmresr_solve_many(ovl_instance *inst, int32_t n, const ovl_solver_params *params);
 
@@ -266,6 +283,20 @@ ovl_status ovl_eigspace_get(ovl_context *ctx, double *v_dev, double *vD_dev);
  * diagonalisation history.  k = 0 empties the space. */
 ovl_status ovl_eigspace_set(ovl_context *ctx, int32_t n, int32_t m, double mu, double delta, int32_t k,
                             const double *v_dev, const double *vD_dev);
+/* Checkpoint of the eigenspace (the eigSUMR basis and its images, Secs. 4-5):
+ * ovl_eigspace_save writes its configuration (n, m, mu, delta, eps, k_recalc),
+ * the diagonalisation count, the recent max|UV| values of the Sec. 5.1
+ * bound, the Ritz values and residuals, and the held vectors v and v^D (FP64,
+ * canonical layout) to the file path_host, with the lattice extents;
+ * ovl_eigspace_load reads such a file into a context of the same extents,
+ * replacing its eigenspace (the sets kept for the three-set
+ * re-diagonalisation are not saved: the next calculating solve starts them
+ * again).  Deflation and further calculating solves continue from the loaded
+ * state as from the saved one.  Errors: OVL_ERR_ARG for an unreadable,
+ * truncated or foreign file or other extents, OVL_ERR_STATE when saving an
+ * unconfigured eigenspace.  Both block until done. */
+ovl_status ovl_eigspace_save(ovl_context *ctx, const char *path_host);
+ovl_status ovl_eigspace_load(ovl_context *ctx, const char *path_host);
 /* Run Alg. 6 on the held vectors now. */
 ovl_status ovl_eigspace_diagonalise(ovl_context *ctx);
 /* Recompute v^D = D v for the held vectors with FP64 sign accuracy eta. */
@@ -320,6 +351,17 @@ ovl_status ovl_profile_enable(ovl_context *ctx, int32_t on);
 ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int64_t *launches,
                             double *milliseconds, double *bytes);
 
+/* Streaming ceiling of the GPU's memory system for rooflines (not part of
+ * the method): kind 0 copies bytes from src_dev to dst_dev, kind 1 reads
+ * src_dev (dst_dev receives one 4-byte word per block: give it >= 64 KiB),
+ * with 16-byte loads and stores over a grid of 16 blocks of 256 threads per
+ * compute unit; bytes a multiple of 16, at least 16 MiB; buffers 16-byte
+ * aligned, caller-owned device memory.  One untimed launch, then reps
+ * launches on the context's stream timed by events: *ms_host = average
+ * milliseconds per launch. */
+ovl_status ovl_stream_bench(ovl_context *ctx, int32_t kind, const void *src_dev, void *dst_dev, int64_t bytes,
+                            int32_t reps, double *ms_host);
+
 /* Execution options of a context (value 0 = off, 1 = on):
  *   OVL_OPT_GRAPHS   (default off) the multi-shift CG replays a graph of four
  *                    iterations per chunk after the first chunk (off: every
@@ -337,8 +379,13 @@ ovl_status ovl_profile_read(ovl_context *ctx, int32_t kernel, int32_t prec, int6
  *                    calls then run fewer shifted systems with a larger smallest
  *                    shift; calls at tight accuracy keep all n_z poles.  Direct
  *                    calls of the sign function and the overlap operator through
- *                    this ABI always use the coefficients passed. */
-enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2, OVL_OPT_ADAPTIVE_NZ = 3 };
+ *                    this ABI always use the coefficients passed.
+ *   OVL_OPT_BOUND_PRINTED (default off) the Sec. 5.1 eq. (bound) with chi
+ *                    on the square root only, chi sqrt(eps^2 + r0^2) - r0, as the
+ *                    equation is printed; off: chi (sqrt(eps^2 + r0^2) - r0), the
+ *                    bound scaled by chi as the text describes.  For comparing
+ *                    the two readings; the eigenvector relaxation only. */
+enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2, OVL_OPT_ADAPTIVE_NZ = 3, OVL_OPT_BOUND_PRINTED = 4 };
 ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
 
 /* Stencil launch shapes.  The first launch of each (precision, epilogue,

@@ -45,7 +45,7 @@ notes):
 """
 import numpy as np
 
-from .lattice import dot, g5, norm
+from .lattice import axpy, axpby, dot, g5, norm
 
 
 class MSCGResult:
@@ -75,6 +75,7 @@ def multishift_cg(apply_A, sigma, b, tol, maxiter=100000):
     n = len(sigma)
     base = int(np.argmin(sigma))
     s0 = sigma[base]
+    b = np.ascontiguousarray(b, dtype=np.complex128)
     x = [np.zeros_like(b) for _ in range(n)]
     bnorm = norm(b)
     shift_iters = np.zeros(n, dtype=np.int64)
@@ -99,15 +100,15 @@ def multishift_cg(apply_A, sigma, b, tol, maxiter=100000):
                 alpha * beta_old * (zeta_old[l] - zeta[l])
                 + zeta_old[l] * alpha_old * (1.0 + (sigma[l] - s0) * alpha))
             alpha_l = alpha * zeta_new[l] / zeta[l]
-            x[l] = x[l] + alpha_l * p[l]
-        r = r - alpha * w
+            axpy(alpha_l, p[l], x[l])                   # x_l = x_l + alpha_l p_l
+        axpy(-alpha, w, r)                              # r = r - alpha w
         rr_new = dot(r, r).real
         beta = rr_new / rr
         for l in range(n):
             if not active[l]:
                 continue
             beta_l = beta * (zeta_new[l] / zeta[l]) ** 2
-            p[l] = zeta_new[l] * r + beta_l * p[l]
+            axpby(zeta_new[l], r, beta_l, p[l])         # p_l = zeta_l' r + beta_l p_l
             zeta_old[l] = zeta[l]
             zeta[l] = zeta_new[l]
             shift_iters[l] += 1

@@ -28,6 +28,8 @@ def lib():
         L.ora_kernel.argtypes = [P, P, ctypes.c_double, P, P]
         L.ora_kernel_sq_shift.argtypes = [P, P, ctypes.c_double, ctypes.c_double, P, P, P]
         L.ora_hopping_sites.argtypes = [P, P, P, P, ctypes.c_int64, P]
+        L.ora_axpy_real.argtypes = [ctypes.c_int64, ctypes.c_double, P, P]
+        L.ora_axpby_real.argtypes = [ctypes.c_int64, ctypes.c_double, P, ctypes.c_double, P]
         _lib = L
     return _lib
 
@@ -143,3 +145,20 @@ def dot(a, b):
 
 def norm(a):
     return float(np.linalg.norm(a.reshape(-1)))
+
+
+def _inplace(y, x):
+    assert y.dtype == np.complex128 and y.flags.c_contiguous and x.dtype == np.complex128
+    assert x.flags.c_contiguous and x.size == y.size
+
+
+def axpy(a, x, y):
+    """y <- y + a x in place (a real), the same values as y + a * x."""
+    _inplace(y, x)
+    lib().ora_axpy_real(y.size, float(a), _ptr(x), _ptr(y))
+
+
+def axpby(a, x, b, y):
+    """y <- a x + b y in place (a, b real), the same values as a * x + b * y."""
+    _inplace(y, x)
+    lib().ora_axpby_real(y.size, float(a), _ptr(x), float(b), _ptr(y))

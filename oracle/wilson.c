@@ -229,3 +229,20 @@ void ora_hopping_sites(const int *L, const cplx *U, const cplx *in,
             for (int a = 0; a < 3; ++a) out[i * 12 + sp * 3 + a] = acc[sp][a];
     }
 }
+
+/* Vector updates of the multi-shift CG on n complex entries, one IEEE
+ * multiply and one add per real component, in the order written:
+ *   ora_axpy_real:  y = y + a x
+ *   ora_axpby_real: y = a x + b y
+ * (a, b real; the same values numpy's y + a * x and a * x + b * y give). */
+void ora_axpy_real(int64_t n, double a, const cplx *x, cplx *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) y[i] = y[i] + a * x[i];
+}
+
+void ora_axpby_real(int64_t n, double a, const cplx *x, double b, cplx *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) y[i] = a * x[i] + b * y[i];
+}

@@ -19,7 +19,7 @@ F64, F32, HALF = 0, 1, 2
 SRC_POINT, SRC_GAUSS, SRC_Z2 = 0, 1, 2
 MAX_NZ = 64
 KERN_STENCIL, KERN_SHIFT = 0, 1
-OPT_GRAPHS, OPT_AUTOTUNE, OPT_ADAPTIVE_NZ = 1, 2, 3
+OPT_GRAPHS, OPT_AUTOTUNE, OPT_ADAPTIVE_NZ, OPT_BOUND_PRINTED = 1, 2, 3, 4
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_NOMEM", -4: "ERR_NOT_CONVERGED",
           -5: "ERR_BREAKDOWN", -6: "ERR_UNSUPPORTED", -7: "ERR_STATE"}
@@ -79,7 +79,8 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_sumr_gmresr_solve", "ovl_profile_enable", "ovl_profile_read", "ovl_eigspace_info",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
            "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option",
-           "ovl_sumr_gmresr_solve_many", "ovl_eigsumr_eigensolve", "ovl_wilson_dslash_noalloc"]
+           "ovl_sumr_gmresr_solve_many", "ovl_eigsumr_eigensolve", "ovl_wilson_dslash_noalloc",
+           "ovl_kernel_interval", "ovl_stream_bench", "ovl_eigspace_save", "ovl_eigspace_load"]
 
 _lib = None
 
@@ -108,6 +109,7 @@ def lib():
         "ovl_zolotarev_coeffs": ([I32, D, D, P], I32),
         "ovl_lowmodes_compute": ([P, D, I32, D, P, P], I32),
         "ovl_lowmodes_set": ([P, I32, P, P], I32),
+        "ovl_kernel_interval": ([P, D, I32, P, P, P], I32),
         "ovl_lowmodes_get": ([P, P], I32),
         "ovl_sign_zolotarev_mscg": ([P, D, P, P, P, I32, D, I32, P], I32),
         "ovl_overlap_apply": ([P, D, D, P, P, P, I32, D, I32, P], I32),
@@ -115,6 +117,7 @@ def lib():
         "ovl_tuning_get": ([P, P, P, I32, P], I32),
         "ovl_tuning_set": ([P, P, P, I32], I32),
         "ovl_set_option": ([P, I32, I32], I32),
+        "ovl_stream_bench": ([P, I32, P, P, I64, I32, P], I32),
         "ovl_sumr_gmresr_solve_many": ([P, I32, P], I32),
         "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
         "ovl_profile_enable": ([P, I32], I32),
@@ -123,6 +126,8 @@ def lib():
         "ovl_eigspace_get": ([P, P, P], I32),
         "ovl_eigspace_set": ([P, I32, I32, D, D, I32, P, P], I32),
         "ovl_eigspace_diagonalise": ([P], I32),
+        "ovl_eigspace_save": ([P, ctypes.c_char_p], I32),
+        "ovl_eigspace_load": ([P, ctypes.c_char_p], I32),
         "ovl_eigspace_recompute": ([P, D, P, D], I32),
         "ovl_deflate_project": ([P, P, P, P, I32], I32),
         "ovl_eigsumr_eigensolve": ([P, P, P, P, I32, I32, D, P, P, P, P], I32),
@@ -253,6 +258,14 @@ class Context:
         self.n_low = n_low
         return list(ev), lmax.value
 
+    def kernel_interval(self, rho, max_iter=400):
+        """(lmin, lmin_err, lmax): ends of the spectrum of |K| by Lanczos on K^2
+        (lmin lies above the true smallest |lambda|; take a margin below it)."""
+        lo, err, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().ovl_kernel_interval(self._h, float(rho), int(max_iter), ctypes.byref(lo), ctypes.byref(err),
+                                         ctypes.byref(hi)))
+        return lo.value, err.value, hi.value
+
     def lowmodes_set(self, evals, evecs):
         n = len(evals)
         ev = (ctypes.c_double * max(n, 1))(*[float(e) for e in evals])
@@ -337,6 +350,12 @@ class Context:
         pd = _dev(vD, (self.V, 4, 3), "vD") if k else None
         _check(lib().ovl_eigspace_set(self._h, int(n), int(m), float(mu), float(delta), k, pv, pd))
 
+    def eigspace_save(self, path):
+        _check(lib().ovl_eigspace_save(self._h, os.fsencode(path)))
+
+    def eigspace_load(self, path):
+        _check(lib().ovl_eigspace_load(self._h, os.fsencode(path)))
+
     def eigspace_diagonalise(self):
         _check(lib().ovl_eigspace_diagonalise(self._h))
 
@@ -366,6 +385,15 @@ class Context:
         return x0, dx0
 
     # -- profiling
+    def stream_bench(self, kind, src, dst, reps=20):
+        """Average ms per launch of the library's streaming kernel: kind 0 copies
+        src into dst (same size), kind 1 reads src (dst: >= 64 KiB scratch)."""
+        ms = ctypes.c_double()
+        _check(lib().ovl_stream_bench(self._h, int(kind), ctypes.c_void_p(src.data_ptr()),
+                                      ctypes.c_void_p(dst.data_ptr()), int(src.numel() * src.element_size()),
+                                      int(reps), ctypes.byref(ms)))
+        return ms.value
+
     def set_option(self, option, value):
         _check(lib().ovl_set_option(self._h, int(option), int(bool(value))))
 
@@ -399,7 +427,7 @@ class Context:
 class Instance(ctypes.Structure):
     _fields_ = [("ctx", ctypes.c_void_p), ("zolo", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("nrhs", ctypes.c_int32), ("stats", ctypes.c_void_p),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("message", ctypes.c_char * 160)]
 
 
 def solve_many(items, params):
@@ -416,7 +444,7 @@ def solve_many(items, params):
         keep.append((x, st))
         arr[i] = Instance(ctx._h.value if hasattr(ctx._h, "value") else ctx._h, ctypes.addressof(zolo),
                           _dev(b, (ctx.V, 4, 3), "b").value, _dev(x, (ctx.V, 4, 3), "x").value, nrhs,
-                          ctypes.addressof(st), 0)
+                          ctypes.addressof(st), 0, b"")
     _check(lib().ovl_sumr_gmresr_solve_many(arr, n, ctypes.byref(params)), allow=(-4,))
     return [(keep[i][0], list(keep[i][1]), arr[i].status) for i in range(n)]
 

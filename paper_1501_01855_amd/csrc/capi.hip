@@ -2,7 +2,9 @@
 // between the canonical complex128 layout and the internal planes, error
 // translation.  No exception crosses this boundary.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -58,6 +60,7 @@ static void check_zolo(const ovl_zolo *z)
 }
 
 static constexpr int MAX_NRHS = 16;
+static constexpr int MAX_SOLVE_THREADS = 32;   // host threads driving instances at once
 
 extern "C" {
 
@@ -229,6 +232,19 @@ ovl_status ovl_zolotarev_coeffs(int32_t n_z, double a, double b, ovl_zolo *out_h
     return guard([&] {
         OVL_REQUIRE(out_host != nullptr, OVL_ERR_ARG, "null output");
         zolotarev(n_z, a, b, *out_host);
+    });
+}
+
+ovl_status ovl_kernel_interval(ovl_context *ctx, double rho, int32_t max_iter, double *lmin_host,
+                               double *lmin_err_host, double *lmax_host)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(std::isfinite(rho), OVL_ERR_ARG, "rho must be finite");
+        OVL_REQUIRE(max_iter >= 2 && max_iter <= 2000, OVL_ERR_ARG, "max_iter must be in [2, 2000]");
+        OVL_REQUIRE(lmin_host != nullptr, OVL_ERR_ARG, "null lmin output");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        kernel_interval(*ctx, rho, max_iter, lmin_host, lmin_err_host, lmax_host);
     });
 }
 
@@ -436,6 +452,105 @@ ovl_status ovl_eigspace_set(ovl_context *ctx, int32_t n, int32_t m, double mu, d
     });
 }
 
+// File layout of a saved eigenspace: the 8-byte tag "OVLEIG01", int32
+// extents[4], n, m, k, ndiag, k_recalc, n_uv, n_ritz; double mu, delta, eps;
+// double uv[n_uv], ritz[n_ritz], resid[n_ritz]; then the k vectors v and the
+// k images v^D, each 12 V complex128 in the canonical layout.
+static const char EIG_TAG[8] = {'O', 'V', 'L', 'E', 'I', 'G', '0', '1'};
+
+ovl_status ovl_eigspace_save(ovl_context *ctx, const char *path)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(path != nullptr, OVL_ERR_ARG, "null path");
+        const EigSpace &e = ctx->eig;
+        OVL_REQUIRE(e.m > 0, OVL_ERR_STATE, "eigenspace not configured");
+        std::FILE *fp = std::fopen(path, "wb");
+        OVL_REQUIRE(fp != nullptr, OVL_ERR_ARG, std::string("cannot open ") + path + " for writing");
+        bool ok = std::fwrite(EIG_TAG, 1, 8, fp) == 8;
+        const int32_t hdr[11] = {ctx->g.L[0], ctx->g.L[1], ctx->g.L[2], ctx->g.L[3], e.n, e.m, e.k, e.ndiag,
+                                 e.krecalc, (int32_t)e.uv_hist.size(), (int32_t)e.ritz.size()};
+        const double par[3] = {e.mu, e.delta, e.eps};
+        ok = ok && std::fwrite(hdr, sizeof(hdr), 1, fp) == 1 && std::fwrite(par, sizeof(par), 1, fp) == 1;
+        auto wr = [&](const std::vector<double> &v) {
+            ok = ok && (v.empty() || std::fwrite(v.data(), sizeof(double), v.size(), fp) == v.size());
+        };
+        wr(e.uv_hist);
+        wr(e.ritz);
+        wr(e.resid);
+        const size_t FB = field_bytes(ctx->g, OVL_F64);
+        double *canon = (double *)ctx->buf("eigio_canon", FB);
+        void *host = ctx->host_stage(FB);
+        for (int set = 0; set < 2 && ok; ++set)
+            for (int i = 0; i < e.k && ok; ++i) {
+                unpack_spinor(*ctx, (set ? e.VD : e.V) + (size_t)i * 12 * ctx->g.V, canon, 1, OVL_F64);
+                OVL_HIP(hipMemcpyAsync(host, canon, FB, hipMemcpyDeviceToHost, ctx->stream));
+                OVL_HIP(hipStreamSynchronize(ctx->stream));
+                ok = std::fwrite(host, 1, FB, fp) == FB;
+            }
+        ok = (std::fclose(fp) == 0) && ok;
+        OVL_REQUIRE(ok, OVL_ERR_ARG, std::string("write to ") + path + " failed");
+    });
+}
+
+ovl_status ovl_eigspace_load(ovl_context *ctx, const char *path)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(path != nullptr, OVL_ERR_ARG, "null path");
+        std::FILE *fp = std::fopen(path, "rb");
+        OVL_REQUIRE(fp != nullptr, OVL_ERR_ARG, std::string("cannot open ") + path);
+        struct Closer {
+            std::FILE *f;
+            ~Closer() { std::fclose(f); }
+        } closer{fp};
+        char tag[8];
+        int32_t hdr[11];
+        double par[3];
+        OVL_REQUIRE(std::fread(tag, 1, 8, fp) == 8 && std::memcmp(tag, EIG_TAG, 8) == 0, OVL_ERR_ARG,
+                    "not an eigenspace file");
+        OVL_REQUIRE(std::fread(hdr, sizeof(hdr), 1, fp) == 1 && std::fread(par, sizeof(par), 1, fp) == 1, OVL_ERR_ARG,
+                    "truncated eigenspace file");
+        for (int mdim = 0; mdim < 4; ++mdim)
+            OVL_REQUIRE(hdr[mdim] == ctx->g.L[mdim], OVL_ERR_ARG, "eigenspace file is for other lattice extents");
+        const int n = hdr[4], m = hdr[5], k = hdr[6], nuv = hdr[9], nritz = hdr[10];
+        OVL_REQUIRE(n >= 1 && m > n && m <= 512 && k >= 0 && k <= m && nuv >= 0 && nuv <= 10 && nritz >= 0 &&
+                        nritz <= m && hdr[7] >= 0 && hdr[8] >= 1,
+                    OVL_ERR_ARG, "eigenspace file header out of range");
+        OVL_REQUIRE(par[0] >= 0.0 && par[0] < 1.0 && par[1] > 0.0 && par[1] < 0.5 && par[2] > 0.0, OVL_ERR_ARG,
+                    "eigenspace file parameters out of range");
+        std::vector<double> uv(nuv), ritz(nritz), resid(nritz);
+        auto rd = [&](std::vector<double> &v) {
+            OVL_REQUIRE(v.empty() || std::fread(v.data(), sizeof(double), v.size(), fp) == v.size(), OVL_ERR_ARG,
+                        "truncated eigenspace file");
+        };
+        rd(uv);
+        rd(ritz);
+        rd(resid);
+        EigSpace &e = ctx->eig;
+        e.mu = -1.0;   // fresh configuration
+        eig_configure(*ctx, n, m, par[0], par[1], par[2], hdr[8]);
+        const size_t FB = field_bytes(ctx->g, OVL_F64);
+        double *canon = (double *)ctx->buf("eigio_canon", FB);
+        void *host = ctx->host_stage(FB);
+        for (int set = 0; set < 2; ++set)
+            for (int i = 0; i < k; ++i) {
+                OVL_REQUIRE(std::fread(host, 1, FB, fp) == FB, OVL_ERR_ARG, "truncated eigenspace file");
+                OVL_HIP(hipMemcpyAsync(canon, host, FB, hipMemcpyHostToDevice, ctx->stream));
+                pack_spinor(*ctx, canon, (set ? e.VD : e.V) + (size_t)i * 12 * ctx->g.V, 1, OVL_F64);
+                OVL_HIP(hipStreamSynchronize(ctx->stream));   // the staging buffer is reused
+            }
+        e.k = k;
+        e.ndiag = hdr[7];
+        e.uv_hist = uv;
+        e.ritz = ritz;
+        e.resid = resid;
+        e.nsets = 0;
+        e.defl_ready = false;
+        e.spec_ready = false;
+    });
+}
+
 ovl_status ovl_eigspace_diagonalise(ovl_context *ctx)
 {
     return guard([&] {
@@ -547,20 +662,45 @@ ovl_status ovl_sumr_gmresr_solve_many(ovl_instance *inst, int32_t n, const ovl_s
                     "an instance list may hold each context once");
     });
     if (st != OVL_OK) return st;
+    // a bounded pool of host threads takes instances from a shared counter;
+    // each keeps its instance's error text (ovl_last_error is per thread)
+    const int workers = std::min<int>(n, MAX_SOLVE_THREADS);
+    std::atomic<int> next{0};
     std::vector<std::thread> pool;
-    pool.reserve(n);
-    for (int i = 0; i < n; ++i)
-        pool.emplace_back([i, inst, params] {
-            ovl_instance &q = inst[i];
-            q.status = ovl_sumr_gmresr_solve(q.ctx, q.zolo, params, q.b_dev, q.x_dev, q.nrhs, q.stats);
+    pool.reserve(workers);
+    for (int w = 0; w < workers; ++w)
+        pool.emplace_back([&next, n, inst, params] {
+            for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) {
+                ovl_instance &q = inst[i];
+                q.message[0] = '\0';
+                q.status = ovl_sumr_gmresr_solve(q.ctx, q.zolo, params, q.b_dev, q.x_dev, q.nrhs, q.stats);
+                if (q.status != OVL_OK) {
+                    std::strncpy(q.message, ovl::last_error(), sizeof(q.message) - 1);
+                    q.message[sizeof(q.message) - 1] = '\0';
+                }
+            }
         });
     for (auto &t : pool) t.join();
     for (int i = 0; i < n; ++i)
         if (inst[i].status != OVL_OK) {
-            set_error("instance " + std::to_string(i) + " failed (status " + std::to_string(inst[i].status) + ")");
+            set_error("instance " + std::to_string(i) + ": " + inst[i].message);
             return (ovl_status)inst[i].status;
         }
     return OVL_OK;
+}
+
+ovl_status ovl_stream_bench(ovl_context *ctx, int32_t kind, const void *src_dev, void *dst_dev, int64_t bytes,
+                            int32_t reps, double *ms_host)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(kind == 0 || kind == 1, OVL_ERR_ARG, "kind must be 0 (copy) or 1 (read)");
+        OVL_REQUIRE(src_dev && dst_dev && ms_host && reps >= 1, OVL_ERR_ARG, "bad arguments");
+        OVL_REQUIRE(bytes >= 16 * 1024 * 1024 && bytes % 16 == 0, OVL_ERR_ARG,
+                    "bytes must be a multiple of 16 and at least 16 MiB");
+        OVL_REQUIRE(((uintptr_t)src_dev | (uintptr_t)dst_dev) % 16 == 0, OVL_ERR_ARG, "buffers must be 16-byte aligned");
+        *ms_host = stream_bench(*ctx, kind, src_dev, dst_dev, bytes, reps);
+    });
 }
 
 ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value)
@@ -574,6 +714,8 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value)
             ctx->autotune = value;
         else if (option == OVL_OPT_ADAPTIVE_NZ)
             ctx->adaptive_nz = value != 0;
+        else if (option == OVL_OPT_BOUND_PRINTED)
+            ctx->eig.bound_printed = value != 0;
         else
             throw Error{OVL_ERR_ARG, "unknown option"};
     });

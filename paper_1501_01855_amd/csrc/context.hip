@@ -3,6 +3,8 @@
 
 #include <algorithm>
 
+#include <thread>
+
 #include "context.h"
 #include "kernels.h"
 
@@ -59,6 +61,7 @@ void Context::spin_wait(hipEvent_t e)
         const hipError_t r = hipEventQuery(e);
         if (r == hipSuccess) return;
         if (r != hipErrorNotReady) OVL_HIP(r);
+        std::this_thread::yield();   // several contexts may be polled by threads sharing the cores
     }
 }
 

@@ -267,8 +267,16 @@ __device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__re
 //             through t, a column slice at a time, so that the t- and
 //             z-neighbours of a slice are fetched by the same XCD shortly
 //             before or after and meet in its L2.
+//  MAP_GRP32 / MAP_GRP64  (for several fields) each XCD owns a contiguous
+//             range of tiles and walks it in groups of G = 32 / 64 tiles, all
+//             fields of a group one after another, the tiles of a group side
+//             by side: the blocks of one tile's fields are G blocks apart on
+//             the same XCD, so the group's links (G x 256 sites, 2.4 MB at
+//             G = 32 in FP32, G = 64 in FP16) are fetched by the first field
+//             and found in that XCD's L2 by the others, and no two blocks in
+//             flight ask for the same link lines at once.
 // Fields run fastest within a tile (the fields of one tile share its links).
-enum { MAP_LEX = 0, MAP_REMAP = 1, MAP_COL = 2 };
+enum { MAP_LEX = 0, MAP_REMAP = 1, MAP_COL = 2, MAP_GRP32 = 3, MAP_GRP64 = 4 };
 
 template <int MAP, int TPS>
 __device__ __forceinline__ void site_of_thread(const Geom &g, unsigned &tile, unsigned &f, int64_t &s, int32_t co[4],
@@ -296,8 +304,43 @@ __device__ __forceinline__ void site_of_thread(const Geom &g, unsigned &tile, un
         co[3] = t;
         s = co[0] + (int64_t)g.L[0] * (co[1] + (int64_t)g.L[1] * (co[2] + (int64_t)g.L[2] * co[3]));
     } else {
-        tile_of_block<MAP == MAP_REMAP>(tile, f);
-        s = (int64_t)tile * SPB + lane;
+        bool idle = false;
+        if constexpr (MAP == MAP_GRP32 || MAP == MAP_GRP64) {
+            // X = 8 ceil(T / 8) for T tiles; XCD x owns T_x = q or q + 1
+            // consecutive tiles (q = T / 8, the first T % 8 XCDs one more),
+            // in groups of G tiles, each group's fields back to back (a last
+            // partial group likewise).  An XCD with q tiles has one idle block
+            // per field, which writes the (zero) partials of slot T + x - r.
+            constexpr unsigned G = MAP == MAP_GRP32 ? 32u : 64u;
+            const unsigned X = gridDim.x, Y = gridDim.y;
+            const unsigned T = (unsigned)((g.V + SPB - 1) / SPB);
+            const unsigned lin = blockIdx.y * X + blockIdx.x;
+            const unsigned xcd = lin % 8, k = lin / 8;
+            const unsigned q = T / 8, rr = T % 8;
+            const unsigned Tx = q + (xcd < rr ? 1u : 0u);
+            const unsigned start = xcd * q + (xcd < rr ? xcd : rr);
+            if (k >= Tx * Y) {
+                idle = true;
+                f = k - Tx * Y;
+                tile = T + xcd - rr;
+            } else {
+                const unsigned full = Tx / G;            // whole groups
+                unsigned t;
+                if (k < full * G * Y) {
+                    const unsigned grp = k / (G * Y), r = k % (G * Y);
+                    f = r / G;
+                    t = grp * G + r % G;
+                } else {
+                    const unsigned last = Tx - full * G, r = k - full * G * Y;
+                    f = r / last;
+                    t = full * G + r % last;
+                }
+                tile = start + t;
+            }
+        } else {
+            tile_of_block<MAP == MAP_REMAP>(tile, f);
+        }
+        s = idle ? g.V : (int64_t)tile * SPB + lane;
         valid = s < g.V;
         const int32_t si = valid ? (int32_t)s : 0;
         co[0] = si % g.L[0];
@@ -843,9 +886,11 @@ __global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT
 // the t-marching kernel with one / two lanes per site (Lt a multiple of 8).
 // With FP16 storage the two lanes of a site share its scale through LDS.  8 .. 11 the
 // LDS-tiled march with T = 1, 2, 4, 8 time slices per block (Lt a multiple of
-// T; FP32 and FP16 storage).
-static constexpr int N_VARIANTS = 12;
-static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7) ? 2 : 1; }
+// T; FP32 and FP16 storage).  12 .. 15 the grouped XCD order MAP_GRP32 /
+// MAP_GRP64 with one / two lanes per site (12: G 32, one lane; 13: G 32, two;
+// 14: G 64, one; 15: G 64, two).
+static constexpr int N_VARIANTS = 16;
+static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7 || v == 13 || v == 15) ? 2 : 1; }
 
 // Tile of the LDS-tiled march: the 256-site box with the fewest padded sites,
 // then the fewest face sites (each face lane fetches a neighbour from memory).
@@ -880,6 +925,7 @@ unsigned stencil_tiles(const Geom &g, int v)
 {
     const int tps = variant_tps(v);
     const int spb = 256 / tps;
+    if (v >= 12) return 8u * (unsigned)(((g.V + spb - 1) / spb + 7) / 8);   // 8 XCDs x their largest share
     if (v >= 8) {
         const TileShape ts = tile_shape(g, v);
         return (unsigned)(ts.n[0] * ts.n[1] * ts.n[2] * ts.nch);
@@ -894,7 +940,7 @@ bool stencil_variant_ok(const Geom &g, int prec, int v)
     if (v < 0 || v >= N_VARIANTS) return false;
     if ((v == 4 || v == 5) && !g.col_ok) return false;
     if ((v == 6 || v == 7) && g.L[3] % 8 != 0) return false;
-    if (v >= 8) return prec != OVL_F64 && g.L[3] % (1 << (v - 8)) == 0;
+    if (v >= 8 && v < 12) return prec != OVL_F64 && g.L[3] % (1 << (v - 8)) == 0;
     return true;
 }
 
@@ -910,7 +956,10 @@ int64_t stencil_tiles_max(const Geom &g)
 template <typename ST, typename GT, int EPI, int TPS, int MAP>
 static void launch_variant(Context &c, const StencilArgs<ST> &a, const GT *U, int nf, const PendingEvent *pe)
 {
-    const int v = MAP == MAP_COL ? (TPS == 2 ? 5 : 4) : (TPS == 2 ? 2 : 0) + (MAP == MAP_REMAP ? 1 : 0);
+    const int v = MAP == MAP_COL     ? (TPS == 2 ? 5 : 4)
+                  : MAP == MAP_GRP32 ? (TPS == 2 ? 13 : 12)
+                  : MAP == MAP_GRP64 ? (TPS == 2 ? 15 : 14)
+                                     : (TPS == 2 ? 2 : 0) + (MAP == MAP_REMAP ? 1 : 0);
     dim3 grid(stencil_tiles(c.g, v), nf);
     launch_k(c, pe, k_stencil<ST, GT, EPI, TPS, MAP>, grid, dim3(256), 0, a, U);
 }
@@ -935,7 +984,7 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
                          const PendingEvent *pe = nullptr)
 {
     if constexpr (!std::is_same<ST, double2>::value) {   // FP32 math only
-        if (id >= 8) {
+        if (id >= 8 && id < 12) {
             launch_lds<ST, GT, EPI>(c, id, a, U, nf, pe);
             return;
         }
@@ -949,6 +998,10 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
         case 4: launch_variant<ST, GT, EPI, 1, MAP_COL>(c, a, U, nf, pe); break;
         case 5: launch_variant<ST, GT, EPI, 2, MAP_COL>(c, a, U, nf, pe); break;
         case 6: launch_tmarch<ST, GT, EPI, 1>(c, a, U, nf, pe); break;
+        case 12: launch_variant<ST, GT, EPI, 1, MAP_GRP32>(c, a, U, nf, pe); break;
+        case 13: launch_variant<ST, GT, EPI, 2, MAP_GRP32>(c, a, U, nf, pe); break;
+        case 14: launch_variant<ST, GT, EPI, 1, MAP_GRP64>(c, a, U, nf, pe); break;
+        case 15: launch_variant<ST, GT, EPI, 2, MAP_GRP64>(c, a, U, nf, pe); break;
         default: launch_tmarch<ST, GT, EPI, 2>(c, a, U, nf, pe); break;
         }
     }

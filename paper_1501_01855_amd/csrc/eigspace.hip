@@ -251,8 +251,11 @@ double eig_sign_accuracy(const Context &c)
         for (double x : e.uv_hist) uv += x;
         uv /= (double)e.uv_hist.size();
     }
-    const double dd = chi * (std::sqrt(e.eps * e.eps + r0 * r0) - r0) /
-                      (std::sqrt((double)(e.m - e.n) * e.krecalc) * std::max(uv, 1e-300));
+    // chi scales the whole target (the text of Sec. 5.1); the printed equation
+    // puts it on the square root alone, available as an option for comparison
+    const double num = e.bound_printed ? chi * std::sqrt(e.eps * e.eps + r0 * r0) - r0
+                                       : chi * (std::sqrt(e.eps * e.eps + r0 * r0) - r0);
+    const double dd = num / (std::sqrt((double)(e.m - e.n) * e.krecalc) * std::max(uv, 1e-300));
     return 2.0 * dd / (1.0 - e.mu);
 }
 

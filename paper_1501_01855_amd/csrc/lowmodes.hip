@@ -174,3 +174,68 @@ void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *eva
 }
 
 }  // namespace ovl
+
+namespace ovl {
+
+// Ends of the spectrum of K^2 by Lanczos (FP64, one vector, no
+// re-orthogonalisation: the extreme Ritz values converge regardless, and
+// the smallest one decreases monotonically towards lambda_min^2).  Set-up
+// for the Zolotarev interval when no kernel modes are treated exactly.
+void kernel_interval(Context &c, double rho, int max_iter, double *lmin, double *lmin_err, double *lmax)
+{
+    const Geom &g = c.g;
+    const size_t FB = field_bytes(g, OVL_F64);
+    double2 *v = (double2 *)c.buf("li_v", FB);
+    double2 *vp = (double2 *)c.buf("li_vp", FB);
+    double2 *w = (double2 *)c.buf("li_w", FB);
+    double2 *t = (double2 *)c.buf("li_t", FB);
+    double *canon = (double *)c.buf("lm_canon", FB);
+    source_generate(c, OVL_SRC_GAUSS, 0x5EED1A00ull, 0, 0, 0, canon);
+    pack_spinor(c, canon, t, 1, OVL_F64);
+    std::vector<double> n2;
+    norm2_f64(c, t, 1, n2);
+    lincomb3_f64(c, 1.0 / std::sqrt(n2[0]), t, 0.0, t, 0.0, nullptr, v, 1);
+    zero_fields(c, vp, 1, OVL_F64);   // read (times 0) by the first step
+    std::vector<double> alpha, beta;   // T = tridiag(beta, alpha, beta)
+    double bprev = 0.0, th_min = 0.0, th_max = 0.0, err = 0.0, last = -1.0;
+    int stable = 0;
+    for (int j = 0; j < max_iter; ++j) {
+        stencil(c, EPI_K, OVL_F64, v, t, 1, rho, 0.0, nullptr, nullptr);
+        stencil(c, EPI_K, OVL_F64, t, w, 1, rho, 0.0, nullptr, nullptr);   // w = K^2 v
+        std::vector<cplx<double>> d;
+        dot_f64(c, v, w, 1, d);
+        const double a = d[0].re;
+        lincomb3_f64(c, 1.0, w, -a, v, -bprev, vp, t, 1);                  // t = w - a v - b_prev v_prev
+        norm2_f64(c, t, 1, n2);
+        const double b = std::sqrt(n2[0]);
+        alpha.push_back(a);
+        beta.push_back(b);
+        const int n = (int)alpha.size();
+        if (n % 10 == 0 || j == max_iter - 1 || b == 0.0) {
+            std::vector<dense::zc> T((size_t)n * n, 0.0);
+            for (int i = 0; i < n; ++i) {
+                T[(size_t)i * n + i] = alpha[i];
+                if (i + 1 < n) T[(size_t)i * n + i + 1] = T[(size_t)(i + 1) * n + i] = beta[i];
+            }
+            std::vector<double> th;
+            std::vector<dense::zc> Y;
+            dense::eigh(n, T, th, Y);
+            th_min = th[0];
+            th_max = th[n - 1];
+            err = std::abs(b * Y[(size_t)(n - 1) * n + 0]);   // |beta_n y_n| of the smallest Ritz pair
+            if (last > 0.0 && std::fabs(last - th_min) <= 1e-10 * th_min) ++stable;
+            else stable = 0;
+            last = th_min;
+            if (stable >= 2 || b == 0.0) break;
+        }
+        std::swap(vp, v);                                                  // v_prev <- v
+        lincomb3_f64(c, 1.0 / b, t, 0.0, t, 0.0, nullptr, v, 1);           // v <- t / b
+        bprev = b;
+    }
+    OVL_HIP(hipStreamSynchronize(c.stream));
+    *lmin = std::sqrt(std::max(th_min, 0.0));
+    if (lmin_err) *lmin_err = err;
+    if (lmax) *lmax = std::sqrt(std::max(th_max, 0.0));
+}
+
+}  // namespace ovl

@@ -41,6 +41,9 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
 
 // Kernel low modes (lowmodes.hip).
 void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *evals, double *lmax);
+// Ends of the K^2 spectrum by Lanczos: sqrt of the smallest / largest Ritz
+// values and the residual bound of the smallest (lowmodes.hip).
+void kernel_interval(Context &c, double rho, int max_iter, double *lmin, double *lmin_err, double *lmax);
 
 // eigSUMR and deflation (eigspace.hip).
 void eig_configure(Context &c, int n, int m, double mu, double delta, double eps, int krecalc);
@@ -57,6 +60,10 @@ void eig_project(Context &c, const double2 *b, double2 *x0, double2 *Dx0);
 // the spectral preconditioner of Sec. 4 from the held eigenspace
 bool spectral_available(const Context &c);
 void spectral_apply(Context &c, const double2 *v, double2 *out, int nf);
+
+// Streaming ceiling of the memory system (stream.hip): average ms per launch
+// of a 16-byte-word copy (kind 0) or read (kind 1) over bytes.
+double stream_bench(Context &c, int kind, const void *src, void *dst, int64_t bytes, int reps);
 
 // Generators (gen.hip).
 void gauge_generate(Context &c, uint64_t seed, double eps, double *canon_out);

@@ -130,11 +130,36 @@ static void sign_f64(Context &c, double rho, const ovl_zolo &zin, const double2 
             }
 }
 
-// u = gamma_5 sign(K) q for the fields with eta[f] > 0.
+// u = gamma_5 sign(K) q for the fields with eta[f] > 0.  The active fields
+// are grouped by the precision their own accuracy calls for, and each group
+// runs its own sign call (its own Zolotarev order with the adaptive option):
+// a field whose middle solve has just restarted at a tight accuracy does not
+// pull the others up to FP32 or FP64.
 static void unitary_f64(Context &c, double rho, const ovl_zolo &z, const double2 *q, double2 *u, int nf,
                         const double *eta, const ovl_solver_params &prm, ovl_stats *st)
 {
-    sign_f64(c, rho, z, q, u, nf, eta, prec_for(prm, min_active(eta, nf)), prm.max_mscg, st, true);
+    int want[MAXF], present[3] = {0, 0, 0};
+    for (int f = 0; f < nf; ++f) {
+        want[f] = eta[f] > 0.0 ? prec_for(prm, eta[f]) : -1;
+        if (want[f] >= 0) present[want[f]] += 1;
+    }
+    const int groups = (present[0] > 0) + (present[1] > 0) + (present[2] > 0);
+    if (groups <= 1) {
+        sign_f64(c, rho, z, q, u, nf, eta, prec_for(prm, min_active(eta, nf)), prm.max_mscg, st, true);
+    } else {
+        // each group's call writes every field of its output (the others'
+        // unspecified), so it goes to a scratch set and its own fields are copied out
+        const size_t FB = field_bytes(c.g, OVL_F64);
+        double2 *tmp = (double2 *)c.buf("u_group", FB * nf);
+        for (int p = 0; p < 3; ++p) {
+            if (!present[p]) continue;
+            double eg[MAXF];
+            for (int f = 0; f < nf; ++f) eg[f] = want[f] == p ? eta[f] : 0.0;
+            sign_f64(c, rho, z, q, tmp, nf, eg, p, prm.max_mscg, st, true);
+            for (int f = 0; f < nf; ++f)
+                if (want[f] == p) copy_fields(c, tmp + (size_t)f * 12 * c.g.V, u + (size_t)f * 12 * c.g.V, 1, OVL_F64);
+        }
+    }
     gamma5_f64(c, u, nf);
 }
 
@@ -583,6 +608,9 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
     if (prm.eig_calc) eig_configure(c, prm.n_eig, prm.m_eig, mu, prm.delta_split, prm.eig_eps, prm.k_recalc);
     std::vector<double> bn, rn;
     norms(c, b, nf, bn);
+    for (int f = 0; f < nf; ++f)
+        OVL_REQUIRE(std::isfinite(bn[f]), OVL_ERR_BREAKDOWN,
+                    "right-hand side " + std::to_string(f) + " has a non-finite entry");
     rn = bn;
     std::vector<int> steps(nf, 0), active(nf, 0);
     ovl_status status = OVL_OK;

@@ -22,6 +22,9 @@ Recipe
 * Layouts are the canonical ones: ``U[site][mu][a][b]`` and
   ``psi[site][spin][colour]``, complex128, site lexicographic with x fastest.
 """
+import concurrent.futures
+import os
+
 import numpy as np
 
 M32 = np.uint64(0xFFFFFFFF)
@@ -228,17 +231,32 @@ def volume(dims):
     return d[0] * d[1] * d[2] * d[3]
 
 
-def gauge_field(dims, seed, eps, chunk=1 << 18):
-    """U_mu(x) = exp(i eps sum_a g_a T^a), canonical complex128 [V,4,3,3]."""
+def gauge_field(dims, seed, eps, chunk=1 << 16, workers=None):
+    """U_mu(x) = exp(i eps sum_a g_a T^a), canonical complex128 [V,4,3,3].
+
+    Links are independent (each has its own counter), so chunks of links are
+    generated by a pool of threads; every link goes through the same sequence
+    of operations whatever the chunking, so the field is the same bit for bit."""
     V = volume(dims)
     nlink = 4 * V
     out = np.empty((nlink, 3, 3), np.complex128)
-    for s in range(0, nlink, chunk):
+
+    def work(s):
         idx = np.arange(s, min(nlink, s + chunk), dtype=np.uint64)
         g = normals(idx, 4, TAG_GAUGE, seed)   # 8 deviates per link
         xr, xi = _su3_algebra(g, eps)
         ur, ui = su3_exp(xr, xi)
         out[s:s + len(idx)] = ur + 1j * ui
+
+    starts = range(0, nlink, chunk)
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or nlink <= chunk:
+        for s in starts:
+            work(s)
+    else:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(work, starts))
     return out.reshape(V, 4, 3, 3)
 
 
