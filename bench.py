@@ -64,19 +64,23 @@ def parse():
                     help="add the twelve 24^3x48 point sources deflated in one batched call")
     ap.add_argument("--half-threshold", type=float, default=3e-3,
                     help="16^3x32 leg: sign accuracies at or above this use FP16 storage (> 1 disables)")
-    ap.add_argument("--c3-eta", type=float, default=1e-3, help="24^3x48: middle-solve accuracy eta~ of GMRESR")
-    ap.add_argument("--eig-calc", type=int, default=3, help="24^3x48: eigSUMR calculating solves")
+    ap.add_argument("--c3-eta", type=float, default=3e-3, help="24^3x48: middle-solve accuracy eta~ of GMRESR")
+    ap.add_argument("--eig-calc", type=int, default=6, help="24^3x48: eigSUMR calculating solves")
     ap.add_argument("--eig-n", type=int, default=20, help="24^3x48: eigenvectors kept (n)")
-    ap.add_argument("--eig-m", type=int, default=60, help="24^3x48: basis size of Alg. 6 (m)")
+    ap.add_argument("--eig-m", type=int, default=100, help="24^3x48: basis size of Alg. 6 (m)")
     ap.add_argument("--eig-eps", type=float, default=1e-4, help="24^3x48: target eigenvector accuracy (Sec. 6)")
-    ap.add_argument("--adaptive-nz", action="store_true",
-                    help="24^3x48: Zolotarev order per sign call from its accuracy (Sec. 3)")
-    ap.add_argument("--bound-printed", action="store_true",
-                    help="24^3x48: eq. (bound) with chi on the square root only (as printed)")
+    ap.add_argument("--fixed-nz", action="store_true",
+                    help="24^3x48: every sign call with all 20 poles (default: the Zolotarev order per sign call "
+                         "from its accuracy, Sec. 3)")
+    ap.add_argument("--bound-text", action="store_true",
+                    help="24^3x48: eq. (bound) with chi scaling the whole bound (default: as printed, chi on the "
+                         "square root only)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware counters: a 1 GiB elementwise copy (calibration), one "
                          "sign-function call per precision on the 24^3x48 workload, the stand-alone 32^3x64 "
                          "stencil and the 12-field 24^3x48 stencil")
+    ap.add_argument("--sign-methods", action="store_true",
+                    help="add the comparison of the multi-shift CG and two-pass Lanczos sign functions")
     ap.add_argument("--eigcg", action="store_true",
                     help="add the GMRESR(eigCG) leg on 16^3x32 (calculating solves, then deflated solves)")
     ap.add_argument("--eigcg-calc", type=int, default=5, help="eigCG leg: calculating solves")
@@ -572,8 +576,8 @@ def c3_headline(torch, ovl, args, tuning):
     """Set-up, eigSUMR calculating solves, the timed deflated solves, the
     profiled replica and the comparison solves on 24^3 x 48."""
     ctx, zolo, B, setup = c3_setup(torch, ovl, tuning)
-    ctx.set_option(ovl.OPT_ADAPTIVE_NZ, 1 if args.adaptive_nz else 0)
-    ctx.set_option(ovl.OPT_BOUND_PRINTED, 1 if args.bound_printed else 0)
+    ctx.set_option(ovl.OPT_ADAPTIVE_NZ, 0 if args.fixed_nz else 1)
+    ctx.set_option(ovl.OPT_BOUND_PRINTED, 0 if args.bound_text else 1)
     n_calc = args.eig_calc
     # eigSUMR calculating solves (Alg. 5 collection at the stricter of the
     # inversion and Sec. 5.1 accuracies, Alg. 6, the three-set step at the end
@@ -633,7 +637,9 @@ def c3_headline(torch, ovl, args, tuning):
         "eigsumr": {"n_eig": args.eig_n, "m_eig": args.eig_m, "eig_eps": args.eig_eps, "calculating_solves": calc,
                     "calculating_seconds": t_calc, "recompute_fp64_seconds": t_recompute,
                     "diagonalisations": info["ndiag"], "ritz": ritz, "residuals": info["resid"],
-                    "bound": "printed (chi on the square root)" if args.bound_printed else "chi scales the bound"},
+                    "bound": "chi scales the bound" if args.bound_text else "as printed (chi on the square root)",
+                    "zolotarev_order": "20 in every sign call" if args.fixed_nz else
+                    "per sign call: the fewest poles n <= 20 with Delta(n) <= eta / 4 (Sec. 3)"},
         "steps": steps, "seconds_timed": t_total, "true_relres_last_step": res_last,
         "profiled_replica_seconds": dtp, "profiled_replica_stats": stp,
         "undeflated_mixed": {"median_seconds": t_und, "solves_per_s": 1.0 / t_und, "median_sumr_iters": it_und,
@@ -686,6 +692,41 @@ def c2_secondary(torch, ovl, args, tuning):
                                "note": "16^3x32: fields and links fit in the 256 MB Infinity Cache"},
            "tuning": ctx.tuning()}
     ctx.close()
+    return out
+
+
+def sign_methods_leg(torch, ovl, tuning=None):
+    """sign(K) psi in FP64 by the multi-shift CG over the 20 Zolotarev poles
+    and by the two-pass Lanczos method, on 16^3 x 32 (ten exact kernel modes)
+    and 24^3 x 48 (Lanczos interval), Gaussian source, at sign accuracies
+    1e-10 and 1e-4: wall time, steps, and the difference of the two results."""
+    out = {}
+    for name in ("16x16x16x32", "24x24x24x48"):
+        if name == "16x16x16x32":
+            ctx, zolo, b = setup_c2(ovl, tuning)
+        else:
+            ctx, zolo, _, _ = c3_setup(torch, ovl, tuning)
+            b = ctx.source(ovl.SRC_GAUSS, seed=102)
+        res = {}
+        for eta in (1e-10, 1e-4):
+            ctx.sign(b, RHO, zolo, eta)   # warm-up (launch tuning)
+            ctx.sign_lanczos(b, RHO, zolo, eta)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1, st1 = ctx.sign(b, RHO, zolo, eta)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s2, st2 = ctx.sign_lanczos(b, RHO, zolo, eta)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            diff = float(torch.linalg.vector_norm(s1 - s2) / torch.linalg.vector_norm(b))
+            res[f"{eta:g}"] = {"mscg": {"seconds": t1 - t0, "iterations": st1.mscg_iters,
+                                        "us_per_iteration": 1e6 * (t1 - t0) / max(1, st1.mscg_iters)},
+                               "lanczos": {"seconds": t2 - t1, "steps_first_pass": st2.mscg_iters,
+                                           "us_per_step_both_passes": 1e6 * (t2 - t1) / max(1, st2.mscg_iters)},
+                               "relative_difference": diff}
+        out[name] = res
+        ctx.close()
     return out
 
 
@@ -776,10 +817,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f16-storage/f32/f64",
         "data": "synthetic",
-        "config": {"workload": "overlap solve 24^3x48 (links exp(i 0.25 A), seed 3), rho=1.4, mu=0.01, N_Z=20 on "
-                               "the Lanczos interval of |K|, eigSUMR deflation with 20 eigenvectors, one spin-colour "
-                               "point source per step (cycling over the 12), mixed precision, GMRESR(relSUMR) to "
-                               "1e-10",
+        "config": {"workload": "overlap solve 24^3x48 (links exp(i 0.25 A), seed 3), rho=1.4, mu=0.01, Zolotarev "
+                               "sign function (" + ("20 poles" if args.fixed_nz else "at most 20 poles, order per call "
+                               "from its accuracy") + ") on the Lanczos interval of |K|, eigSUMR deflation with "
+                               f"{args.eig_n} eigenvectors (m={args.eig_m}, {args.eig_calc} calculating solves), one "
+                               "spin-colour point source per step (cycling over the 12), mixed precision, "
+                               f"GMRESR(relSUMR) to 1e-10 (middle solves to {args.c3_eta:g})",
                    "global_batch": 1, "lattice": C3_NAME, "parallelism": "single GPU"},
         "fp64_solves_per_s": f64["solves_per_s"] if f64 else None,
         "mixed_over_fp64": (value / f64["solves_per_s"]) if f64 else None,
@@ -807,6 +850,9 @@ def main():
         out["c1_plain_4c4"] = c1_leg(torch, ovl)
         out["adjoint"] = adjoint_leg(torch, ovl)
         print("[bench] 4^4 and adjoint legs done", file=sys.stderr, flush=True)
+    if args.sign_methods or args.extras:
+        out["sign_methods"] = sign_methods_leg(torch, ovl, tuning)
+        print("[bench] sign-function methods done", file=sys.stderr, flush=True)
     if args.eigcg:
         out["eigcg_16c32"] = eigcg_leg(torch, ovl, args.eigcg_calc)
     if args.eigsolve:

@@ -127,6 +127,15 @@ typedef struct {
                               diagonalises at m and after each middle solve, the
                               Sec. 5.1 bound caps the sign accuracy, and each middle
                               solve keeps the preconditioner it started with. */
+    int32_t eig_block;     /* with eig_calc (relSUMR middle solve): the nrhs
+                              right-hand sides are solved together and every
+                              field's Krylov vectors (q, U q) enter the one
+                              eigenspace (block eigSUMR); Alg. 6 then
+                              orthonormalises the basis canonically
+                              (eigenvectors of V^H V, directions below 1e-10 of
+                              the largest dropped) since Krylov sequences of
+                              related sources are nearly dependent.  0: calculating
+                              solves run one right-hand side after another. */
 } ovl_solver_params;
 
 typedef struct ovl_context ovl_context;
@@ -210,6 +219,20 @@ ovl_status ovl_lowmodes_get(ovl_context *ctx, double *evecs_dev);
 ovl_status ovl_sign_zolotarev_mscg(ovl_context *ctx, double rho, const ovl_zolo *zolo,
                                    const double *in_dev, double *out_dev, int32_t nrhs,
                                    double eta, int32_t prec, ovl_stats *stats_host);
+
+/* out = sign(K) in by the two-pass Lanczos method (the Lanczos approach to
+ * the sign function cited in Sec. 1 after eq. 4), FP64: the context's low
+ * modes exactly; on the rest, Lanczos on K^2 keeps only its tridiagonal
+ * matrix T in a first pass, stopping once lambda_max ||y_k - y_{k-10}|| <=
+ * eta ||in|| for y_k = ||in_perp|| T_k^{-1/2} e_1 (checked every ten steps),
+ * and a second pass regenerates the Lanczos vectors from the stored
+ * coefficients and sums them with weights y; the result is K times that sum.
+ * No rational approximation error: zolo is used for its interval only
+ * (zolo->a <= |lambda| <= zolo->b off the low modes; 0 < a < b).  stats_host
+ * (may be null): mscg_iters = Lanczos steps of the first pass, summed over
+ * the nrhs fields.  OVL_ERR_NOT_CONVERGED after 20000 steps. */
+ovl_status ovl_sign_lanczos(ovl_context *ctx, double rho, const ovl_zolo *zolo, const double *in_dev,
+                            double *out_dev, int32_t nrhs, double eta, ovl_stats *stats_host);
 
 /* out = D[mu] in (Sec. 1, eq. 1) with the sign function as above. */
 ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_zolo *zolo,

@@ -92,14 +92,27 @@ class Deflation:
         return (self.P @ alpha).reshape(self.shape), (self.DP @ alpha).reshape(self.shape)
 
 
-def rayleigh_ritz(V, VD, n, mu, delta):
+def rayleigh_ritz(V, VD, n, mu, delta, canonical=False, cut=1e-10):
     """Alg. 6 on the columns of V (basis) and VD (their images under D):
-    returns (v, vD, theta, C) with v = V C, vD = VD C, C = R^{-1} Y[:, :n]."""
+    returns (v, vD, theta, C) with v = V C, vD = VD C, C = R^{-1} Y[:, :n];
+    with canonical, R^{-1} is replaced by B = W_k diag(l_k^{-1/2}) over the
+    eigenpairs (l, W) of V^H V above cut times the largest (the basis of a
+    block collection, whose Krylov sequences are nearly dependent)."""
     E = V.conj().T @ V
     E = 0.5 * (E + E.conj().T)
+    N = V.shape[0]
+    if canonical:
+        lam, W = np.linalg.eigh(E)
+        keep = lam > cut * lam.max()
+        B = W[:, keep] / np.sqrt(lam[keep])
+        G5VD = (g5(VD.T.reshape((VD.shape[1], N // 12, 4, 3))).reshape(VD.shape[1], -1)).T
+        M = VD.conj().T @ VD + 2.0 * mu * delta * (V.conj().T @ G5VD)
+        G = B.conj().T @ (0.5 * (M + M.conj().T)) @ B
+        theta, Y = np.linalg.eigh(0.5 * (G + G.conj().T))
+        C = B @ Y[:, :n]
+        return V @ C, VD @ C, theta[:n], C
     L = np.linalg.cholesky(E)            # E = L L^H, R = L^H
     R = L.conj().T
-    N = V.shape[0]
     # gamma_5 in canonical layout: spins 2, 3 negated
     G5VD = (g5(VD.T.reshape((VD.shape[1], N // 12, 4, 3))).reshape(VD.shape[1], -1)).T
     M = VD.conj().T @ VD + 2.0 * mu * delta * (V.conj().T @ G5VD)
@@ -117,8 +130,9 @@ class EigSUMR:
 
     collect(q, u): v_k = q, v^D_k = (1 - mu)/2 u + (1 + mu)/2 q, u = U q."""
 
-    def __init__(self, n, m, mu, delta=0.1, eps=1e-4, krecalc=25):
+    def __init__(self, n, m, mu, delta=0.1, eps=1e-4, krecalc=25, canonical=False):
         assert m > n
+        self.canonical = canonical
         self.n, self.m, self.mu, self.delta = n, m, float(mu), float(delta)
         self.eps, self.krecalc = eps, krecalc
         self.V, self.VD = [], []
@@ -139,7 +153,8 @@ class EigSUMR:
         if len(self.V) <= self.n:
             return
         nprev = self.n if self.ndiag > 0 else 0
-        v, vD, theta, C = rayleigh_ritz(_mat(self.V), _mat(self.VD), self.n, self.mu, self.delta)
+        v, vD, theta, C = rayleigh_ritz(_mat(self.V), _mat(self.VD), self.n, self.mu, self.delta,
+                                        canonical=self.canonical)
         self.V = [v[:, i].reshape(self.shape) for i in range(self.n)]
         self.VD = [vD[:, i].reshape(self.shape) for i in range(self.n)]
         self.theta = theta

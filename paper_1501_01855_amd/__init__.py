@@ -69,7 +69,8 @@ class SolverParams(ctypes.Structure):
                 ("use_deflation", ctypes.c_int32), ("eig_calc", ctypes.c_int32),
                 ("n_eig", ctypes.c_int32), ("m_eig", ctypes.c_int32), ("k_recalc", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("eig_eps", ctypes.c_double),
-                ("delta_split", ctypes.c_double), ("middle_cg", ctypes.c_int32)]
+                ("delta_split", ctypes.c_double), ("middle_cg", ctypes.c_int32),
+                ("eig_block", ctypes.c_int32)]
 
 
 EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults", "ovl_device_bytes",
@@ -80,7 +81,8 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_eigspace_get", "ovl_eigspace_set", "ovl_eigspace_diagonalise", "ovl_eigspace_recompute",
            "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option",
            "ovl_sumr_gmresr_solve_many", "ovl_eigsumr_eigensolve", "ovl_wilson_dslash_noalloc",
-           "ovl_kernel_interval", "ovl_stream_bench", "ovl_eigspace_save", "ovl_eigspace_load"]
+           "ovl_kernel_interval", "ovl_stream_bench", "ovl_eigspace_save", "ovl_eigspace_load",
+           "ovl_sign_lanczos"]
 
 _lib = None
 
@@ -113,6 +115,7 @@ def lib():
         "ovl_lowmodes_get": ([P, P], I32),
         "ovl_sign_zolotarev_mscg": ([P, D, P, P, P, I32, D, I32, P], I32),
         "ovl_overlap_apply": ([P, D, D, P, P, P, I32, D, I32, P], I32),
+        "ovl_sign_lanczos": ([P, D, P, P, P, I32, D, P], I32),
         "ovl_overlap_adjoint": ([P, D, D, P, P, P, I32, D, I32, P, P, P], I32),
         "ovl_tuning_get": ([P, P, P, I32, P], I32),
         "ovl_tuning_set": ([P, P, P, I32], I32),
@@ -286,6 +289,15 @@ class Context:
                                                     _dev(out, (self.V, 4, 3), "out"),
                                                     self._nrhs(psi), float(eta), prec,
                                                     ctypes.byref(st)), allow)
+        return out, st
+
+    def sign_lanczos(self, psi, rho, zolo, eta):
+        """sign(K) psi by the two-pass Lanczos method (FP64); zolo gives the interval."""
+        out = torch.empty_like(psi)
+        st = Stats()
+        _check(lib().ovl_sign_lanczos(self._h, float(rho), ctypes.byref(zolo), _dev(psi, (self.V, 4, 3), "psi"),
+                                      _dev(out, (self.V, 4, 3), "out"), self._nrhs(psi), float(eta),
+                                      ctypes.byref(st)))
         return out, st
 
     def overlap(self, psi, rho, mu, zolo, eta, prec=F64):

@@ -14,7 +14,7 @@ SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libovl.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["context.hip", "dslash.hip", "blas.hip", "mscg.hip", "solver.hip", "zolo.cpp", "dense.cpp",
-           "gen.hip", "lowmodes.hip", "eigspace.hip", "adjoint.hip", "noalloc.hip", "stream.hip", "capi.hip"]
+           "gen.hip", "lowmodes.hip", "eigspace.hip", "adjoint.hip", "noalloc.hip", "stream.hip", "lanczos.hip", "capi.hip"]
 ARCH = os.environ.get("OVL_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -3,6 +3,7 @@
 // translation.  No exception crosses this boundary.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -317,6 +318,30 @@ ovl_status ovl_sign_zolotarev_mscg(ovl_context *ctx, double rho, const ovl_zolo 
     });
 }
 
+ovl_status ovl_sign_lanczos(ovl_context *ctx, double rho, const ovl_zolo *zolo, const double *in_dev,
+                            double *out_dev, int32_t nrhs, double eta, ovl_stats *stats_host)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(zolo != nullptr && zolo->a > 0.0 && zolo->b > zolo->a && std::isfinite(zolo->b), OVL_ERR_ARG,
+                    "need the interval 0 < a < b of |K| (zolo->a, zolo->b)");
+        OVL_REQUIRE(in_dev && out_dev && nrhs >= 1 && nrhs <= MAX_NRHS, OVL_ERR_ARG, "bad field arguments");
+        OVL_REQUIRE(std::isfinite(rho) && eta > 0.0 && eta < 1.0, OVL_ERR_ARG, "need finite rho and 0 < eta < 1");
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        ovl_stats st{};
+        const auto t0 = std::chrono::steady_clock::now();
+        const size_t FB = field_bytes(ctx->g, OVL_F64) * nrhs;
+        double2 *a = (double2 *)ctx->buf("api_a", FB);
+        double2 *b = (double2 *)ctx->buf("api_b", FB);
+        pack_spinor(*ctx, in_dev, a, nrhs, OVL_F64);
+        sign_lanczos(*ctx, rho, *zolo, a, b, nrhs, eta, 20000, &st);
+        unpack_spinor(*ctx, b, out_dev, nrhs, OVL_F64);
+        OVL_HIP(hipStreamSynchronize(ctx->stream));
+        st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats_host) *stats_host = st;
+    });
+}
+
 ovl_status ovl_overlap_apply(ovl_context *ctx, double rho, double mu, const ovl_zolo *zolo, const double *in_dev,
                              double *out_dev, int32_t nrhs, double eta, int32_t prec, ovl_stats *stats_host)
 {
@@ -384,9 +409,11 @@ ovl_status ovl_sumr_gmresr_solve(ovl_context *ctx, const ovl_zolo *zolo, const o
         OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
         const size_t FB = field_bytes(ctx->g, OVL_F64);
         if (stats_host) std::memset(stats_host, 0, sizeof(ovl_stats) * nrhs);
-        // calculating (eigSUMR) solves run one right-hand side after another;
-        // otherwise all right-hand sides are solved together
-        const int batch = p.eig_calc ? 1 : nrhs;
+        // calculating (eigSUMR / eigCG) solves run one right-hand side after
+        // another unless they collect as a block; otherwise all right-hand
+        // sides are solved together
+        OVL_REQUIRE(!(p.eig_block && p.middle_cg), OVL_ERR_UNSUPPORTED, "block collection needs the relSUMR middle solve");
+        const int batch = (p.eig_calc && !p.eig_block) ? 1 : nrhs;
         double2 *b = (double2 *)ctx->buf("api_b64", FB * batch);
         double2 *x = (double2 *)ctx->buf("api_x64", FB * batch);
         for (int f0 = 0; f0 < nrhs; f0 += batch) {

@@ -28,6 +28,7 @@ struct EigSpace {
     double mu = -1.0, delta = 0.1, eps = 1e-4;
     int krecalc = 25;
     bool bound_printed = false;   // eq. (bound) with chi on the square root only (measurement option)
+    bool canonical = false;       // Alg. 6 orthonormalises canonically (block collection)
     double2 *V = nullptr, *VD = nullptr;   // [m] packed FP64 fields each
     int ndiag = 0;
     int nsets = 0;   // eigenvector sets kept from earlier eigensolver restarts (0..2)

@@ -774,27 +774,146 @@ __device__ __forceinline__ void ld_nbr(const ST *in, const float *sc, int64_t V,
     unpack(r, v);
 }
 
-template <int MU, typename ST, typename GT>
+// A link as stored (the planes ld_link reads), for staging in LDS: FP32 as
+// four float4 and one float2, FP16 as two uint4 and one uint32.
+template <typename GT>
+struct LinkRaw;
+template <>
+struct LinkRaw<float2> {
+    float4 q[4];
+    float2 r;
+};
+template <>
+struct LinkRaw<__half2> {
+    uint4 q[2];
+    uint32_t r;
+};
+__device__ __forceinline__ void ld_link_raw(const float2 *__restrict__ U, int64_t P, int mu, int64_t s,
+                                            LinkRaw<float2> &l)
+{
+    const float4 *Q = reinterpret_cast<const float4 *>(U);
+    const float2 *R = reinterpret_cast<const float2 *>(Q + 16 * P);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) l.q[k] = Q[(mu * 4 + k) * P + s];
+    l.r = R[mu * P + s];
+}
+__device__ __forceinline__ void ld_link_raw(const __half2 *__restrict__ U, int64_t P, int mu, int64_t s,
+                                            LinkRaw<__half2> &l)
+{
+    const uint4 *Q = reinterpret_cast<const uint4 *>(U);
+    const uint32_t *R = reinterpret_cast<const uint32_t *>(Q + 8 * P);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) l.q[k] = Q[(mu * 2 + k) * P + s];
+    l.r = R[mu * P + s];
+}
+// the values ld_link returns for the same stored link
+__device__ __forceinline__ void unpack_link(const LinkRaw<float2> &l, cplx<float> u[9])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        u[2 * k] = {l.q[k].x, l.q[k].y};
+        u[2 * k + 1] = {l.q[k].z, l.q[k].w};
+    }
+    u[8] = {l.r.x, l.r.y};
+}
+__device__ __forceinline__ void unpack_link(const LinkRaw<__half2> &l, cplx<float> u[9])
+{
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const uint4 q = l.q[k];
+        const float2 a = h2f2(q.x), b = h2f2(q.y), c = h2f2(q.z), d = h2f2(q.w);
+        u[4 * k] = {a.x, a.y};
+        u[4 * k + 1] = {b.x, b.y};
+        u[4 * k + 2] = {c.x, c.y};
+        u[4 * k + 3] = {d.x, d.y};
+    }
+    const float2 r = h2f2(l.r);
+    u[8] = {r.x, r.y};
+}
+// The forward links of NLD spatial directions for the tile's sites at the
+// current slice, plane by plane (lane-consecutive words, no bank conflicts):
+// FP16 stages x, y, z (27 KB), FP32 x, y (36 KB beside the 24 KB of spinors).
+template <typename GT, int NLD>
+struct LinkLds {
+    using QT = typename std::remove_reference<decltype(LinkRaw<GT>{}.q[0])>::type;
+    using RT = decltype(LinkRaw<GT>{}.r);
+    static constexpr int NQ = sizeof(LinkRaw<GT>{}.q) / sizeof(QT);
+    QT q[NLD][NQ][LDS_SITES];
+    RT r[NLD][LDS_SITES];
+    __device__ __forceinline__ void put(int mu, int lane, const LinkRaw<GT> &l)
+    {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) q[mu][k][lane] = l.q[k];
+        r[mu][lane] = l.r;
+    }
+    __device__ __forceinline__ void get(int mu, int lane, cplx<float> u[9]) const
+    {
+        LinkRaw<GT> l;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) l.q[k] = q[mu][k][lane];
+        l.r = r[mu][lane];
+        unpack_link(l, u);
+    }
+};
+
+// A link through one generic pointer pair: planes q[k * qs] and the last
+// entry *r, in LDS (qs = LDS_SITES) or in memory (qs = the plane stride).
+template <typename GT>
+__device__ __forceinline__ void ld_link_at(const typename LinkLds<GT, 1>::QT *q, int64_t qs,
+                                           const typename LinkLds<GT, 1>::RT *r, cplx<float> u[9])
+{
+    LinkRaw<GT> l;
+#pragma unroll
+    for (int k = 0; k < LinkLds<GT, 1>::NQ; ++k) l.q[k] = q[k * qs];
+    l.r = *r;
+    unpack_link(l, u);
+}
+
+// One spatial direction of the LDS-tiled stencil.  With Lu (links staged in
+// LDS for this direction) the own forward link and, for a neighbour inside the
+// tile, the backward neighbour's forward link U_mu(x - mu) come from LDS; the
+// choice is a pointer, not a branch (as for the neighbour spinors).
+template <int MU, bool USEL, typename ST, typename GT, typename LL>
 __device__ __forceinline__ void tile_dir(const ST *in, const float *sc, const GT *__restrict__ U, int64_t V,
                                          int64_t Pu, int64_t s, int32_t c, int32_t Lm, int64_t st, int tid, int lstep,
-                                         bool fin, bool bin, const ST *Lsp, const float *Lsc, cplx<float> acc[12])
+                                         bool fin, bool bin, const ST *Lsp, const float *Lsc, const LL *Lu,
+                                         cplx<float> acc[12])
 {
     cplx<float> v[12], u[9];
     const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st : s + st;
     const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st : s - st;
     ld_nbr(in, sc, V, fwd, fin, Lsp, Lsc, tid + lstep, v);
-    ld_link(U, Pu, MU, s, u);
+    if constexpr (USEL)
+        ld_link_at<GT>(&Lu->q[MU][0][tid], LDS_SITES, &Lu->r[MU][tid], u);
+    else
+        ld_link(U, Pu, MU, s, u);
     hop_term<MU, true>(v, u, acc);
     ld_nbr(in, sc, V, bwd, bin, Lsp, Lsc, tid - lstep, v);
-    ld_link(U, Pu, MU, bwd, u);
+    if constexpr (USEL) {
+        using QT = typename LinkLds<GT, 1>::QT;
+        using RT = typename LinkLds<GT, 1>::RT;
+        constexpr int NQ = LinkLds<GT, 1>::NQ;
+        const QT *Qg = reinterpret_cast<const QT *>(U);
+        const RT *Rg = reinterpret_cast<const RT *>(Qg + 4 * NQ * Pu);
+        const QT *q = bin ? &Lu->q[MU][0][tid - lstep] : Qg + (int64_t)MU * NQ * Pu + bwd;
+        const RT *r = bin ? &Lu->r[MU][tid - lstep] : Rg + (int64_t)MU * Pu + bwd;
+        ld_link_at<GT>(q, bin ? (int64_t)LDS_SITES : Pu, r, u);
+    } else {
+        ld_link(U, Pu, MU, bwd, u);
+    }
     hop_term<MU, false>(v, u, acc);
 }
 
-template <typename ST, typename GT, int EPI>
-__global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT *__restrict__ U, TileShape ts)
+template <typename ST, typename GT, int EPI, bool LINKS>
+__device__ __forceinline__ void stencil_lds_body(const StencilArgs<ST> &a, const GT *__restrict__ U,
+                                                 const TileShape &ts)
 {
     __shared__ ST Lsp[Planes<ST>::n * LDS_SITES];   // the tile's stored spinors at the current slice
     __shared__ float Lsc[LDS_SITES];                 // their scales (FP16 storage; unused otherwise)
+    constexpr int NLD = std::is_same<GT, __half2>::value ? 3 : 2;   // spatial directions with staged links
+    using LL = LinkLds<GT, NLD>;
+    __shared__ typename std::conditional<LINKS, LL, char>::type Lu_store;
+    LL *Lu = LINKS ? reinterpret_cast<LL *>(&Lu_store) : nullptr;
     const Geom &g = a.g;
     const unsigned X = gridDim.x, Y = gridDim.y;
     const unsigned lin = blockIdx.y * X + blockIdx.x;
@@ -850,14 +969,25 @@ __global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT
         const int t = t0 + j;
         const int64_t s = xyz + (int64_t)t * S3;
         if (valid) st_raw(Lsp + tid, Lsc + tid, LDS_SITES, cur);
+        if constexpr (LINKS) {
+            if (valid)
+#pragma unroll
+                for (int mu = 0; mu < NLD; ++mu) {
+                    LinkRaw<GT> l;
+                    ld_link_raw(U, Pu, mu, s, l);
+                    Lu->put(mu, tid, l);
+                    asm volatile("" ::: "memory");   // one direction's link in registers at a time
+                }
+        }
         __syncthreads();
         if (valid) {
             cplx<float> acc[12];
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
-            tile_dir<0>(in, sc, U, V, Pu, s, co[0], g.L[0], g.stride[0], tid, 1, f0, k0, Lsp, Lsc, acc);
-            tile_dir<1>(in, sc, U, V, Pu, s, co[1], g.L[1], g.stride[1], tid, b0, f1, k1, Lsp, Lsc, acc);
-            tile_dir<2>(in, sc, U, V, Pu, s, co[2], g.L[2], g.stride[2], tid, b0 * b1, f2, k2, Lsp, Lsc, acc);
+            tile_dir<0, LINKS>(in, sc, U, V, Pu, s, co[0], g.L[0], g.stride[0], tid, 1, f0, k0, Lsp, Lsc, Lu, acc);
+            tile_dir<1, LINKS>(in, sc, U, V, Pu, s, co[1], g.L[1], g.stride[1], tid, b0, f1, k1, Lsp, Lsc, Lu, acc);
+            tile_dir<2, LINKS && (NLD > 2)>(in, sc, U, V, Pu, s, co[2], g.L[2], g.stride[2], tid, b0 * b1, f2, k2,
+                                            Lsp, Lsc, Lu, acc);
             const int64_t sp = t == Lt - 1 ? s - (int64_t)(Lt - 1) * S3 : s + S3;
             SpRaw<ST> nr;
             ld_raw_site(in, sc, V, sp, nr);
@@ -879,6 +1009,20 @@ __global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT
     store_partials<ST, EPI>(a, f, tile, part);
 }
 
+template <typename ST, typename GT, int EPI, bool LINKS>
+__global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT *__restrict__ U, TileShape ts)
+{
+    stencil_lds_body<ST, GT, EPI, LINKS>(a, U, ts);
+}
+// with the links staged: registers held to two waves per SIMD (the LDS of
+// two blocks fits a compute unit)
+template <typename ST, typename GT, int EPI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_stencil_ldsl(
+    StencilArgs<ST> a, const GT *__restrict__ U, TileShape ts)
+{
+    stencil_lds_body<ST, GT, EPI, true>(a, U, ts);
+}
+
 // Launch shape chosen per (precision, epilogue, nf) by timing the variants on
 // the context's lattice the first time that shape is used (autotuning).
 // Launch variants: 0 / 1 one lane per site, MAP_LEX / MAP_REMAP; 2 / 3 two
@@ -888,8 +1032,11 @@ __global__ __launch_bounds__(256) void k_stencil_lds(StencilArgs<ST> a, const GT
 // LDS-tiled march with T = 1, 2, 4, 8 time slices per block (Lt a multiple of
 // T; FP32 and FP16 storage).  12 .. 15 the grouped XCD order MAP_GRP32 /
 // MAP_GRP64 with one / two lanes per site (12: G 32, one lane; 13: G 32, two;
-// 14: G 64, one; 15: G 64, two).
-static constexpr int N_VARIANTS = 16;
+// 14: G 64, one; 15: G 64, two).  16 .. 19 the LDS-tiled march (T = 1, 2, 4,
+// 8) with the tile's forward spatial links also staged in LDS, so that the
+// backward hop of a site inside the tile reads its neighbour's link there.
+static constexpr int N_VARIANTS = 20;
+static bool variant_lds(int v) { return (v >= 8 && v < 12) || v >= 16; }
 static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7 || v == 13 || v == 15) ? 2 : 1; }
 
 // Tile of the LDS-tiled march: the 256-site box with the fewest padded sites,
@@ -916,7 +1063,7 @@ static TileShape tile_shape(const Geom &g, int v)
             }
         }
     }
-    ts.T = 1 << (v - 8);
+    ts.T = 1 << (v >= 16 ? v - 16 : v - 8);
     ts.nch = g.L[3] / ts.T;
     return ts;
 }
@@ -925,8 +1072,8 @@ unsigned stencil_tiles(const Geom &g, int v)
 {
     const int tps = variant_tps(v);
     const int spb = 256 / tps;
-    if (v >= 12) return 8u * (unsigned)(((g.V + spb - 1) / spb + 7) / 8);   // 8 XCDs x their largest share
-    if (v >= 8) {
+    if (v >= 12 && v < 16) return 8u * (unsigned)(((g.V + spb - 1) / spb + 7) / 8);   // 8 XCDs x their largest share
+    if (variant_lds(v)) {
         const TileShape ts = tile_shape(g, v);
         return (unsigned)(ts.n[0] * ts.n[1] * ts.n[2] * ts.nch);
     }
@@ -940,7 +1087,7 @@ bool stencil_variant_ok(const Geom &g, int prec, int v)
     if (v < 0 || v >= N_VARIANTS) return false;
     if ((v == 4 || v == 5) && !g.col_ok) return false;
     if ((v == 6 || v == 7) && g.L[3] % 8 != 0) return false;
-    if (v >= 8 && v < 12) return prec != OVL_F64 && g.L[3] % (1 << (v - 8)) == 0;
+    if (variant_lds(v)) return prec != OVL_F64 && g.L[3] % (1 << (v >= 16 ? v - 16 : v - 8)) == 0;
     return true;
 }
 
@@ -976,7 +1123,10 @@ static void launch_lds(Context &c, int v, const StencilArgs<ST> &a, const GT *U,
 {
     const TileShape ts = tile_shape(c.g, v);
     dim3 grid(stencil_tiles(c.g, v), nf);
-    launch_k(c, pe, k_stencil_lds<ST, GT, EPI>, grid, dim3(256), 0, a, U, ts);
+    if (v >= 16)
+        launch_k(c, pe, k_stencil_ldsl<ST, GT, EPI>, grid, dim3(256), 0, a, U, ts);
+    else
+        launch_k(c, pe, k_stencil_lds<ST, GT, EPI, false>, grid, dim3(256), 0, a, U, ts);
 }
 
 template <typename ST, typename GT, int EPI>
@@ -984,7 +1134,7 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
                          const PendingEvent *pe = nullptr)
 {
     if constexpr (!std::is_same<ST, double2>::value) {   // FP32 math only
-        if (id >= 8 && id < 12) {
+        if (variant_lds(id)) {
             launch_lds<ST, GT, EPI>(c, id, a, U, nf, pe);
             return;
         }

@@ -65,6 +65,7 @@ void eig_configure(Context &c, int n, int m, double mu, double delta, double eps
     e.delta = delta;
     e.eps = eps;
     e.krecalc = krecalc;
+    e.canonical = false;   // a block-collecting solve turns it on after configuring
 }
 
 // Alg. 5: v_k = q, v^D_k = (1 - mu)/2 u + (1 + mu)/2 q, with u = U q.
@@ -115,24 +116,43 @@ void eig_diagonalise(Context &c)
     const std::vector<zc> MD = to_z(g);
     gram_f64(c, e.V, k, e.VD, k, true, g);
     const std::vector<zc> G5M = to_z(g);
-    std::vector<zc> R;
-    OVL_REQUIRE(dense::cholesky_upper(k, E, R), OVL_ERR_BREAKDOWN,
-                "eigSUMR: basis lost linear independence (Cholesky of V^H V failed)");
-    const std::vector<zc> Rinv = dense::inv_upper(k, R);
     std::vector<zc> M(k * k);
     const double s = 2.0 * e.mu * e.delta;
     for (int i = 0; i < k * k; ++i) M[i] = MD[i] + s * G5M[i];
-    // G = R^{-H} M R^{-1}
-    const std::vector<zc> MR = dense::matmul(k, k, k, M, Rinv);
-    const std::vector<zc> G = dense::matmul_ah(k, k, k, Rinv, MR);
+    // B with B^H (V^H V) B = 1: R^{-1} from Cholesky V^H V = R^H R, or, for a
+    // block collection whose Krylov sequences are nearly dependent, canonically
+    // W_k diag(l_k^{-1/2}) over the eigenpairs of V^H V above 1e-10 of the largest
+    std::vector<zc> B;
+    int nb = k;
+    if (!e.canonical) {
+        std::vector<zc> R;
+        OVL_REQUIRE(dense::cholesky_upper(k, E, R), OVL_ERR_BREAKDOWN,
+                    "eigSUMR: basis lost linear independence (Cholesky of V^H V failed)");
+        B = dense::inv_upper(k, R);
+    } else {
+        std::vector<double> lam;
+        std::vector<zc> W;
+        dense::eigh(k, E, lam, W);
+        std::vector<int> keep;
+        for (int j = 0; j < k; ++j)
+            if (lam[j] > 1e-10 * lam.back()) keep.push_back(j);
+        nb = (int)keep.size();
+        OVL_REQUIRE(nb >= n, OVL_ERR_BREAKDOWN, "eigSUMR: fewer independent directions than wanted eigenvectors");
+        B.assign((size_t)k * nb, 0.0);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < nb; ++j) B[(size_t)i * nb + j] = W[(size_t)i * k + keep[j]] / std::sqrt(lam[keep[j]]);
+    }
+    // G = B^H M B
+    const std::vector<zc> MB = dense::matmul(k, k, nb, M, B);
+    const std::vector<zc> G = dense::matmul_ah(k, nb, nb, B, MB);
     std::vector<double> th;
     std::vector<zc> Y;
-    dense::eigh(k, G, th, Y);
-    // C = R^{-1} Y[:, :n]  (k x n)
-    std::vector<zc> Yn((size_t)k * n);
-    for (int i = 0; i < k; ++i)
-        for (int j = 0; j < n; ++j) Yn[(size_t)i * n + j] = Y[(size_t)i * k + j];
-    const std::vector<zc> C = dense::matmul(k, k, n, Rinv, Yn);
+    dense::eigh(nb, G, th, Y);
+    // C = B Y[:, :n]  (k x n)
+    std::vector<zc> Yn((size_t)nb * n);
+    for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < n; ++j) Yn[(size_t)i * n + j] = Y[(size_t)i * nb + j];
+    const std::vector<zc> C = dense::matmul(k, nb, n, B, Yn);
     // rotation magnitude of the new Krylov vectors into the eigenvectors
     const int nprev = e.ndiag > 0 ? n : 0;
     double uv = 0.0;

@@ -177,10 +177,92 @@ void lowmodes_compute(Context &c, double rho, int n_low, double tol, double *eva
 
 namespace ovl {
 
+// Symmetric tridiagonal T (diagonal a[0..n), off-diagonal b[0..n-1)): the
+// number of eigenvalues below x by the Sturm sequence of the LDL^T pivots.
+static int sturm_below(const std::vector<double> &a, const std::vector<double> &b, int n, double x)
+{
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < n; ++i) {
+        d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// The k-th smallest eigenvalue of T by bisection inside its Gershgorin bounds.
+static double tri_eig(const std::vector<double> &a, const std::vector<double> &b, int n, int k)
+{
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_below(a, b, n, mid) > k) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// |last component| of the unit eigenvector of T for eigenvalue th, by two
+// steps of inverse iteration (tridiagonal solves with partial pivoting).
+static double tri_evec_last(const std::vector<double> &a, const std::vector<double> &b, int n, double th)
+{
+    std::vector<double> y(n, 1.0 / std::sqrt((double)n));
+    const double shift = th * (1.0 - 1e-13) - 1e-300;
+    for (int pass = 0; pass < 2; ++pass) {
+        // Gaussian elimination on (T - shift) z = y, rows i, i+1 swapped when needed
+        std::vector<double> d(n), u(n, 0.0), w(n, 0.0), r = y;
+        for (int i = 0; i < n; ++i) d[i] = a[i] - shift;
+        std::vector<double> lo(n > 0 ? n - 1 : 0);
+        for (int i = 0; i + 1 < n; ++i) {
+            u[i] = b[i];
+            lo[i] = b[i];
+        }
+        // U has diagonal d, superdiagonals u, w (from pivoting)
+        for (int i = 0; i + 1 < n; ++i) {
+            if (std::fabs(lo[i]) > std::fabs(d[i])) {   // swap rows i and i+1
+                std::swap(d[i], lo[i]);
+                const double t1 = u[i];
+                u[i] = d[i + 1];
+                d[i + 1] = t1;
+                if (i + 2 < n) {
+                    w[i] = u[i + 1];
+                    u[i + 1] = 0.0;
+                }
+                std::swap(r[i], r[i + 1]);
+            }
+            const double m = d[i] != 0.0 ? lo[i] / d[i] : 0.0;
+            d[i + 1] -= m * u[i];
+            if (i + 2 < n) u[i + 1] -= m * w[i];
+            r[i + 1] -= m * r[i];
+        }
+        std::vector<double> z(n);
+        for (int i = n - 1; i >= 0; --i) {
+            double t = r[i];
+            if (i + 1 < n) t -= u[i] * z[i + 1];
+            if (i + 2 < n) t -= w[i] * z[i + 2];
+            z[i] = t / (d[i] != 0.0 ? d[i] : 1e-300);
+        }
+        double nn = 0.0;
+        for (double v : z) nn += v * v;
+        nn = std::sqrt(nn);
+        for (int i = 0; i < n; ++i) y[i] = z[i] / nn;
+    }
+    return std::fabs(y[n - 1]);
+}
+
 // Ends of the spectrum of K^2 by Lanczos (FP64, one vector, no
 // re-orthogonalisation: the extreme Ritz values converge regardless, and
 // the smallest one decreases monotonically towards lambda_min^2).  Set-up
 // for the Zolotarev interval when no kernel modes are treated exactly.
+// Every ten steps the extreme eigenvalues of the tridiagonal matrix are
+// found by bisection; the run stops when the smallest has moved by less than
+// 1e-10 (relative) over two such checks.
 void kernel_interval(Context &c, double rho, int max_iter, double *lmin, double *lmin_err, double *lmax)
 {
     const Geom &g = c.g;
@@ -197,7 +279,7 @@ void kernel_interval(Context &c, double rho, int max_iter, double *lmin, double 
     lincomb3_f64(c, 1.0 / std::sqrt(n2[0]), t, 0.0, t, 0.0, nullptr, v, 1);
     zero_fields(c, vp, 1, OVL_F64);   // read (times 0) by the first step
     std::vector<double> alpha, beta;   // T = tridiag(beta, alpha, beta)
-    double bprev = 0.0, th_min = 0.0, th_max = 0.0, err = 0.0, last = -1.0;
+    double bprev = 0.0, th_min = 0.0, th_max = 0.0, last = -1.0;
     int stable = 0;
     for (int j = 0; j < max_iter; ++j) {
         stencil(c, EPI_K, OVL_F64, v, t, 1, rho, 0.0, nullptr, nullptr);
@@ -212,17 +294,8 @@ void kernel_interval(Context &c, double rho, int max_iter, double *lmin, double 
         beta.push_back(b);
         const int n = (int)alpha.size();
         if (n % 10 == 0 || j == max_iter - 1 || b == 0.0) {
-            std::vector<dense::zc> T((size_t)n * n, 0.0);
-            for (int i = 0; i < n; ++i) {
-                T[(size_t)i * n + i] = alpha[i];
-                if (i + 1 < n) T[(size_t)i * n + i + 1] = T[(size_t)(i + 1) * n + i] = beta[i];
-            }
-            std::vector<double> th;
-            std::vector<dense::zc> Y;
-            dense::eigh(n, T, th, Y);
-            th_min = th[0];
-            th_max = th[n - 1];
-            err = std::abs(b * Y[(size_t)(n - 1) * n + 0]);   // |beta_n y_n| of the smallest Ritz pair
+            th_min = tri_eig(alpha, beta, n, 0);
+            th_max = tri_eig(alpha, beta, n, n - 1);
             if (last > 0.0 && std::fabs(last - th_min) <= 1e-10 * th_min) ++stable;
             else stable = 0;
             last = th_min;
@@ -233,8 +306,9 @@ void kernel_interval(Context &c, double rho, int max_iter, double *lmin, double 
         bprev = b;
     }
     OVL_HIP(hipStreamSynchronize(c.stream));
+    const int n = (int)alpha.size();
     *lmin = std::sqrt(std::max(th_min, 0.0));
-    if (lmin_err) *lmin_err = err;
+    if (lmin_err) *lmin_err = beta[n - 1] * tri_evec_last(alpha, beta, n, th_min);   // |beta_n y_n|
     if (lmax) *lmax = std::sqrt(std::max(th_max, 0.0));
 }
 

@@ -27,6 +27,11 @@ void overlap_adjoint(Context &c, double rho, double mu, const ovl_zolo &z, const
 void overlap_f64(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in,
                  double2 *out, int nf, double eta, int prec, int maxiter, ovl_stats *st);
 
+// sign(K) in -> out (packed FP64, nf fields) by the two-pass Lanczos method;
+// z gives the interval [a, b] of |K| off the low modes (lanczos.hip).
+void sign_lanczos(Context &c, double rho, const ovl_zolo &z, const double2 *in, double2 *out, int nf, double eta,
+                  int maxiter, ovl_stats *st);
+
 // Zolotarev coefficients (zolo.cpp).
 void zolotarev(int nz, double a, double b, ovl_zolo &out);
 

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_sumr_step(SumrCoef k, double2 *__restri
 static void norms(Context &c, const double2 *x, int nf, std::vector<double> &out)
 {
     norm2_f64(c, x, nf, out);
-    for (auto &v : out) v = std::sqrt(std::max(0.0, v));
+    for (auto &v : out) v = std::isnan(v) ? v : std::sqrt(std::max(0.0, v));   // a NaN stays visible
 }
 
 static void dots(Context &c, const double2 *x, const double2 *y, int nf, std::vector<zc> &out)
@@ -272,9 +272,9 @@ struct SumrField {
 // relSUMR for (1 + rho U) x_f = bp_f on the fields with mask[f], x holding x0
 // (zero when x_zero).  Ax0 (nullable) holds (1 + rho U) x0 when the caller
 // knows it (the deflated start supplies it from the stored D psi', Sec. 4),
-// which saves a sign call.  collect (one field only): feed every (q, U q) to
-// eigSUMR (Alg. 5) and use the stricter of the inversion and eigenvector sign
-// accuracies (Sec. 5.1).
+// which saves a sign call.  collect: feed every active field's (q, U q) to
+// eigSUMR (Alg. 5; several fields only in block collection) and use the
+// stricter of the inversion and eigenvector sign accuracies (Sec. 5.1).
 static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, double rhoK, double rho,
                  const double2 *bp, double2 *x, int nf, const std::vector<int> &mask, bool x_zero,
                  const double2 *Ax0, double tol, double epsA, bool collect, ovl_stats *st)
@@ -387,7 +387,9 @@ static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, do
         if (nact == 0) break;
         for (int f = 0; f < nf; ++f) eta[f] = F[f].active ? eta_for(F[f]) : 0.0;
         unitary_f64(c, rhoK, z, q, u, nf, eta.data(), prm, st);
-        if (collect) eig_collect(c, q, u);
+        if (collect)   // Alg. 5: every active field's (q, U q); one field unless collecting as a block
+            for (int f = 0; f < nf; ++f)
+                if (F[f].active) eig_collect(c, q + (size_t)f * n, u + (size_t)f * n);
         std::vector<zc> g;
         dots(c, qt, u, nf, g);
         SumrCoef k{};
@@ -589,8 +591,8 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
                        int nf, ovl_stats *st)
 {
     OVL_REQUIRE(nf >= 1 && nf <= MAXF, OVL_ERR_ARG, "too many right-hand sides in one batch");
-    OVL_REQUIRE(!(prm.eig_calc && nf > 1), OVL_ERR_ARG,
-                "eigSUMR collects from one right-hand side at a time (solve calculating right-hand sides singly)");
+    OVL_REQUIRE(!(prm.eig_calc && nf > 1 && !prm.eig_block), OVL_ERR_ARG,
+                "without eig_block, eigSUMR collects from one right-hand side at a time");
     const auto t0 = std::chrono::steady_clock::now();
     const double mu = prm.mu;
     const double rhoK = prm.rho;
@@ -605,7 +607,10 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
 
     zero_fields(c, x, nf, OVL_F64);
     copy_fields(c, b, r, nf, OVL_F64);
-    if (prm.eig_calc) eig_configure(c, prm.n_eig, prm.m_eig, mu, prm.delta_split, prm.eig_eps, prm.k_recalc);
+    if (prm.eig_calc) {
+        eig_configure(c, prm.n_eig, prm.m_eig, mu, prm.delta_split, prm.eig_eps, prm.k_recalc);
+        c.eig.canonical = prm.eig_block != 0;
+    }
     std::vector<double> bn, rn;
     norms(c, b, nf, bn);
     for (int f = 0; f < nf; ++f)

@@ -278,3 +278,57 @@ class _NoRelaxDivisor(eig.EigSUMR):
 def test_new_vector_errors_reject_planted(tiny):
     ratios = _new_vector_error(tiny, _NoRelaxDivisor(6, 24, MU, eps=1e-4, krecalc=25))
     assert max(ratios) > 1.0
+
+
+# --- block collection (several right-hand sides' Krylov vectors, one Alg. 6) ----
+
+
+def test_canonical_rayleigh_ritz_on_dependent_basis(tiny):
+    """With an exactly repeated direction V^H V is singular (Cholesky fails);
+    the canonical orthonormalisation gives the Ritz pairs of the basis
+    without the repeats."""
+    rng = np.random.default_rng(2)
+    idx = np.argsort(np.abs(tiny["h"]))[:6]
+    V = tiny["Y"][:, idx] @ (rng.normal(size=(6, 6)) + 1j * rng.normal(size=(6, 6)))
+    V2 = np.concatenate([V, V[:, :3]], axis=1)
+    with pytest.raises(np.linalg.LinAlgError):
+        eig.rayleigh_ritz(V2, tiny["D"] @ V2, 4, MU, 0.1)
+    _, _, th, _ = eig.rayleigh_ritz(V, tiny["D"] @ V, 4, MU, 0.1)
+    v2, vD2, th2, _ = eig.rayleigh_ritz(V2, tiny["D"] @ V2, 4, MU, 0.1, canonical=True)
+    assert np.allclose(th2, th, atol=1e-12)
+    assert np.allclose(vD2, tiny["D"] @ v2, atol=1e-10)
+    assert np.allclose(v2.conj().T @ v2, np.eye(4), atol=1e-10)
+
+
+def _krylov_pairs(tiny, b, steps):
+    """The Alg. 1 basis (q, U q) of `steps` SUMR iterations with the exact U."""
+    S = tiny["G5"] @ (2.0 * tiny["D"] - (1 + MU) * np.eye(tiny["D"].shape[0])) / (1 - MU)
+    pairs = []
+    krylov.sumr(lambda v, eta: g5((S @ v.reshape(-1)).reshape(v.shape)), (1 - MU) / (1 + MU),
+                (2.0 / (1 + MU)) * b, 1e-300, maxiter=steps,
+                on_step=lambda q, u: pairs.append((q.copy(), 0.5 * (1 - MU) * u + 0.5 * (1 + MU) * q)))
+    return pairs
+
+
+def test_block_collection_ritz_values_interlace(tiny):
+    """Krylov vectors of two right-hand sides in one basis: each of the n lowest
+    Ritz values of M over the union is at most the same Ritz value over either
+    sequence alone (Courant-Fischer on nested subspaces), and with exact images
+    the Ritz pairs are exact Rayleigh-Ritz pairs of gamma_5 D."""
+    pa = _krylov_pairs(tiny, synth.z2_source(tiny["dims"], 90), 14)
+    pb = _krylov_pairs(tiny, synth.z2_source(tiny["dims"], 91), 14)
+    n = 5
+
+    def ritz(pairs):
+        V = eig._mat([p[0] for p in pairs])
+        VD = eig._mat([p[1] for p in pairs])
+        return eig.rayleigh_ritz(V, VD, n, MU, 0.1, canonical=True)
+    _, _, ta, _ = ritz(pa)
+    _, _, tb, _ = ritz(pb)
+    v, vD, tab, _ = ritz(pa + pb)
+    assert np.all(tab <= ta + 1e-12) and np.all(tab <= tb + 1e-12)
+    assert np.allclose(vD, tiny["D"] @ v, atol=1e-10)
+    for i in range(n):
+        hv = np.vdot(v[:, i], tiny["G5"] @ vD[:, i]).real
+        r = np.linalg.norm(tiny["G5"] @ vD[:, i] - hv * v[:, i])
+        assert np.min(np.abs(tiny["h"] - hv)) <= r + 1e-12
