@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison solves on 24^3x48")
     ap.add_argument("--headline-only", action="store_true",
-                    help="only the 24^3x48 headline and its comparison solves (for kernel traces)")
+                    help="only the 24^3x48 headline and its comparison solves, plus the legs other flags ask for "
+                         "(no CPU baseline)")
     ap.add_argument("--extras", action="store_true",
                     help="add the 24 uneven instances, the 4^4 plain method and the adjoint legs")
     ap.add_argument("--batch12", action="store_true",
@@ -79,6 +80,9 @@ def parse():
                     help="short run for hardware counters: a 1 GiB elementwise copy (calibration), one "
                          "sign-function call per precision on the 24^3x48 workload, the stand-alone 32^3x64 "
                          "stencil and the 12-field 24^3x48 stencil")
+    ap.add_argument("--variant-sweep", action="store_true",
+                    help="only: time every stencil launch variant on the 12-field 24^3x48 and 1-field 32^3x64 "
+                         "stencils (also the hardware-counter run for them)")
     ap.add_argument("--sign-methods", action="store_true",
                     help="add the comparison of the multi-shift CG and two-pass Lanczos sign functions")
     ap.add_argument("--eigcg", action="store_true",
@@ -650,7 +654,9 @@ def c3_headline(torch, ovl, args, tuning):
                            "true_relres_last": res_f64} if f64 else None),
         "deflation": {"sumr_iteration_gain": it_und / it_def if it_def else None,
                       "time_gain": t_und / t_def if t_def else None,
-                      "eigenvalue_ratio": absr[-1] / absr[0] if absr and absr[0] > 0 else None,
+                      # |h| of gamma_5 D(mu) is at least mu; a Ritz value inside
+                      # (-mu, mu) is a mixture of a +- pair, so mu bounds the lower end
+                      "eigenvalue_ratio": absr[-1] / max(absr[0], C3_MU) if absr else None,
                       "abs_ritz_min_max": [absr[0], absr[-1]] if absr else None,
                       "setup_beyond_plain_solves_s": extra,
                       "break_even_sources": (extra / gain) if gain > 0 else None,
@@ -730,6 +736,46 @@ def sign_methods_leg(torch, ovl, tuning=None):
     return out
 
 
+def variant_sweep(torch, ovl, reps=10):
+    """Every admissible stencil launch variant forced through the tuning table:
+    the hopping stencil over twelve fields of 24^3 x 48 (links seed 3, links
+    read once per launch in the algorithmic bytes) and over one field of
+    32^3 x 64 (links seed 5), FP32 and FP16 storage, one warm-up launch and
+    `reps` timed launches each (HIP events on the dispatches).  Under
+    rocprofv3 --pmc the dispatches come in the order listed here, `reps + 1`
+    per variant."""
+    out = []
+    for name, dims, seed, nf in (("24^3x48, 12 fields", (24, 24, 24, 48), 3, 12),
+                                 ("32^3x64, 1 field", (32, 32, 32, 64), 5, 1)):
+        ctx = ovl.Context(dims)
+        ctx.gauge_generate(seed, 0.25)
+        if nf == 1:
+            psi = ctx.source(ovl.SRC_GAUSS, seed=7)
+        else:
+            psi = torch.stack([ctx.source(ovl.SRC_GAUSS, seed=300 + f) for f in range(nf)])
+        for prec in (ovl.F32, ovl.HALF):
+            for v in range(ovl.N_STENCIL_VARIANTS):
+                try:
+                    ctx.set_tuning({(prec * 8 + 0) * 64 + nf: v})   # the hopping epilogue, nf fields
+                except ovl.OvlError:
+                    continue   # not admissible on this lattice or in this precision
+                ctx.wilson_dslash(psi, prec)
+                torch.cuda.synchronize()
+                ctx.profile(True)
+                for _ in range(reps):
+                    ctx.wilson_dslash(psi, prec)
+                torch.cuda.synchronize()
+                p = ctx.profile_read(ovl.KERN_STENCIL, prec)
+                ctx.profile(False)
+                out.append({"lattice": name, "prec": PREC_NAMES[prec], "variant": v, "launches": p["launches"],
+                            "avg_us": 1e3 * p["ms"] / p["launches"], "bytes_per_launch": p["bytes"] / p["launches"],
+                            "GBps": p["bytes"] / (p["ms"] * 1e6)})
+                print(f"[bench] variant sweep {name} {PREC_NAMES[prec]} variant {v}: "
+                      f"{out[-1]['avg_us']:.1f} us, {out[-1]['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+        ctx.close()
+    return out
+
+
 def stream_ceiling(torch, ovl):
     """The library's own streaming kernels on 1 GiB buffers: copy (1 GiB
     read + 1 GiB written per launch) and read-only."""
@@ -790,6 +836,9 @@ def main():
     if args.profile_run:
         profile_run(torch, ovl, tuning, args)
         return
+    if args.variant_sweep:
+        print(json.dumps({"variant_sweep": variant_sweep(torch, ovl)}), flush=True)
+        return
     ctx, zolo, c3, prof = c3_headline(torch, ovl, args, tuning)
     ks = kernel_summary(prof)
     dom = max(ks, key=lambda k: ks[k]["ms"])
@@ -834,16 +883,15 @@ def main():
     }
     out["tuning"] = {C3_NAME: c3.pop("tuning")}
     ctx.close()
-    if args.headline_only:
-        print(json.dumps(out), flush=True)
-        return
-    out["c2_16c32"] = c2_secondary(torch, ovl, args, tuning)
-    out["tuning"]["16x16x16x32"] = out["c2_16c32"].pop("tuning")
-    print("[bench] 16^3x32 plain method done", file=sys.stderr, flush=True)
-    out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
-    out["tuning"].update(out["dslash_hbm"].pop("tuning"))
-    out["dslash_hbm"]["stream_ceiling"] = stream_ceiling(torch, ovl)
-    print("[bench] stand-alone stencil and streaming ceiling done", file=sys.stderr, flush=True)
+    if not args.headline_only:   # the secondary workloads; optional legs below run either way
+        out["c2_16c32"] = c2_secondary(torch, ovl, args, tuning)
+        out["tuning"]["16x16x16x32"] = out["c2_16c32"].pop("tuning")
+        print("[bench] 16^3x32 plain method done", file=sys.stderr, flush=True)
+        out["dslash_hbm"] = dslash_alone(torch, ovl, tuning)
+        for name, t in out["dslash_hbm"].pop("tuning").items():   # merged: 24^3x48 holds the solve's choices too
+            out["tuning"].setdefault(name, {}).update(t)
+        out["dslash_hbm"]["stream_ceiling"] = stream_ceiling(torch, ovl)
+        print("[bench] stand-alone stencil and streaming ceiling done", file=sys.stderr, flush=True)
     if args.extras:
         out["uneven_instances"] = uneven_leg(torch, ovl)
         print("[bench] uneven instances done", file=sys.stderr, flush=True)
@@ -857,7 +905,7 @@ def main():
         out["eigcg_16c32"] = eigcg_leg(torch, ovl, args.eigcg_calc)
     if args.eigsolve:
         out["eigsolve_16c32"] = eigsolve_leg(torch, ovl)
-    if not args.no_cpu:
+    if not args.no_cpu and not args.headline_only:
         it = f64["runs"][len(f64["runs"]) // 2]["mscg_iters"] if f64 else c3["undeflated_mixed"]["runs"][0]["mscg_iters"]
         out["cpu_baseline"] = cpu_baseline_c3(it)
     print(json.dumps(out), flush=True)

@@ -421,10 +421,18 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
  * registers, one t chunk per XCD, when Lt is a multiple of 8; 8 .. 11: one
  * lane per site of a 256-site spatial tile whose spinors are shared through
  * LDS, each block walking T = 1, 2, 4, 8 time slices (FP32 and FP16 storage,
- * Lt a multiple of T)).
+ * Lt a multiple of T); 12 .. 15: one / two lanes per site with each XCD
+ * owning a contiguous eighth of the tiles, walked in groups of 32 (12, 13) or
+ * 64 (14, 15) tiles with every field of the launch back to back inside a
+ * group, so that a group's links are reused from that XCD's L2; 16 .. 19: as
+ * 8 .. 11 with the tile's forward x, y, z links also staged in LDS).
+ * A key is (precision * 8 + epilogue) * 64 + min(field count, 63), the
+ * epilogue 0 for the plain hopping term; variants run 0 .. OVL_STENCIL_VARIANTS - 1.
  * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the
- * number held; ovl_tuning_set installs pairs (variants out of range are an
- * argument error), so a run can reuse another run's choices. */
+ * number held; ovl_tuning_set installs pairs (a variant out of range or not
+ * admissible on the context's lattice and precision is an argument error),
+ * so a run can reuse another run's choices. */
+enum { OVL_STENCIL_VARIANTS = 20 };
 ovl_status ovl_tuning_get(ovl_context *ctx, int32_t *keys, int32_t *variants, int32_t cap, int32_t *n);
 ovl_status ovl_tuning_set(ovl_context *ctx, const int32_t *keys, const int32_t *variants, int32_t n);
 

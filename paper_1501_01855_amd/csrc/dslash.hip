@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // 14: G 64, one; 15: G 64, two).  16 .. 19 the LDS-tiled march (T = 1, 2, 4,
 // 8) with the tile's forward spatial links also staged in LDS, so that the
 // backward hop of a site inside the tile reads its neighbour's link there.
-static constexpr int N_VARIANTS = 20;
+static constexpr int N_VARIANTS = OVL_STENCIL_VARIANTS;
 static bool variant_lds(int v) { return (v >= 8 && v < 12) || v >= 16; }
 static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7 || v == 13 || v == 15) ? 2 : 1; }
 

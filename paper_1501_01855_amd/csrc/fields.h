@@ -124,11 +124,24 @@ __device__ __forceinline__ uint32_t f22h2(float a, float b)
     return *reinterpret_cast<uint32_t *>(&h);
 }
 
+// 1 / m for an FP16-stored site whose largest |real component| is m.  A
+// site with m below the smallest normal float is stored as zero (m set to 0):
+// 1 / m would overflow to infinity there (such values occur at the edge of the
+// support of Krylov vectors grown from a point source).
+__device__ __forceinline__ float h8_inv_scale(float &m)
+{
+    if (!(m >= 0x1p-126f)) {
+        m = 0.f;
+        return 0.f;
+    }
+    return 1.f / m;
+}
+
 __device__ __forceinline__ void as_stored(const h8 *, cplx<float> *v, int n)
 {
     float m = 0.f;
     for (int c = 0; c < n; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    const float inv = m > 0.f ? 1.f / m : 0.f;
+    const float inv = h8_inv_scale(m);
     for (int c = 0; c < n; ++c) {
         const float2 q = h2f2(f22h2(v[c].re * inv, v[c].im * inv));
         v[c] = {q.x * m, q.y * m};
@@ -153,7 +166,7 @@ __device__ __forceinline__ void st_sp(h8 *__restrict__ p, int64_t V, int64_t s, 
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    const float inv = m > 0.f ? 1.f / m : 0.f;
+    const float inv = h8_inv_scale(m);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         uint4 t;
@@ -195,7 +208,7 @@ __device__ __forceinline__ float half_max(const cplx<float> v[6])
 // the values st_sp_half_scaled stores, with the site scale m
 __device__ __forceinline__ void as_stored_scaled(cplx<float> v[6], float m)
 {
-    const float inv = m > 0.f ? 1.f / m : 0.f;
+    const float inv = h8_inv_scale(m);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         const float2 q = h2f2(f22h2(v[c].re * inv, v[c].im * inv));
@@ -205,7 +218,7 @@ __device__ __forceinline__ void as_stored_scaled(cplx<float> v[6], float m)
 __device__ __forceinline__ void st_sp_half_scaled(h8 *__restrict__ p, int64_t V, int64_t s, int h,
                                                   const cplx<float> v[6], float m)
 {
-    const float inv = m > 0.f ? 1.f / m : 0.f;
+    const float inv = h8_inv_scale(m);
     uint32_t w[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) w[c] = f22h2(v[c].re * inv, v[c].im * inv);

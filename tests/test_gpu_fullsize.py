@@ -200,3 +200,26 @@ def test_c3_eigsumr_solve_with_oracle_operator():
     r = norm(b - ov(xh, 1e-13)) / norm(b)
     print("case C3 oracle true residual", r, flush=True)
     assert r <= 1e-10
+
+
+def test_c3_half_sign_of_point_source():
+    """sign(K) of a point source on 24^3 x 48 with FP16 storage at the relaxed
+    accuracy 1e-2 (20 poles): before the multi-shift CG's vectors cover the
+    lattice their outermost sites fall below FP32's normal range, where a
+    site's FP16 scale cannot be inverted (such sites are stored as zero).  The
+    call completes, and the result agrees with the FP64 sign at 1e-10 within
+    the requested accuracy."""
+    ovl = require_gpu()
+    dims = (24, 24, 24, 48)
+    ctx = ovl.Context(dims)
+    ctx.gauge_generate(3, 0.25)
+    lo, _, _ = ctx.kernel_interval(RHO)
+    _, zg = _zolo_pair(ovl, 20, 0.95 * lo, 8.0 - RHO)
+    b = ctx.source(ovl.SRC_POINT, site=0, spin=0, colour=0)
+    s16, st16 = ctx.sign(b, RHO, zg, 1e-2, prec=ovl.HALF)
+    s64, _ = ctx.sign(b, RHO, zg, 1e-10)
+    h16, h64 = to_host(s16), to_host(s64)
+    err = norm(h16 - h64) / norm(to_host(b))
+    print("case C3 FP16 point-source sign: iterations", st16.mscg_iters, "difference", err, flush=True)
+    assert np.all(np.isfinite(h16)) and err <= 1e-2
+    ctx.close()
