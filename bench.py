@@ -70,6 +70,11 @@ def parse():
     ap.add_argument("--eig-n", type=int, default=20, help="24^3x48: eigenvectors kept (n)")
     ap.add_argument("--eig-m", type=int, default=100, help="24^3x48: basis size of Alg. 6 (m)")
     ap.add_argument("--eig-eps", type=float, default=1e-4, help="24^3x48: target eigenvector accuracy (Sec. 6)")
+    ap.add_argument("--eig-block", action="store_true",
+                    help="24^3x48: the calculating solves as one batched call collecting into one basis "
+                         "(block eigSUMR) instead of one after another")
+    ap.add_argument("--full-links", action="store_true",
+                    help="24^3x48: FP32 / FP16 stencils on the full 18-real links instead of two rows")
     ap.add_argument("--fixed-nz", action="store_true",
                     help="24^3x48: every sign call with all 20 poles (default: the Zolotarev order per sign call "
                          "from its accuracy, Sec. 3)")
@@ -451,8 +456,16 @@ def dslash_alone(torch, ovl, tuning=None, reps=50):
         ctx.set_tuning(tuning["32x32x32x64"])
     ctx.gauge_generate(5, 0.25)
     psi = ctx.source(ovl.SRC_GAUSS, seed=7)
-    res = {"lattice": "32^3x64", **_stencil_rates(torch, ovl, ctx, psi, reps)}
+    res = {"lattice": "32^3x64", "two_row_links": ctx.gauge_info()[1], **_stencil_rates(torch, ovl, ctx, psi, reps)}
     res["tuning"] = {"32x32x32x64": ctx.tuning()}
+    ctx.close()
+    # the same with the full 18-real links (fresh context: its own launch choices)
+    ctx = ovl.Context((32, 32, 32, 64))
+    ctx.set_option(ovl.OPT_TWO_ROW_LINKS, 0)
+    ctx.gauge_generate(5, 0.25)
+    psi = ctx.source(ovl.SRC_GAUSS, seed=7)
+    res["full_links"] = _stencil_rates(torch, ovl, ctx, psi, reps)
+    res["full_links"]["tuning"] = ctx.tuning()
     ctx.close()
     ctx = ovl.Context((24, 24, 24, 48))
     if tuning and "24x24x24x48" in tuning:
@@ -530,13 +543,15 @@ C3_NAME = "24x24x24x48"
 TRAFFIC_C3 = os.path.join(HERE, "profiles", "traffic_overlap_solve_24c48.txt")
 
 
-def c3_setup(torch, ovl, tuning=None):
+def c3_setup(torch, ovl, tuning=None, full_links=False):
     """The 24^3 x 48 workload: links, the Zolotarev interval from Lanczos on
     K^2 (a = 0.95 x its smallest Ritz value, b = 8 - rho, a rigorous bound),
     the coefficients and the twelve spin-colour point sources at the origin."""
     ctx = ovl.Context(C3_DIMS)
     if tuning and C3_NAME in tuning:
         ctx.set_tuning(tuning[C3_NAME])
+    if full_links:
+        ctx.set_option(ovl.OPT_TWO_ROW_LINKS, 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.gauge_generate(C3_SEED, C3_EPS)
@@ -546,15 +561,16 @@ def c3_setup(torch, ovl, tuning=None):
     B = [ctx.source(ovl.SRC_POINT, site=0, spin=s, colour=c) for s in range(4) for c in range(3)]
     torch.cuda.synchronize()
     info = {"seconds": time.perf_counter() - t0, "interval": [a, b], "lanczos_lmin": lo, "lanczos_lmin_err": err,
-            "lanczos_lmax": hi, "zolotarev_delta": zolo.delta, "n_z": NZ}
+            "lanczos_lmax": hi, "zolotarev_delta": zolo.delta, "n_z": NZ,
+            "two_row_links": ctx.gauge_info()[1], "su3_deviation": ctx.gauge_info()[0]}
     return ctx, zolo, B, info
 
 
-def c3_params(ovl, args, mixed=True, calc=0, defl=1):
+def c3_params(ovl, args, mixed=True, calc=0, defl=1, block=0):
     return ovl.solver_defaults(rho=RHO, mu=C3_MU, tol=TOL, eta_tilde=args.c3_eta, relax_floor=1e-2,
                                f32_threshold=(1e-6 if mixed else 10.0), half_threshold=(3e-3 if mixed else 10.0),
                                max_outer=16, max_middle=6000, max_mscg=20000, use_deflation=defl, eig_calc=calc,
-                               n_eig=args.eig_n, m_eig=args.eig_m, eig_eps=args.eig_eps)
+                               n_eig=args.eig_n, m_eig=args.eig_m, eig_eps=args.eig_eps, eig_block=block)
 
 
 def timed_solve(torch, ctx, b, zolo, p):
@@ -579,7 +595,7 @@ def median(xs):
 def c3_headline(torch, ovl, args, tuning):
     """Set-up, eigSUMR calculating solves, the timed deflated solves, the
     profiled replica and the comparison solves on 24^3 x 48."""
-    ctx, zolo, B, setup = c3_setup(torch, ovl, tuning)
+    ctx, zolo, B, setup = c3_setup(torch, ovl, tuning, args.full_links)
     ctx.set_option(ovl.OPT_ADAPTIVE_NZ, 0 if args.fixed_nz else 1)
     ctx.set_option(ovl.OPT_BOUND_PRINTED, 0 if args.bound_text else 1)
     n_calc = args.eig_calc
@@ -588,11 +604,21 @@ def c3_headline(torch, ovl, args, tuning):
     # of each) on the first sources, then v^D recomputed in FP64
     ctx.eigspace_set(args.eig_n, args.eig_m, C3_MU)
     calc = []
-    for i in range(n_calc):
-        dt, st, code, _ = timed_solve(torch, ctx, B[i], zolo, c3_params(ovl, args, True, 1, 1))
-        calc.append({"seconds": dt, "status": code, **st})
-        print(f"[bench] C3 calculating solve {i}: {dt:.1f} s, {st['sumr_iters']} SUMR iterations",
-              file=sys.stderr, flush=True)
+    if args.eig_block:   # the first n_calc sources in one calculating call, one basis (block eigSUMR)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, sts, code = ctx.solve(torch.stack(B[:n_calc]), zolo, c3_params(ovl, args, True, 1, 1, block=1))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        calc.append({"seconds": dt, "status": code, "sources": n_calc,
+                     "sumr_iters_per_source": [st.sumr_iters for st in sts]})
+        print(f"[bench] C3 block calculating solve of {n_calc} sources: {dt:.1f} s", file=sys.stderr, flush=True)
+    else:
+        for i in range(n_calc):
+            dt, st, code, _ = timed_solve(torch, ctx, B[i], zolo, c3_params(ovl, args, True, 1, 1))
+            calc.append({"seconds": dt, "status": code, **st})
+            print(f"[bench] C3 calculating solve {i}: {dt:.1f} s, {st['sumr_iters']} SUMR iterations",
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.eigspace_recompute(RHO, zolo, 1e-12)
@@ -638,7 +664,9 @@ def c3_headline(torch, ovl, args, tuning):
     gain = t_und - t_def
     out = {
         "setup": setup,
-        "eigsumr": {"n_eig": args.eig_n, "m_eig": args.eig_m, "eig_eps": args.eig_eps, "calculating_solves": calc,
+        "eigsumr": {"n_eig": args.eig_n, "m_eig": args.eig_m, "eig_eps": args.eig_eps,
+                    "calculating": "one block call" if args.eig_block else "one source after another",
+                    "calculating_solves": calc,
                     "calculating_seconds": t_calc, "recompute_fp64_seconds": t_recompute,
                     "diagonalisations": info["ndiag"], "ritz": ritz, "residuals": info["resid"],
                     "bound": "chi scales the bound" if args.bound_text else "as printed (chi on the square root)",
@@ -869,7 +897,8 @@ def main():
         "config": {"workload": "overlap solve 24^3x48 (links exp(i 0.25 A), seed 3), rho=1.4, mu=0.01, Zolotarev "
                                "sign function (" + ("20 poles" if args.fixed_nz else "at most 20 poles, order per call "
                                "from its accuracy") + ") on the Lanczos interval of |K|, eigSUMR deflation with "
-                               f"{args.eig_n} eigenvectors (m={args.eig_m}, {args.eig_calc} calculating solves), one "
+                               f"{args.eig_n} eigenvectors (m={args.eig_m}, {args.eig_calc} calculating solves"
+                               + (" in one block call" if args.eig_block else "") + "), one "
                                "spin-colour point source per step (cycling over the 12), mixed precision, "
                                f"GMRESR(relSUMR) to 1e-10 (middle solves to {args.c3_eta:g})",
                    "global_batch": 1, "lattice": C3_NAME, "parallelism": "single GPU"},

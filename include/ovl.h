@@ -407,9 +407,23 @@ ovl_status ovl_stream_bench(ovl_context *ctx, int32_t kind, const void *src_dev,
  *                    on the square root only, chi sqrt(eps^2 + r0^2) - r0, as the
  *                    equation is printed; off: chi (sqrt(eps^2 + r0^2) - r0), the
  *                    bound scaled by chi as the text describes.  For comparing
- *                    the two readings; the eigenvector relaxation only. */
-enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2, OVL_OPT_ADAPTIVE_NZ = 3, OVL_OPT_BOUND_PRINTED = 4 };
+ *                    the two readings; the eigenvector relaxation only.
+ *   OVL_OPT_TWO_ROW_LINKS (default on) the FP32 and FP16 stencils read 12 of
+ *                    the 18 reals of each link and rebuild the third row as
+ *                    the conjugate cross product of the first two, when every
+ *                    loaded link passes the SU(3) test of ovl_gauge_info
+ *                    (otherwise, or with the option off, the full links). */
+enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2, OVL_OPT_ADAPTIVE_NZ = 3, OVL_OPT_BOUND_PRINTED = 4,
+       OVL_OPT_TWO_ROW_LINKS = 5 };
 ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
+
+/* The loaded links (Sec. 1, eq. 2: U_mu(x) in SU(3)).  *su3_deviation
+ * receives the largest |U_2b - conj(U_0 x U_1)_b| over all links and entries,
+ * computed in FP64 when the links were loaded; *two_row is 1 when the FP32
+ * and FP16 stencils use the two-row form (deviation at most 2^-23 and
+ * OVL_OPT_TWO_ROW_LINKS on), else 0.  Either pointer may be null.
+ * OVL_ERR_STATE without links. */
+ovl_status ovl_gauge_info(ovl_context *ctx, double *su3_deviation, int32_t *two_row);
 
 /* Stencil launch shapes.  The first launch of each (precision, epilogue,
  * field count) times the launch variants on the context's lattice and keeps

@@ -20,7 +20,7 @@ SRC_POINT, SRC_GAUSS, SRC_Z2 = 0, 1, 2
 MAX_NZ = 64
 KERN_STENCIL, KERN_SHIFT = 0, 1
 N_STENCIL_VARIANTS = 20   # launch variants of the stencil (tuning-table values 0 .. 19)
-OPT_GRAPHS, OPT_AUTOTUNE, OPT_ADAPTIVE_NZ, OPT_BOUND_PRINTED = 1, 2, 3, 4
+OPT_GRAPHS, OPT_AUTOTUNE, OPT_ADAPTIVE_NZ, OPT_BOUND_PRINTED, OPT_TWO_ROW_LINKS = 1, 2, 3, 4, 5
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_NOMEM", -4: "ERR_NOT_CONVERGED",
           -5: "ERR_BREAKDOWN", -6: "ERR_UNSUPPORTED", -7: "ERR_STATE"}
@@ -83,7 +83,7 @@ EXPORTS = ["ovl_create", "ovl_destroy", "ovl_last_error", "ovl_solver_defaults",
            "ovl_deflate_project", "ovl_overlap_adjoint", "ovl_tuning_get", "ovl_tuning_set", "ovl_set_option",
            "ovl_sumr_gmresr_solve_many", "ovl_eigsumr_eigensolve", "ovl_wilson_dslash_noalloc",
            "ovl_kernel_interval", "ovl_stream_bench", "ovl_eigspace_save", "ovl_eigspace_load",
-           "ovl_sign_lanczos"]
+           "ovl_sign_lanczos", "ovl_gauge_info"]
 
 _lib = None
 
@@ -121,6 +121,7 @@ def lib():
         "ovl_tuning_get": ([P, P, P, I32, P], I32),
         "ovl_tuning_set": ([P, P, P, I32], I32),
         "ovl_set_option": ([P, I32, I32], I32),
+        "ovl_gauge_info": ([P, P, P], I32),
         "ovl_stream_bench": ([P, I32, P, P, I64, I32, P], I32),
         "ovl_sumr_gmresr_solve_many": ([P, I32, P], I32),
         "ovl_sumr_gmresr_solve": ([P, P, P, P, P, I32, P], I32),
@@ -409,6 +410,14 @@ class Context:
 
     def set_option(self, option, value):
         _check(lib().ovl_set_option(self._h, int(option), int(bool(value))))
+
+    def gauge_info(self):
+        """(largest deviation of the links' third rows from the two-row rebuild,
+        whether the FP32 / FP16 stencils use the two-row form)."""
+        dev = ctypes.c_double()
+        tr = ctypes.c_int32()
+        _check(lib().ovl_gauge_info(self._h, ctypes.byref(dev), ctypes.byref(tr)))
+        return dev.value, bool(tr.value)
 
     def tuning(self):
         """The stencil launch variants chosen so far, {key: variant}."""

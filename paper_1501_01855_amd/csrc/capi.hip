@@ -743,8 +743,21 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value)
             ctx->adaptive_nz = value != 0;
         else if (option == OVL_OPT_BOUND_PRINTED)
             ctx->eig.bound_printed = value != 0;
-        else
+        else if (option == OVL_OPT_TWO_ROW_LINKS) {
+            ctx->two_row_opt = value != 0;
+            update_link_form(*ctx);
+        } else
             throw Error{OVL_ERR_ARG, "unknown option"};
+    });
+}
+
+ovl_status ovl_gauge_info(ovl_context *ctx, double *su3_deviation, int32_t *two_row)
+{
+    return guard([&] {
+        check_ctx(ctx);
+        OVL_REQUIRE(ctx->have_gauge, OVL_ERR_STATE, "no gauge field loaded");
+        if (su3_deviation) *su3_deviation = ctx->su3_dev;
+        if (two_row) *two_row = ctx->g.two_row;
     });
 }
 

@@ -82,6 +82,7 @@ struct Geom {
     int32_t cb[3], cn[3];
     int32_t col_sites;   // cb[0] cb[1] cb[2]
     int32_t col_ok;
+    int32_t two_row;     // FP32 / FP16 stencils read the two-row links (set when the links are loaded)
 };
 
 inline Geom make_geom(const int32_t d[4])
@@ -95,6 +96,7 @@ inline Geom make_geom(const int32_t d[4])
     }
     g.V = s;
     g.Pu = s + LINK_PAD;
+    g.two_row = 0;
     // the split into 8 = cx cy cz columns with the smallest halo: a cut face
     // along m re-reads 2 / cb[m] of the column's sites, a cut along x whole
     // 128-byte lines (8 sites) per row end, so x rows stay whole if possible

@@ -58,6 +58,10 @@ struct Context {
     double2 *U64 = nullptr;   // [4][9][Pu] (Geom::Pu: padded plane stride)
     float2 *U32 = nullptr;    // 36 Pu float2: float4 [4][4][Pu] + float2 [4][Pu]
     void *U16 = nullptr;      // 36 Pu __half2: uint4 [4][2][Pu] + uint32 [4][Pu]
+    void *U32r = nullptr;     // two-row FP32 links: float4 [4][2][Pu] + float4 [4][Pu]
+    void *U16r = nullptr;     // two-row FP16 links: uint4 [4][Pu] + uint2 [4][Pu]
+    double su3_dev = -1.0;    // largest |third row - conj(row 0 x row 1)| over the loaded links
+    bool two_row_opt = true;  // OVL_OPT_TWO_ROW_LINKS
     bool have_gauge = false;
 
     // kernel low modes: FP64 packed [n][12][V] and eigenvalues

@@ -181,6 +181,8 @@ Context::~Context()
     if (U64) hipFree(U64);
     if (U32) hipFree(U32);
     if (U16) hipFree(U16);
+    if (U32r) hipFree(U32r);
+    if (U16r) hipFree(U16r);
     if (low) hipFree(low);
     for (int p = 1; p < 3; ++p)
         if (low_lp[p]) hipFree(low_lp[p]);

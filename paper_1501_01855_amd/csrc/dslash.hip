@@ -13,6 +13,7 @@
 // block orders, lanes walking time columns, LDS-shared spatial tiles); an
 // autotuner picks one per precision, epilogue and field count.
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "context.h"
@@ -72,10 +73,26 @@ __global__ void k_f32_to_f64(const float4 *__restrict__ in, double2 *__restrict_
 }
 
 __global__ void k_pack_gauge(const double2 *__restrict__ canon, double2 *__restrict__ U64,
-                             float2 *__restrict__ U32, __half2 *__restrict__ U16, int64_t V, int64_t Pu)
+                             float2 *__restrict__ U32, __half2 *__restrict__ U16, float2 *__restrict__ U32r,
+                             __half2 *__restrict__ U16r, int64_t V, int64_t Pu)
 {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= V) return;
+    // two-row forms (the planes ld_link reads for f2r12 / h2r12): entries
+    // 0..3 in the Q planes, 4 and 5 in the R plane
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double2 u = canon[s * 36 + mu * 9 + k];
+            const float2 f = make_float2((float)u.x, (float)u.y);
+            if (k < 4) {
+                U32r[2 * ((mu * 2 + k / 2) * Pu + s) + k % 2] = f;
+                U16r[4 * (mu * Pu + s) + k] = __floats2half2_rn((float)u.x, (float)u.y);
+            } else {
+                U32r[2 * (8 * Pu + mu * Pu + s) + (k - 4)] = f;
+                U16r[4 * 4 * Pu + 2 * (mu * Pu + s) + (k - 4)] = __floats2half2_rn((float)u.x, (float)u.y);
+            }
+        }
     // FP32: float4 Q[4][4][Pu] then float2 R[4][Pu]; FP16: uint4 Q[4][2][Pu]
     // then uint32 R[4][Pu] (the layouts ld_link reads)
     float *Q32 = reinterpret_cast<float *>(U32);
@@ -182,6 +199,40 @@ void convert_spinor(Context &c, const void *src, int sprec, void *dst, int dprec
     OVL_HIP(hipGetLastError());
 }
 
+// Per block: the largest |u_2b - conj(u_0 x u_1)_b| over the links of its
+// sites (FP64), the test for the two-row form.
+__global__ __launch_bounds__(256) void k_su3_dev(const double2 *__restrict__ canon, int64_t V,
+                                                 double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double m = 0.0;
+    if (s < V)
+        for (int mu = 0; mu < 4; ++mu) {
+            cplx<double> u[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const double2 t = canon[s * 36 + mu * 9 + k];
+                u[k] = {t.x, t.y};
+            }
+            cplx<double> w[9] = {u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7], u[8]};
+            su3_third_row(w);
+#pragma unroll
+            for (int k = 6; k < 9; ++k) m = fmax(m, fmax(fabs(w[k].re - u[k].re), fabs(w[k].im - u[k].im)));
+        }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Links whose third rows agree with the two-row rebuild to this bound use
+// the two-row form in FP32 and FP16 (about the rounding of FP32 storage).
+static constexpr double TWO_ROW_TOL = 0x1p-23;
+
 void pack_gauge(Context &c, const double *canon)
 {
     const Geom &g = c.g;
@@ -189,12 +240,30 @@ void pack_gauge(Context &c, const double *canon)
         OVL_HIP(hipMalloc(&c.U64, (size_t)g.Pu * 36 * sizeof(double2)));
         OVL_HIP(hipMalloc(&c.U32, (size_t)g.Pu * 36 * sizeof(float2)));
         OVL_HIP(hipMalloc(&c.U16, (size_t)g.Pu * 36 * sizeof(__half2)));
-        c.bytes_held += (int64_t)g.Pu * 36 * (16 + 8 + 4);
+        OVL_HIP(hipMalloc(&c.U32r, (size_t)g.Pu * 24 * sizeof(float2)));
+        OVL_HIP(hipMalloc(&c.U16r, (size_t)g.Pu * 24 * sizeof(__half2)));
+        c.bytes_held += (int64_t)g.Pu * (36 * (16 + 8 + 4) + 24 * (8 + 4));
     }
     k_pack_gauge<<<site_blocks(g), 256, 0, c.stream>>>((const double2 *)canon, c.U64, c.U32, (__half2 *)c.U16,
-                                                       g.V, g.Pu);
+                                                       (float2 *)c.U32r, (__half2 *)c.U16r, g.V, g.Pu);
     OVL_HIP(hipGetLastError());
+    const int nb = (int)site_blocks(g);
+    double *part = (double *)c.buf("su3_dev", sizeof(double) * nb);
+    k_su3_dev<<<nb, 256, 0, c.stream>>>((const double2 *)canon, g.V, part);
+    OVL_HIP(hipGetLastError());
+    std::vector<double> h(nb);
+    OVL_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, c.stream));
+    OVL_HIP(hipStreamSynchronize(c.stream));
+    double m = 0.0;
+    for (double v : h) m = std::max(m, std::isnan(v) ? INFINITY : v);
+    c.su3_dev = m;
     c.have_gauge = true;
+    update_link_form(c);
+}
+
+void update_link_form(Context &c)
+{
+    c.g.two_row = (c.two_row_opt && c.have_gauge && c.su3_dev >= 0.0 && c.su3_dev <= TWO_ROW_TOL) ? 1 : 0;
 }
 
 // ------------------------------------------------------------- stencil kernel
@@ -208,16 +277,27 @@ __device__ __forceinline__ void gather_dir(const ST *__restrict__ in, const GT *
                                            int64_t s,
                                            int32_t c, int32_t Lm, int64_t st, cplx<R> acc[12])
 {
-    cplx<R> psi[12];
-    cplx<R> u[9];
     const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st : s + st;
     const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st : s - st;
-    ld_sp(in, V, fwd, psi);
-    ld_link(U, Pu, MU, s, u);
-    hop_term<MU, true>(psi, u, acc);
-    ld_sp(in, V, bwd, psi);
-    ld_link(U, Pu, MU, bwd, u);
-    hop_term<MU, false>(psi, u, acc);
+    if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: on the packed halves
+        hv2 w[12], u[9];
+        float sc;
+        ld_sp_h(in, V, fwd, w, sc);
+        ld_link_h(U, Pu, MU, s, u);
+        hop_term_h<MU, true>(w, sc, u, acc);
+        ld_sp_h(in, V, bwd, w, sc);
+        ld_link_h(U, Pu, MU, bwd, u);
+        hop_term_h<MU, false>(w, sc, u, acc);
+    } else {
+        cplx<R> psi[12];
+        cplx<R> u[9];
+        ld_sp(in, V, fwd, psi);
+        ld_link(U, Pu, MU, s, u);
+        hop_term<MU, true>(psi, u, acc);
+        ld_sp(in, V, bwd, psi);
+        ld_link(U, Pu, MU, bwd, u);
+        hop_term<MU, false>(psi, u, acc);
+    }
 }
 
 // Directions MU0..MU1.  Four directions run as a non-unrolled loop (bounded
@@ -231,6 +311,31 @@ __device__ __forceinline__ void gather(const ST *__restrict__ in, const GT *__re
     if constexpr (MU1 - MU0 == 1) {
         gather_dir<MU0, R>(in, U, V, Pu, s, co[MU0], Ls[MU0], st[MU0], acc);
         gather_dir<MU1, R>(in, U, V, Pu, s, co[MU1], Ls[MU1], st[MU1], acc);
+    } else if constexpr (std::is_same<ST, h8>::value) {   // FP16 storage: on the packed halves
+        hv2 w[12], u[9];
+        float sc;
+#pragma unroll 1
+        for (int mu = MU0; mu <= MU1; ++mu) {
+            const int32_t c = co[mu], Lm = Ls[mu];
+            const int64_t fwd = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st[mu] : s + st[mu];
+            const int64_t bwd = (c == 0) ? s + (int64_t)(Lm - 1) * st[mu] : s - st[mu];
+            ld_sp_h(in, V, fwd, w, sc);
+            ld_link_h(U, Pu, mu, s, u);
+            switch (mu) {
+            case 0: hop_term_h<0, true>(w, sc, u, acc); break;
+            case 1: hop_term_h<1, true>(w, sc, u, acc); break;
+            case 2: hop_term_h<2, true>(w, sc, u, acc); break;
+            default: hop_term_h<3, true>(w, sc, u, acc); break;
+            }
+            ld_sp_h(in, V, bwd, w, sc);
+            ld_link_h(U, Pu, mu, bwd, u);
+            switch (mu) {
+            case 0: hop_term_h<0, false>(w, sc, u, acc); break;
+            case 1: hop_term_h<1, false>(w, sc, u, acc); break;
+            case 2: hop_term_h<2, false>(w, sc, u, acc); break;
+            default: hop_term_h<3, false>(w, sc, u, acc); break;
+            }
+        }
     } else {
         cplx<R> psi[12];
         cplx<R> u[9];
@@ -806,6 +911,55 @@ __device__ __forceinline__ void ld_link_raw(const __half2 *__restrict__ U, int64
     for (int k = 0; k < 2; ++k) l.q[k] = Q[(mu * 2 + k) * P + s];
     l.r = R[mu * P + s];
 }
+template <>
+struct LinkRaw<f2r12> {
+    float4 q[2];
+    float4 r;
+};
+template <>
+struct LinkRaw<h2r12> {
+    uint4 q[1];
+    uint2 r;
+};
+__device__ __forceinline__ void ld_link_raw(const f2r12 *__restrict__ U, int64_t P, int mu, int64_t s,
+                                            LinkRaw<f2r12> &l)
+{
+    const float4 *Q = reinterpret_cast<const float4 *>(U);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) l.q[k] = Q[(mu * 2 + k) * P + s];
+    l.r = Q[8 * P + mu * P + s];
+}
+__device__ __forceinline__ void ld_link_raw(const h2r12 *__restrict__ U, int64_t P, int mu, int64_t s,
+                                            LinkRaw<h2r12> &l)
+{
+    const uint4 *Q = reinterpret_cast<const uint4 *>(U);
+    l.q[0] = Q[mu * P + s];
+    l.r = reinterpret_cast<const uint2 *>(Q + 4 * P)[mu * P + s];
+}
+__device__ __forceinline__ void unpack_link(const LinkRaw<f2r12> &l, cplx<float> u[9])
+{
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        u[2 * k] = {l.q[k].x, l.q[k].y};
+        u[2 * k + 1] = {l.q[k].z, l.q[k].w};
+    }
+    u[4] = {l.r.x, l.r.y};
+    u[5] = {l.r.z, l.r.w};
+    su3_third_row(u);
+}
+__device__ __forceinline__ void unpack_link(const LinkRaw<h2r12> &l, cplx<float> u[9])
+{
+    const uint4 q = l.q[0];
+    const float2 a = h2f2(q.x), b = h2f2(q.y), c = h2f2(q.z), d = h2f2(q.w);
+    u[0] = {a.x, a.y};
+    u[1] = {b.x, b.y};
+    u[2] = {c.x, c.y};
+    u[3] = {d.x, d.y};
+    const float2 e = h2f2(l.r.x), f = h2f2(l.r.y);
+    u[4] = {e.x, e.y};
+    u[5] = {f.x, f.y};
+    su3_third_row(u);
+}
 // the values ld_link returns for the same stored link
 __device__ __forceinline__ void unpack_link(const LinkRaw<float2> &l, cplx<float> u[9])
 {
@@ -910,7 +1064,9 @@ __device__ __forceinline__ void stencil_lds_body(const StencilArgs<ST> &a, const
 {
     __shared__ ST Lsp[Planes<ST>::n * LDS_SITES];   // the tile's stored spinors at the current slice
     __shared__ float Lsc[LDS_SITES];                 // their scales (FP16 storage; unused otherwise)
-    constexpr int NLD = std::is_same<GT, __half2>::value ? 3 : 2;   // spatial directions with staged links
+    // spatial directions with staged links: three where a link takes at most
+    // 48 bytes (FP16, both FP32 two-row and FP16 two-row), else two
+    constexpr int NLD = sizeof(LinkRaw<GT>) <= 48 ? 3 : 2;
     using LL = LinkLds<GT, NLD>;
     __shared__ typename std::conditional<LINKS, LL, char>::type Lu_store;
     LL *Lu = LINKS ? reinterpret_cast<LL *>(&Lu_store) : nullptr;
@@ -1212,6 +1368,18 @@ static void launch_stencil_t(Context &c, const StencilArgs<ST> &a, const GT *U, 
     if (prof) c.prof_end(pe);
 }
 
+template <typename ST, typename GT>
+static void stencil_epi(Context &c, int epi, const StencilArgs<ST> &a, const GT *U, int nf, int prec)
+{
+    switch (epi) {
+    case EPI_HOP: launch_stencil_t<ST, GT, EPI_HOP>(c, a, U, nf, prec, true); break;
+    case EPI_K: launch_stencil_t<ST, GT, EPI_K>(c, a, U, nf, prec, true); break;
+    case EPI_K2DOT: launch_stencil_t<ST, GT, EPI_K2DOT>(c, a, U, nf, prec, true); break;
+    case EPI_KPLUS: launch_stencil_t<ST, GT, EPI_KPLUS>(c, a, U, nf, prec, true); break;
+    default: throw Error{OVL_ERR_ARG, "stencil: epilogue"};
+    }
+}
+
 void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, double rho,
              double sigma, const void *aux, double *partial, const int *stop, int it, const void *aux2,
              const int *itb)
@@ -1220,31 +1388,21 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
     if (prec == OVL_F64) {
         StencilArgs<double2> a{c.g, (const double2 *)in, (double2 *)out, (const double2 *)aux,
                                (const double2 *)aux2, 4.0 - rho, sigma, partial, stop, it, itb};
-        switch (epi) {
-        case EPI_HOP: launch_stencil_t<double2, double2, EPI_HOP>(c, a, c.U64, nf, prec, true); break;
-        case EPI_K: launch_stencil_t<double2, double2, EPI_K>(c, a, c.U64, nf, prec, true); break;
-        case EPI_K2DOT: launch_stencil_t<double2, double2, EPI_K2DOT>(c, a, c.U64, nf, prec, true); break;
-        case EPI_KPLUS: launch_stencil_t<double2, double2, EPI_KPLUS>(c, a, c.U64, nf, prec, true); break;
-        }
+        stencil_epi(c, epi, a, c.U64, nf, prec);
     } else if (prec == OVL_F32) {
         StencilArgs<float4> a{c.g, (const float4 *)in, (float4 *)out, (const float4 *)aux,
                               (const float4 *)aux2, 4.0 - rho, sigma, partial, stop, it, itb};
-        switch (epi) {
-        case EPI_HOP: launch_stencil_t<float4, float2, EPI_HOP>(c, a, c.U32, nf, prec, true); break;
-        case EPI_K: launch_stencil_t<float4, float2, EPI_K>(c, a, c.U32, nf, prec, true); break;
-        case EPI_K2DOT: launch_stencil_t<float4, float2, EPI_K2DOT>(c, a, c.U32, nf, prec, true); break;
-        case EPI_KPLUS: launch_stencil_t<float4, float2, EPI_KPLUS>(c, a, c.U32, nf, prec, true); break;
-        }
+        if (c.g.two_row)
+            stencil_epi(c, epi, a, (const f2r12 *)c.U32r, nf, prec);
+        else
+            stencil_epi(c, epi, a, (const float2 *)c.U32, nf, prec);
     } else {
         StencilArgs<h8> a{c.g, (const h8 *)in, (h8 *)out, (const h8 *)aux, (const h8 *)aux2, 4.0 - rho,
                           sigma, partial, stop, it, itb};
-        const __half2 *U = (const __half2 *)c.U16;
-        switch (epi) {
-        case EPI_HOP: launch_stencil_t<h8, __half2, EPI_HOP>(c, a, U, nf, prec, true); break;
-        case EPI_K: launch_stencil_t<h8, __half2, EPI_K>(c, a, U, nf, prec, true); break;
-        case EPI_K2DOT: launch_stencil_t<h8, __half2, EPI_K2DOT>(c, a, U, nf, prec, true); break;
-        case EPI_KPLUS: launch_stencil_t<h8, __half2, EPI_KPLUS>(c, a, U, nf, prec, true); break;
-        }
+        if (c.g.two_row)
+            stencil_epi(c, epi, a, (const h2r12 *)c.U16r, nf, prec);
+        else
+            stencil_epi(c, epi, a, (const __half2 *)c.U16, nf, prec);
     }
 }
 
@@ -1280,7 +1438,8 @@ void launch_K(Context &c, double rho, const void *in, void *out, int nf, int pre
 // reads of the epilogues that take more inputs.
 double stencil_link_bytes(const Geom &g, int prec)
 {
-    return (double)g.V * 36 * (prec == OVL_F64 ? 16 : prec == OVL_F32 ? 8 : 4);
+    const int entries = (prec != OVL_F64 && g.two_row) ? 24 : 36;   // complex entries per site
+    return (double)g.V * entries * (prec == OVL_F64 ? 16 : prec == OVL_F32 ? 8 : 4);
 }
 
 double stencil_bytes(const Geom &g, int prec, int epi)

@@ -14,6 +14,7 @@
 //         + uint32 [4][P] (entry 8)
 #pragma once
 #include <hip/hip_fp16.h>
+#include <type_traits>
 
 #include "common.h"
 
@@ -283,6 +284,73 @@ __device__ __forceinline__ void ld_link(const __half2 *__restrict__ U, int64_t P
     u[8] = {r.x, r.y};
 }
 
+// Two-row links.  For a link in SU(3) the third row is the complex conjugate
+// of the cross product of the first two, so the FP32 and FP16 stencils can
+// read 12 reals per link and rebuild the rest; the context keeps this form
+// beside the full one and uses it when every loaded link passes an SU(3)
+// test.  The tag types (the size of one stored complex entry) select the
+// loaders below; their planes: FP32 entries 0..3 as two float4 planes per
+// direction, Q [4 mu][2][P], then entries 4, 5 as one float4 plane R [4 mu][P]
+// (three loads per link); FP16 entries 0..3 as one uint4 plane Q [4 mu][1][P],
+// then entries 4, 5 as one uint2 plane R [4 mu][P] (two loads per link).
+struct f2r12 {
+    float2 v;
+};
+struct h2r12 {
+    __half2 v;
+};
+template <typename GT>
+struct is_two_row {
+    static constexpr bool value = std::is_same<GT, f2r12>::value || std::is_same<GT, h2r12>::value;
+};
+
+// u[6..8] = conj(u[0..2] x u[3..5]), row-major u[a * 3 + b]
+template <typename R>
+__device__ __forceinline__ void su3_third_row(cplx<R> u[9])
+{
+    const cplx<R> c0 = u[1] * u[5] - u[2] * u[4];
+    const cplx<R> c1 = u[2] * u[3] - u[0] * u[5];
+    const cplx<R> c2 = u[0] * u[4] - u[1] * u[3];
+    u[6] = {c0.re, -c0.im};
+    u[7] = {c1.re, -c1.im};
+    u[8] = {c2.re, -c2.im};
+}
+
+__device__ __forceinline__ void ld_link(const f2r12 *__restrict__ U, int64_t P, int mu, int64_t s,
+                                        cplx<float> u[9])
+{
+    const float4 *Q = reinterpret_cast<const float4 *>(U);
+    const float4 *R = Q + 8 * P;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float4 q = Q[(mu * 2 + k) * P + s];
+        u[2 * k] = {q.x, q.y};
+        u[2 * k + 1] = {q.z, q.w};
+    }
+    const float4 r = R[mu * P + s];
+    u[4] = {r.x, r.y};
+    u[5] = {r.z, r.w};
+    su3_third_row(u);
+}
+
+__device__ __forceinline__ void ld_link(const h2r12 *__restrict__ U, int64_t P, int mu, int64_t s,
+                                        cplx<float> u[9])
+{
+    const uint4 *Q = reinterpret_cast<const uint4 *>(U);
+    const uint2 *R = reinterpret_cast<const uint2 *>(Q + 4 * P);
+    const uint4 q = Q[mu * P + s];
+    const float2 a = h2f2(q.x), b = h2f2(q.y), c = h2f2(q.z), d = h2f2(q.w);
+    u[0] = {a.x, a.y};
+    u[1] = {b.x, b.y};
+    u[2] = {c.x, c.y};
+    u[3] = {d.x, d.y};
+    const uint2 r = R[mu * P + s];
+    const float2 e = h2f2(r.x), f = h2f2(r.y);
+    u[4] = {e.x, e.y};
+    u[5] = {f.x, f.y};
+    su3_third_row(u);
+}
+
 // ------------------------------------------------------------------ spin algebra
 // Chiral basis: gamma_mu = [[0, A_mu], [B_mu, 0]] in 2x2 spin blocks with
 // A_k = -i s_k, B_k = i s_k = -A_k (k = x, y, z), A_t = B_t = 1, A B = 1.
@@ -388,6 +456,132 @@ __device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[
     cplx<R> h[6], g[6];
     spin_proj<MU, FWD>(psi, h);
     link_mul<FWD>(u, h, g);
+    spin_recon<MU, FWD>(g, acc);
+}
+
+// ------------------------------------------------------------------ FP16 hops on packed halves
+// With FP16 storage the hop runs on the stored halves: the spin projection as
+// packed FP16 adds (a site's components are at most 1 in modulus after its
+// scale, so the projection is at most 2), the link product as two-term FP16
+// dot products accumulated in FP32 (each half product is exact in FP32), the
+// neighbour's scale applied to the product, the spin reconstruction and the
+// sum over directions in FP32.  This halves the vector instructions of a hop
+// against converting everything to FP32 first.
+typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ hv2 as_hv2(uint32_t w) { return __builtin_bit_cast(hv2, w); }
+__device__ __forceinline__ float dot2(hv2 a, hv2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+
+// an FP16-stored site: its 12 components as packed halves, and its scale
+__device__ __forceinline__ void ld_sp_h(const h8 *__restrict__ p, int64_t V, int64_t s, hv2 w[12], float &sc)
+{
+    sc = reinterpret_cast<const float *>(p + 3 * V)[s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint4 t = p[k * V + s].v;
+        w[4 * k] = as_hv2(t.x);
+        w[4 * k + 1] = as_hv2(t.y);
+        w[4 * k + 2] = as_hv2(t.z);
+        w[4 * k + 3] = as_hv2(t.w);
+    }
+}
+
+// FP16 links as packed halves (the planes of ld_link)
+__device__ __forceinline__ void ld_link_h(const __half2 *__restrict__ U, int64_t P, int mu, int64_t s, hv2 u[9])
+{
+    const uint4 *Q = reinterpret_cast<const uint4 *>(U);
+    const uint32_t *R = reinterpret_cast<const uint32_t *>(Q + 8 * P);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const uint4 q = Q[(mu * 2 + k) * P + s];
+        u[4 * k] = as_hv2(q.x);
+        u[4 * k + 1] = as_hv2(q.y);
+        u[4 * k + 2] = as_hv2(q.z);
+        u[4 * k + 3] = as_hv2(q.w);
+    }
+    u[8] = as_hv2(R[mu * P + s]);
+}
+// conj(x y - z w) for complex halves, rounded to half
+__device__ __forceinline__ hv2 conj_cross_h(hv2 x, hv2 y, hv2 z, hv2 w)
+{
+    const float re = dot2(z, (hv2){-w.x, w.y}, dot2(x, (hv2){y.x, -y.y}, 0.f));
+    const float im = dot2(z, -w.yx, dot2(x, y.yx, 0.f));
+    return (hv2){(_Float16)re, (_Float16)(-im)};
+}
+__device__ __forceinline__ void ld_link_h(const h2r12 *__restrict__ U, int64_t P, int mu, int64_t s, hv2 u[9])
+{
+    const uint4 *Q = reinterpret_cast<const uint4 *>(U);
+    const uint2 *R = reinterpret_cast<const uint2 *>(Q + 4 * P);
+    const uint4 q = Q[mu * P + s];
+    u[0] = as_hv2(q.x);
+    u[1] = as_hv2(q.y);
+    u[2] = as_hv2(q.z);
+    u[3] = as_hv2(q.w);
+    const uint2 r = R[mu * P + s];
+    u[4] = as_hv2(r.x);
+    u[5] = as_hv2(r.y);
+    u[6] = conj_cross_h(u[1], u[5], u[2], u[4]);
+    u[7] = conj_cross_h(u[2], u[3], u[0], u[5]);
+    u[8] = conj_cross_h(u[0], u[4], u[1], u[3]);
+}
+
+template <int MU>
+__device__ __forceinline__ void apply_A_h(hv2 v0, hv2 v1, hv2 &w0, hv2 &w1)
+{
+    if constexpr (MU == 0) {          // -i s_x: (-i v1, -i v0)
+        w0 = (hv2){v1.y, -v1.x};
+        w1 = (hv2){v0.y, -v0.x};
+    } else if constexpr (MU == 1) {   // -i s_y: (-v1, v0)
+        w0 = -v1;
+        w1 = v0;
+    } else if constexpr (MU == 2) {   // -i s_z: (-i v0, i v1)
+        w0 = (hv2){v0.y, -v0.x};
+        w1 = (hv2){-v1.y, v1.x};
+    } else {                          // 1
+        w0 = v0;
+        w1 = v1;
+    }
+}
+
+// hop_term on packed halves: psi the neighbour's stored components and sc its
+// scale, u the link (W = U_mu(x) for FWD, U_mu(x - mu) otherwise)
+template <int MU, bool FWD>
+__device__ __forceinline__ void hop_term_h(const hv2 psi[12], float sc, const hv2 u[9], cplx<float> acc[12])
+{
+    // W h = sum_b W_ab h_b: re = dot2(W_ab, (h.x, -h.y)), im = dot2(W_ab, (h.y, h.x));
+    // W^+ h = sum_b conj(W_ba) h_b: re = dot2(W_ba, h), im = dot2(W_ba, (h.y, -h.x))
+    hv2 pr[6], pi[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        hv2 a0, a1;
+        apply_A_h<MU>(psi[6 + c], psi[9 + c], a0, a1);
+        const hv2 h0 = FWD ? psi[c] - a0 : psi[c] + a0;
+        const hv2 h1 = FWD ? psi[3 + c] - a1 : psi[3 + c] + a1;
+        if constexpr (FWD) {
+            pr[c] = (hv2){h0.x, -h0.y};
+            pi[c] = h0.yx;
+            pr[3 + c] = (hv2){h1.x, -h1.y};
+            pi[3 + c] = h1.yx;
+        } else {
+            pr[c] = h0;
+            pi[c] = (hv2){h0.y, -h0.x};
+            pr[3 + c] = h1;
+            pi[3 + c] = (hv2){h1.y, -h1.x};
+        }
+    }
+    cplx<float> g[6];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const hv2 W = FWD ? u[a * 3 + b] : u[b * 3 + a];
+                re = dot2(W, pr[sp * 3 + b], re);
+                im = dot2(W, pi[sp * 3 + b], im);
+            }
+            g[sp * 3 + a] = {sc * re, sc * im};
+        }
     spin_recon<MU, FWD>(g, acc);
 }
 

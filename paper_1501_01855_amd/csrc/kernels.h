@@ -41,6 +41,9 @@ void stencil(Context &c, int epi, int prec, const void *in, void *out, int nf, d
 // links alone (read once by a launch over several fields)
 double stencil_bytes(const Geom &g, int prec, int epi);
 double stencil_link_bytes(const Geom &g, int prec);
+// FP32 / FP16 stencils on the two-row links iff the option allows it and the
+// loaded links passed the SU(3) test
+void update_link_form(Context &c);
 // the launch variant for (prec, epi, nf), autotuned on first use
 int stencil_variant(Context &c, int epi, int prec, int nf);
 // tiles (blocks per field) of stencil launch variant v; the largest over variants

@@ -117,23 +117,58 @@ def test_half_storage_of_subnormal_sites():
     ctx.close()
 
 
+def test_two_row_links_and_fallback():
+    """Links in SU(3) (Sec. 1, eq. 2) pass the test (deviation at rounding
+    level) and the FP32 / FP16 stencils read two rows per link; the result
+    matches the oracle as the full links do.  Links times the phase exp(0.3 i)
+    (unitary, determinant not 1) fail it, the full links are used, and the
+    stencils still match the oracle on those links."""
+    ovl = require_gpu()
+    dims = (4, 6, 2, 8)
+    U = synth.gauge_field(dims, 15, 0.4)
+    psi = synth.gaussian_source(dims, 7)
+    for links, two_row in ((U, True), (U * np.exp(0.3j), False)):
+        ora = WilsonKernel(dims, links, 1.4)
+        ctx = ovl.Context(dims)
+        ctx.gauge_load(to_dev(links))
+        dev, tr = ctx.gauge_info()
+        print("case two-row", two_row, "deviation", dev, flush=True)
+        assert tr == two_row
+        assert (dev < 1e-13) if two_row else (dev > 0.1)
+        h32 = to_host(ctx.wilson_dslash(to_dev(psi), prec=ovl.F32))
+        h16 = to_host(ctx.wilson_dslash(to_dev(psi), prec=ovl.HALF))
+        ref = ora.hop(psi)
+        assert max_rel_elem(h32, ref) < 2e-6
+        assert max_rel_elem(h16, ref) < 5e-3
+        if two_row:   # the same field through the full links
+            ctx.set_option(ovl.OPT_TWO_ROW_LINKS, 0)
+            assert not ctx.gauge_info()[1]
+            f32 = to_host(ctx.wilson_dslash(to_dev(psi), prec=ovl.F32))
+            assert max_rel_elem(f32, ref) < 2e-6 and rel(f32, h32) < 1e-6
+            ctx.set_option(ovl.OPT_TWO_ROW_LINKS, 1)
+            assert ctx.gauge_info()[1]
+        ctx.close()
+
+
 def _keys(prec, nf):
     # stencil launch table keys: (prec * 8 + epilogue) * 64 + field count
     return [(prec * 8 + e) * 64 + nf for e in range(4)]
 
 
+@pytest.mark.parametrize("form", ["two_row", "full"])
 @pytest.mark.parametrize("dims", [(8, 8, 8, 16), (4, 6, 2, 8)])
-def test_every_launch_variant(dims):
+def test_every_launch_variant(dims, form):
     """Every stencil launch variant (traversal order, t-marching columns, lanes
     per site, LDS tiles with 1, 2, 4, 8 time slices per block with and without
     the tile's links in LDS, grouped XCD order of several fields' tiles), forced through
     the tuning table, for the plain stencil and K
     (two fields) and for the multi-shift CG's fused K^2 + sigma / dot launch
-    (through sign(K)), in each storage precision."""
+    (through sign(K)), in each storage precision, with the FP32 / FP16 links
+    read as two rows (third rebuilt) and in full."""
     ovl = require_gpu()
     from oracle import krylov
     from oracle.zolotarev import Zolotarev
-    print("case", dims, flush=True)
+    print("case", dims, form, flush=True)
     U = synth.gauge_field(dims, 14, 0.3)
     ora = WilsonKernel(dims, U, 1.4)
     psi = np.stack([synth.gaussian_source(dims, 40), synth.z2_source(dims, 41)])
@@ -150,6 +185,9 @@ def test_every_launch_variant(dims):
         for v in variants:
             ctx = ovl.Context(dims)
             ctx.gauge_load(to_dev(U))
+            if form == "full":
+                ctx.set_option(ovl.OPT_TWO_ROW_LINKS, 0)
+            assert ctx.gauge_info()[1] == (form == "two_row")
             ctx.set_tuning({k: v for nf in (1, 2) for k in _keys(prec, nf)})
             h = to_host(ctx.wilson_dslash(to_dev(psi), prec=prec))
             k = to_host(ctx.kernel_K_apply(to_dev(psi), 1.4, prec=prec))
