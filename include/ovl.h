@@ -439,14 +439,16 @@ ovl_status ovl_gauge_info(ovl_context *ctx, double *su3_deviation, int32_t *two_
  * owning a contiguous eighth of the tiles, walked in groups of 32 (12, 13) or
  * 64 (14, 15) tiles with every field of the launch back to back inside a
  * group, so that a group's links are reused from that XCD's L2; 16 .. 19: as
- * 8 .. 11 with the tile's forward x, y, z links also staged in LDS).
+ * 8 .. 11 with the tile's forward x, y, z links also staged in LDS; 20, FP16
+ * storage only: one lane per site walking every field of the launch with the
+ * site's eight links held in registers, links read once per tile).
  * A key is (precision * 8 + epilogue) * 64 + min(field count, 63), the
  * epilogue 0 for the plain hopping term; variants run 0 .. OVL_STENCIL_VARIANTS - 1.
  * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the
  * number held; ovl_tuning_set installs pairs (a variant out of range or not
  * admissible on the context's lattice and precision is an argument error),
  * so a run can reuse another run's choices. */
-enum { OVL_STENCIL_VARIANTS = 20 };
+enum { OVL_STENCIL_VARIANTS = 21 };
 ovl_status ovl_tuning_get(ovl_context *ctx, int32_t *keys, int32_t *variants, int32_t cap, int32_t *n);
 ovl_status ovl_tuning_set(ovl_context *ctx, const int32_t *keys, const int32_t *variants, int32_t n);
 

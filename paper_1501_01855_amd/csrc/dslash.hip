@@ -531,17 +531,18 @@ __device__ __forceinline__ void stencil_epilogue(const StencilArgs<ST> &a, unsig
                 as_stored(a.out, ws, NC);
                 const ST *aux2 = a.aux2 + f * fstride<ST>(V);
                 if constexpr (TPS == 1) ld_sp(aux2, V, s, rv); else ld_sp_half(aux2, V, s, half, rv);
-                double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+                // a site's sums in the arithmetic precision, the tile's in FP64
+                R d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    const double wr = ws[c].re, wi = ws[c].im;
-                    d0 += (double)x[c].re * wr + (double)x[c].im * wi;
-                    d1 += (double)rv[c].re * wr + (double)rv[c].im * wi;
+                    const R wr = ws[c].re, wi = ws[c].im;
+                    d0 += x[c].re * wr + x[c].im * wi;
+                    d1 += rv[c].re * wr + rv[c].im * wi;
                     d2 += wr * wr + wi * wi;
                 }
-                part[0] += d0;
-                part[1] += d1;
-                part[2] += d2;
+                part[0] += (double)d0;
+                part[1] += (double)d1;
+                part[2] += (double)d2;
             } else {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) o[c] = o[c] + x[c];
@@ -593,17 +594,17 @@ __device__ __forceinline__ void stencil_epilogue_pair_h8(const StencilArgs<h8> &
         for (int c = 0; c < 6; ++c) ws[c] = o[c];
         as_stored_scaled(ws, m);
         ld_sp_half(a.aux2 + f * fstride<h8>(V), V, s, half, rv);
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+        float d0 = 0.f, d1 = 0.f, d2 = 0.f;   // a site's sums in FP32, the tile's in FP64
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            const double wr = ws[c].re, wi = ws[c].im;
-            d0 += (double)x[c].re * wr + (double)x[c].im * wi;
-            d1 += (double)rv[c].re * wr + (double)rv[c].im * wi;
+            const float wr = ws[c].re, wi = ws[c].im;
+            d0 += x[c].re * wr + x[c].im * wi;
+            d1 += rv[c].re * wr + rv[c].im * wi;
             d2 += wr * wr + wi * wi;
         }
-        part[0] += d0;
-        part[1] += d1;
-        part[2] += d2;
+        part[0] += (double)d0;
+        part[1] += (double)d1;
+        part[2] += (double)d2;
     }
     st_sp_half_scaled(out, V, s, half, o, m);
 }
@@ -681,6 +682,72 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
     else if (valid)
         stencil_epilogue<ST, EPI, TPS>(a, f, s, half, acc, part);
     store_partials<ST, EPI>(a, f, tile, part);
+}
+
+// Several fields at once with their links read once (FP16 storage): one lane
+// per site of a 256-site tile loads the site's eight links, U_mu(x) and
+// U_mu(x - mu), into registers as packed halves (the two-row form rebuilt
+// once) and then walks every field of the launch, so the links that a launch
+// over nf fields needs once are fetched once per tile instead of once per
+// field.  Tiles are lexicographic runs of 256 sites, each XCD (blocks go to
+// the eight XCDs round-robin) owning a contiguous eighth of them, so the
+// neighbouring tiles whose spinors a tile's faces read run on the same XCD.
+template <typename GT, int EPI>
+__global__ __launch_bounds__(256) void k_stencil_mf(StencilArgs<h8> a, const GT *__restrict__ U, int nf)
+{
+    const Geom &g = a.g;
+    const int64_t V = g.V, Pu = g.Pu;
+    const unsigned T = (unsigned)((V + 255) / 256), per = gridDim.x / 8;
+    const unsigned tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t s = (int64_t)tile * 256 + threadIdx.x;
+    const bool valid = tile < T && s < V;
+    hv2 u[8][9];        // U_mu(x) in u[mu], U_mu(x - mu) in u[4 + mu]
+    int64_t nb[8];      // x + mu in nb[mu], x - mu in nb[4 + mu]
+    if (valid) {
+        int64_t r = s;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const int32_t c = (int32_t)(r % g.L[mu]), Lm = g.L[mu];
+            r /= g.L[mu];
+            const int64_t st = g.stride[mu];
+            nb[mu] = (c == Lm - 1) ? s - (int64_t)(Lm - 1) * st : s + st;
+            nb[4 + mu] = (c == 0) ? s + (int64_t)(Lm - 1) * st : s - st;
+            ld_link_h(U, Pu, mu, s, u[mu]);
+            ld_link_h(U, Pu, mu, nb[4 + mu], u[4 + mu]);
+        }
+    }
+    const int it = a.itb ? *a.itb + a.it : a.it;
+#pragma unroll 1
+    for (int f = 0; f < nf; ++f) {
+        if (a.stop != nullptr && it >= a.stop[f]) continue;   // field converged (the same for the whole block)
+        double part[3] = {0.0, 0.0, 0.0};
+        if (valid) {
+            const h8 *in = a.in + f * fstride<h8>(V);
+            cplx<float> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+            hv2 w[12];
+            float sc;
+            ld_sp_h(in, V, nb[0], w, sc);
+            hop_term_h<0, true>(w, sc, u[0], acc);
+            ld_sp_h(in, V, nb[4], w, sc);
+            hop_term_h<0, false>(w, sc, u[4], acc);
+            ld_sp_h(in, V, nb[1], w, sc);
+            hop_term_h<1, true>(w, sc, u[1], acc);
+            ld_sp_h(in, V, nb[5], w, sc);
+            hop_term_h<1, false>(w, sc, u[5], acc);
+            ld_sp_h(in, V, nb[2], w, sc);
+            hop_term_h<2, true>(w, sc, u[2], acc);
+            ld_sp_h(in, V, nb[6], w, sc);
+            hop_term_h<2, false>(w, sc, u[6], acc);
+            ld_sp_h(in, V, nb[3], w, sc);
+            hop_term_h<3, true>(w, sc, u[3], acc);
+            ld_sp_h(in, V, nb[7], w, sc);
+            hop_term_h<3, false>(w, sc, u[7], acc);
+            stencil_epilogue<h8, EPI, 1>(a, f, s, 0, acc, part);
+        }
+        store_partials<h8, EPI>(a, f, tile, part);
+    }
 }
 
 // The same stencil with each thread walking a column of T = Lt / 8 sites in
@@ -1191,8 +1258,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // 14: G 64, one; 15: G 64, two).  16 .. 19 the LDS-tiled march (T = 1, 2, 4,
 // 8) with the tile's forward spatial links also staged in LDS, so that the
 // backward hop of a site inside the tile reads its neighbour's link there.
+// 20 (FP16 storage) one lane per site walking every field of the launch with
+// the site's links held in registers (k_stencil_mf).
 static constexpr int N_VARIANTS = OVL_STENCIL_VARIANTS;
-static bool variant_lds(int v) { return (v >= 8 && v < 12) || v >= 16; }
+static bool variant_lds(int v) { return (v >= 8 && v < 12) || (v >= 16 && v < 20); }
 static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7 || v == 13 || v == 15) ? 2 : 1; }
 
 // Tile of the LDS-tiled march: the 256-site box with the fewest padded sites,
@@ -1228,7 +1297,8 @@ unsigned stencil_tiles(const Geom &g, int v)
 {
     const int tps = variant_tps(v);
     const int spb = 256 / tps;
-    if (v >= 12 && v < 16) return 8u * (unsigned)(((g.V + spb - 1) / spb + 7) / 8);   // 8 XCDs x their largest share
+    if ((v >= 12 && v < 16) || v == 20)
+        return 8u * (unsigned)(((g.V + spb - 1) / spb + 7) / 8);   // 8 XCDs x their largest share
     if (variant_lds(v)) {
         const TileShape ts = tile_shape(g, v);
         return (unsigned)(ts.n[0] * ts.n[1] * ts.n[2] * ts.nch);
@@ -1244,6 +1314,7 @@ bool stencil_variant_ok(const Geom &g, int prec, int v)
     if ((v == 4 || v == 5) && !g.col_ok) return false;
     if ((v == 6 || v == 7) && g.L[3] % 8 != 0) return false;
     if (variant_lds(v)) return prec != OVL_F64 && g.L[3] % (1 << (v >= 16 ? v - 16 : v - 8)) == 0;
+    if (v == 20) return prec == OVL_HALF;
     return true;
 }
 
@@ -1251,7 +1322,8 @@ int64_t stencil_tiles_max(const Geom &g)
 {
     int64_t m = 0;
     for (int v = 0; v < N_VARIANTS; ++v)
-        if (stencil_variant_ok(g, OVL_F64, v) || stencil_variant_ok(g, OVL_F32, v))
+        if (stencil_variant_ok(g, OVL_F64, v) || stencil_variant_ok(g, OVL_F32, v) ||
+            stencil_variant_ok(g, OVL_HALF, v))
             m = std::max<int64_t>(m, stencil_tiles(g, v));
     return m;
 }
@@ -1308,6 +1380,12 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
         case 13: launch_variant<ST, GT, EPI, 2, MAP_GRP32>(c, a, U, nf, pe); break;
         case 14: launch_variant<ST, GT, EPI, 1, MAP_GRP64>(c, a, U, nf, pe); break;
         case 15: launch_variant<ST, GT, EPI, 2, MAP_GRP64>(c, a, U, nf, pe); break;
+        case 20:
+            if constexpr (std::is_same<ST, h8>::value)
+                launch_k(c, pe, k_stencil_mf<GT, EPI>, dim3(stencil_tiles(c.g, 20)), dim3(256), 0, a, U, nf);
+            else
+                throw Error{OVL_ERR_ARG, "stencil variant 20 is for FP16 storage"};
+            break;
         default: launch_tmarch<ST, GT, EPI, 2>(c, a, U, nf, pe); break;
         }
     }

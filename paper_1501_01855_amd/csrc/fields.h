@@ -469,7 +469,10 @@ __device__ __forceinline__ void hop_term(const cplx<R> psi[12], const cplx<R> u[
 // against converting everything to FP32 first.
 typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ hv2 as_hv2(uint32_t w) { return __builtin_bit_cast(hv2, w); }
-__device__ __forceinline__ float dot2(hv2 a, hv2 b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+
+// d = w.x h.x + w.y h.y + c with the half products exact in FP32
+// (v_dot2_f32_f16; through the builtin, so that the compiler schedules it).
+__device__ __forceinline__ float dot2(hv2 w, hv2 h, float c) { return __builtin_amdgcn_fdot2(w, h, c, false); }
 
 // an FP16-stored site: its 12 components as packed halves, and its scale
 __device__ __forceinline__ void ld_sp_h(const h8 *__restrict__ p, int64_t V, int64_t s, hv2 w[12], float &sc)
@@ -547,28 +550,29 @@ __device__ __forceinline__ void apply_A_h(hv2 v0, hv2 v1, hv2 &w0, hv2 &w1)
 template <int MU, bool FWD>
 __device__ __forceinline__ void hop_term_h(const hv2 psi[12], float sc, const hv2 u[9], cplx<float> acc[12])
 {
+    // With h = psi_up -+ A psi_down (the upper half of (1 -+ gamma_mu) psi):
     // W h = sum_b W_ab h_b: re = dot2(W_ab, (h.x, -h.y)), im = dot2(W_ab, (h.y, h.x));
-    // W^+ h = sum_b conj(W_ba) h_b: re = dot2(W_ba, h), im = dot2(W_ba, (h.y, -h.x))
+    // W^+ h = sum_b conj(W_ba) h_b: re = dot2(W_ba, h), im = dot2(W_ba, (h.y, -h.x)).
+    // Each operand form is one packed add of psi_up and A psi_down, written
+    // out from the two (not from h) so that the swaps and signs become its
+    // source modifiers.
     hv2 pr[6], pi[6];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        hv2 a0, a1;
-        apply_A_h<MU>(psi[6 + c], psi[9 + c], a0, a1);
-        const hv2 h0 = FWD ? psi[c] - a0 : psi[c] + a0;
-        const hv2 h1 = FWD ? psi[3 + c] - a1 : psi[3 + c] + a1;
-        if constexpr (FWD) {
-            pr[c] = (hv2){h0.x, -h0.y};
-            pi[c] = h0.yx;
-            pr[3 + c] = (hv2){h1.x, -h1.y};
-            pi[3 + c] = h1.yx;
-        } else {
-            pr[c] = h0;
-            pi[c] = (hv2){h0.y, -h0.x};
-            pr[3 + c] = h1;
-            pi[3 + c] = (hv2){h1.y, -h1.x};
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            hv2 a0, a1;
+            apply_A_h<MU>(psi[6 + c], psi[9 + c], a0, a1);
+            const hv2 up = psi[3 * k + c], ad = k == 0 ? a0 : a1;
+            if constexpr (FWD) {   // h = up - ad
+                pr[3 * k + c] = (hv2){up.x, -up.y} - (hv2){ad.x, -ad.y};
+                pi[3 * k + c] = (hv2){up.y, up.x} - (hv2){ad.y, ad.x};
+            } else {               // h = up + ad
+                pr[3 * k + c] = up + ad;
+                pi[3 * k + c] = (hv2){up.y, -up.x} + (hv2){ad.y, -ad.x};
+            }
         }
-    }
-    cplx<float> g[6];
+    cplx<float> g[6];   // W h (FWD) or W^+ h, times the neighbour's scale
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll

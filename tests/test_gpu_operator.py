@@ -160,7 +160,8 @@ def _keys(prec, nf):
 def test_every_launch_variant(dims, form):
     """Every stencil launch variant (traversal order, t-marching columns, lanes
     per site, LDS tiles with 1, 2, 4, 8 time slices per block with and without
-    the tile's links in LDS, grouped XCD order of several fields' tiles), forced through
+    the tile's links in LDS, grouped XCD order of several fields' tiles, all
+    fields of a tile in one lane with its links in registers), forced through
     the tuning table, for the plain stencil and K
     (two fields) and for the multi-shift CG's fused K^2 + sigma / dot launch
     (through sign(K)), in each storage precision, with the FP32 / FP16 links
@@ -179,7 +180,7 @@ def test_every_launch_variant(dims, form):
     tol = {ovl.F64: 1e-14, ovl.F32: 2e-6, ovl.HALF: 5e-3}
     for prec in (ovl.F64, ovl.F32, ovl.HALF):
         variants = {ovl.F64: list(range(8)) + [12, 13, 14, 15], ovl.F32: list(range(20)),
-                    ovl.HALF: list(range(20))}[prec]
+                    ovl.HALF: list(range(21))}[prec]
         if dims == (4, 6, 2, 8):   # no split of x, y, z into 8 columns: 4 and 5 unavailable
             variants = [v for v in variants if v not in (4, 5)]
         for v in variants:
