@@ -38,6 +38,7 @@ sys.path.insert(0, HERE)
 
 METRIC = "overlap solves/s at 1e-10 resid (mixed vs FP64) + Dslash HBM GB/s % peak"
 HBM_PEAK_GBS = 8000.0
+VALU_ISSUE_PEAK = 256 * 2.4   # G wave instructions/s: 256 CUs, one vector wave instruction per clock each
 DIMS = (16, 16, 16, 32)
 RHO, MU, NZ, NLOW, TOL = 1.4, 0.02, 20, 10, 1e-10
 # middle-solve accuracy of GMRESR for the 16^3 x 32 workload, tuned as Alg. 3
@@ -210,9 +211,10 @@ def kernel_summary(prof):
     return out
 
 
-def read_traffic(name, path):
-    """HBM bytes per launch of kernel slot `name` from the committed
-    hardware-counter summary, if it was taken on the current kernel sources."""
+def read_counter(kind, name, path):
+    """A per-launch figure of kernel slot `name` from the committed
+    hardware-counter summary (kind "traffic": HBM-side bytes; "valu": vector
+    wave instructions), if it was taken on the current kernel sources."""
     try:
         with open(path) as fh:
             lines = fh.read().splitlines()
@@ -224,9 +226,14 @@ def read_traffic(name, path):
         return None, "kernel sources changed since the counters were taken"
     for ln in lines:
         f = ln.split()
-        if len(f) >= 3 and f[0] == "traffic" and f[1] == name:
-            return float(f[2]), "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, calibrated"
+        if len(f) >= 3 and f[0] == kind and f[1] == name:
+            return float(f[2]), ("rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, calibrated" if kind == "traffic"
+                                 else "rocprofv3 --pmc SQ_INSTS_VALU")
     return None, "slot not in the counter summary"
+
+
+def read_traffic(name, path):
+    return read_counter("traffic", name, path)
 
 
 def uneven_leg(torch, ovl):
@@ -872,10 +879,16 @@ def main():
     dom = max(ks, key=lambda k: ks[k]["ms"])
     d = ks[dom]
     traffic, traffic_note = read_traffic(dom, TRAFFIC_C3)
+    valu, valu_note = read_counter("valu", dom, TRAFFIC_C3)
+    issue = None
+    if valu is not None:   # vector instruction issue: one wave instruction per clock per CU
+        rate = valu / (d["avg_us"] * 1e-6) / 1e9
+        issue = {"valu_wave_instructions_per_launch": valu, "achieved": rate, "peak": VALU_ISSUE_PEAK,
+                 "unit": "G wave-instructions/s", "frac": rate / VALU_ISSUE_PEAK, "source": valu_note}
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": d["bytes_per_launch"], "avg_us": d["avg_us"],
-                "traffic_note": traffic_note,
+                "traffic_note": traffic_note, "issue": issue,
                 "working_set": "24^3x48: the multi-shift CG's fields (25 x 34.5 MB in FP16 storage) and links "
                                "exceed the 256 MB Infinity Cache"}
     t_total = c3.pop("seconds_timed")
