@@ -67,9 +67,11 @@ def parse():
     ap.add_argument("--half-threshold", type=float, default=3e-3,
                     help="16^3x32 leg: sign accuracies at or above this use FP16 storage (> 1 disables)")
     ap.add_argument("--c3-eta", type=float, default=3e-3, help="24^3x48: middle-solve accuracy eta~ of GMRESR")
-    ap.add_argument("--eig-calc", type=int, default=6, help="24^3x48: eigSUMR calculating solves")
+    ap.add_argument("--relax-cap", type=float, default=1e-2,
+                    help="24^3x48: loosest sign accuracy of the relaxed middle solves (Sec. 3: tuned per ensemble)")
+    ap.add_argument("--eig-calc", type=int, default=4, help="24^3x48: eigSUMR calculating solves")
     ap.add_argument("--eig-n", type=int, default=20, help="24^3x48: eigenvectors kept (n)")
-    ap.add_argument("--eig-m", type=int, default=100, help="24^3x48: basis size of Alg. 6 (m)")
+    ap.add_argument("--eig-m", type=int, default=160, help="24^3x48: basis size of Alg. 6 (m)")
     ap.add_argument("--eig-eps", type=float, default=1e-4, help="24^3x48: target eigenvector accuracy (Sec. 6)")
     ap.add_argument("--eig-block", action="store_true",
                     help="24^3x48: the calculating solves as one batched call collecting into one basis "
@@ -574,7 +576,7 @@ def c3_setup(torch, ovl, tuning=None, full_links=False):
 
 
 def c3_params(ovl, args, mixed=True, calc=0, defl=1, block=0):
-    return ovl.solver_defaults(rho=RHO, mu=C3_MU, tol=TOL, eta_tilde=args.c3_eta, relax_floor=1e-2,
+    return ovl.solver_defaults(rho=RHO, mu=C3_MU, tol=TOL, eta_tilde=args.c3_eta, relax_floor=args.relax_cap,
                                f32_threshold=(1e-6 if mixed else 10.0), half_threshold=(3e-3 if mixed else 10.0),
                                max_outer=16, max_middle=6000, max_mscg=20000, use_deflation=defl, eig_calc=calc,
                                n_eig=args.eig_n, m_eig=args.eig_m, eig_eps=args.eig_eps, eig_block=block)
@@ -861,6 +863,10 @@ def cpu_baseline_c3(mscg_iters_per_solve, samples=3, iters=6):
 
 def main():
     args = parse()
+    if not 1 <= args.eig_calc <= 11:
+        print("bench.py: --eig-calc takes 1 .. 11 (the twelve spin-colour sources, at least one left to time)",
+              file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU (no multi-GPU path); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
