@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--half-threshold", type=float, default=3e-3,
                     help="16^3x32 leg: sign accuracies at or above this use FP16 storage (> 1 disables)")
     ap.add_argument("--c3-eta", type=float, default=3e-3, help="24^3x48: middle-solve accuracy eta~ of GMRESR")
-    ap.add_argument("--relax-cap", type=float, default=1e-2,
+    ap.add_argument("--relax-cap", type=float, default=3e-2,
                     help="24^3x48: loosest sign accuracy of the relaxed middle solves (Sec. 3: tuned per ensemble)")
     ap.add_argument("--eig-calc", type=int, default=4, help="24^3x48: eigSUMR calculating solves")
     ap.add_argument("--eig-n", type=int, default=20, help="24^3x48: eigenvectors kept (n)")
