@@ -69,9 +69,9 @@ def parse():
     ap.add_argument("--c3-eta", type=float, default=3e-3, help="24^3x48: middle-solve accuracy eta~ of GMRESR")
     ap.add_argument("--relax-cap", type=float, default=3e-2,
                     help="24^3x48: loosest sign accuracy of the relaxed middle solves (Sec. 3: tuned per ensemble)")
-    ap.add_argument("--eig-calc", type=int, default=4, help="24^3x48: eigSUMR calculating solves")
+    ap.add_argument("--eig-calc", type=int, default=3, help="24^3x48: eigSUMR calculating solves")
     ap.add_argument("--eig-n", type=int, default=20, help="24^3x48: eigenvectors kept (n)")
-    ap.add_argument("--eig-m", type=int, default=160, help="24^3x48: basis size of Alg. 6 (m)")
+    ap.add_argument("--eig-m", type=int, default=200, help="24^3x48: basis size of Alg. 6 (m)")
     ap.add_argument("--eig-eps", type=float, default=1e-4, help="24^3x48: target eigenvector accuracy (Sec. 6)")
     ap.add_argument("--eig-block", action="store_true",
                     help="24^3x48: the calculating solves as one batched call collecting into one basis "

@@ -440,8 +440,8 @@ ovl_status ovl_gauge_info(ovl_context *ctx, double *su3_deviation, int32_t *two_
  * 64 (14, 15) tiles with every field of the launch back to back inside a
  * group, so that a group's links are reused from that XCD's L2; 16 .. 19: as
  * 8 .. 11 with the tile's forward x, y, z links also staged in LDS; 20, FP16
- * storage only: one lane per site walking every field of the launch with the
- * site's eight links held in registers, links read once per tile).
+ * storage only: one lane per site walking a group of four fields with the
+ * site's eight links held in registers, links read once per tile and group).
  * A key is (precision * 8 + epilogue) * 64 + min(field count, 63), the
  * epilogue 0 for the plain hopping term; variants run 0 .. OVL_STENCIL_VARIANTS - 1.
  * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the

@@ -684,14 +684,18 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
     store_partials<ST, EPI>(a, f, tile, part);
 }
 
-// Several fields at once with their links read once (FP16 storage): one lane
-// per site of a 256-site tile loads the site's eight links, U_mu(x) and
-// U_mu(x - mu), into registers as packed halves (the two-row form rebuilt
-// once) and then walks every field of the launch, so the links that a launch
-// over nf fields needs once are fetched once per tile instead of once per
-// field.  Tiles are lexicographic runs of 256 sites, each XCD (blocks go to
+// Several fields at once with their links read once per group of fields
+// (FP16 storage): one lane per site of a 256-site tile loads the site's eight
+// links, U_mu(x) and U_mu(x - mu), into registers as packed halves (the
+// two-row form rebuilt once) and then walks the MF_GROUP fields of its block
+// (grid y), so a launch over nf fields fetches each link nf / MF_GROUP times
+// instead of nf times, while the blocks in flight (all tiles of one group
+// before the next) work on the same fields and meet each other's face
+// spinors in L2.  Tiles are lexicographic runs of 256 sites, each XCD (blocks go to
 // the eight XCDs round-robin) owning a contiguous eighth of them, so the
 // neighbouring tiles whose spinors a tile's faces read run on the same XCD.
+static constexpr int MF_GROUP = 4;   // fields per block of the multi-field stencil
+
 template <typename GT, int EPI>
 __global__ __launch_bounds__(256) void k_stencil_mf(StencilArgs<h8> a, const GT *__restrict__ U, int nf)
 {
@@ -717,8 +721,9 @@ __global__ __launch_bounds__(256) void k_stencil_mf(StencilArgs<h8> a, const GT 
         }
     }
     const int it = a.itb ? *a.itb + a.it : a.it;
+    const int f0 = (int)blockIdx.y * MF_GROUP, f1 = f0 + MF_GROUP < nf ? f0 + MF_GROUP : nf;
 #pragma unroll 1
-    for (int f = 0; f < nf; ++f) {
+    for (int f = f0; f < f1; ++f) {
         if (a.stop != nullptr && it >= a.stop[f]) continue;   // field converged (the same for the whole block)
         double part[3] = {0.0, 0.0, 0.0};
         if (valid) {
@@ -1258,8 +1263,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // 14: G 64, one; 15: G 64, two).  16 .. 19 the LDS-tiled march (T = 1, 2, 4,
 // 8) with the tile's forward spatial links also staged in LDS, so that the
 // backward hop of a site inside the tile reads its neighbour's link there.
-// 20 (FP16 storage) one lane per site walking every field of the launch with
-// the site's links held in registers (k_stencil_mf).
+// 20 (FP16 storage) one lane per site walking a group of four fields with the
+// site's links held in registers (k_stencil_mf).
 static constexpr int N_VARIANTS = OVL_STENCIL_VARIANTS;
 static bool variant_lds(int v) { return (v >= 8 && v < 12) || (v >= 16 && v < 20); }
 static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7 || v == 13 || v == 15) ? 2 : 1; }
@@ -1382,7 +1387,8 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
         case 15: launch_variant<ST, GT, EPI, 2, MAP_GRP64>(c, a, U, nf, pe); break;
         case 20:
             if constexpr (std::is_same<ST, h8>::value)
-                launch_k(c, pe, k_stencil_mf<GT, EPI>, dim3(stencil_tiles(c.g, 20)), dim3(256), 0, a, U, nf);
+                launch_k(c, pe, k_stencil_mf<GT, EPI>, dim3(stencil_tiles(c.g, 20), (nf + MF_GROUP - 1) / MF_GROUP),
+                         dim3(256), 0, a, U, nf);
             else
                 throw Error{OVL_ERR_ARG, "stencil variant 20 is for FP16 storage"};
             break;
