@@ -689,9 +689,8 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
 // links, U_mu(x) and U_mu(x - mu), into registers as packed halves (the
 // two-row form rebuilt once) and then walks the MF_GROUP fields of its block
 // (grid y), so a launch over nf fields fetches each link nf / MF_GROUP times
-// instead of nf times, while the blocks in flight (all tiles of one group
-// before the next) work on the same fields and meet each other's face
-// spinors in L2.  Tiles are lexicographic runs of 256 sites, each XCD (blocks go to
+// instead of nf times (and the launch has nf / MF_GROUP times more blocks
+// than with every field in one block).  Tiles are lexicographic runs of 256 sites, each XCD (blocks go to
 // the eight XCDs round-robin) owning a contiguous eighth of them, so the
 // neighbouring tiles whose spinors a tile's faces read run on the same XCD.
 static constexpr int MF_GROUP = 4;   // fields per block of the multi-field stencil
