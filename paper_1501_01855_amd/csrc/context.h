@@ -53,6 +53,7 @@ struct Context {
     hipStream_t stream = nullptr;
     int device = 0;
     int num_cu = 256;
+    int upd_per_cu[3][2] = {};   // resident blocks per CU of the multi-shift update kernel [prec][all]
 
     // gauge field, packed per precision
     double2 *U64 = nullptr;   // [4][9][Pu] (Geom::Pu: padded plane stride)

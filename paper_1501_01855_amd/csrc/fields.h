@@ -180,6 +180,52 @@ __device__ __forceinline__ void st_sp(h8 *__restrict__ p, int64_t V, int64_t s, 
     reinterpret_cast<float *>(p + 3 * V)[s] = m;
 }
 
+// One site's spinor as stored, for loads issued well before their values are
+// needed (sp_values then gives what ld_sp would have).
+template <typename ST> struct SpStored;
+template <> struct SpStored<double2> { double2 q[12]; };
+template <> struct SpStored<float4> { float4 q[6]; };
+template <> struct SpStored<h8> { uint4 q[3]; float sc; };
+
+template <typename ST>
+__device__ __forceinline__ void ld_sp_stored(const ST *__restrict__ p, int64_t V, int64_t s, SpStored<ST> &r)
+{
+    if constexpr (std::is_same<ST, h8>::value) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r.q[k] = p[k * V + s].v;
+        r.sc = reinterpret_cast<const float *>(p + 3 * V)[s];
+    } else {
+#pragma unroll
+        for (int k = 0; k < Planes<ST>::n; ++k) r.q[k] = p[k * V + s];
+    }
+}
+__device__ __forceinline__ void sp_values(const SpStored<double2> &r, cplx<double> v[12])
+{
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = {r.q[c].x, r.q[c].y};
+}
+__device__ __forceinline__ void sp_values(const SpStored<float4> &r, cplx<float> v[12])
+{
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        v[2 * k] = {r.q[k].x, r.q[k].y};
+        v[2 * k + 1] = {r.q[k].z, r.q[k].w};
+    }
+}
+__device__ __forceinline__ void sp_values(const SpStored<h8> &r, cplx<float> v[12])
+{
+    const float sc = r.sc;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint4 t = r.q[k];
+        const float2 a = h2f2(t.x), b = h2f2(t.y), c = h2f2(t.z), d = h2f2(t.w);
+        v[4 * k] = {a.x * sc, a.y * sc};
+        v[4 * k + 1] = {b.x * sc, b.y * sc};
+        v[4 * k + 2] = {c.x * sc, c.y * sc};
+        v[4 * k + 3] = {d.x * sc, d.y * sc};
+    }
+}
+
 // Half of an FP16-stored spinor (two lanes per site): half 0 holds complex
 // components 0..5 (plane 0 and the low half of plane 1), half 1 components
 // 6..11 (the high half of plane 1 and plane 2).  The site's scale is shared,

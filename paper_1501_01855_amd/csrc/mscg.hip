@@ -31,7 +31,6 @@
 
 namespace ovl {
 
-static constexpr int UPD_BLOCKS = 1024;   // grid of the update kernels (grid-stride over sites)
 
 struct MscgFinal {
     int iters, breakdown, act_total, pad;
@@ -139,19 +138,42 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
     const MscgScal &sc = S[(it & 1) * nf + f];
     const int64_t fo = f * fstride<ST>(V);
     const int64_t s0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    // the four sums of partials, their loads issued in one pass (each sum in
-    // the same per-thread order as a separate pass)
+    // The first site's r and w do not depend on the step's scalars: their
+    // loads go out before the sums of partials, and arrive during them.
+    SpStored<ST> r_first, w_first;
+    if (s0 < V) {
+        ld_sp_stored((it == 0 ? src : rin) + fo, V, s0, r_first);
+        ld_sp_stored(w + fo, V, s0, w_first);
+    }
+    // The four sums of partials.  Each thread adds its terms in index order;
+    // the loads of PB consecutive terms of each sum are issued together (an
+    // index past the end reads the last entry, and adds nothing).
     const double *pf = part + (int64_t)f * 3 * pw_n;
     const double *rf = rr_in + (int64_t)f * rr_n;
     double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
     const int nmax = pw_n > rr_n ? pw_n : rr_n;
-    for (int i = threadIdx.x; i < nmax; i += blockDim.x) {
-        if (i < pw_n) {
-            v0 += pf[i];
-            v1 += pf[pw_n + i];
-            v2 += pf[2 * pw_n + i];
+    constexpr int PB = 8;
+    for (int i0 = threadIdx.x; i0 < nmax; i0 += PB * blockDim.x) {
+        double a0[PB], a1[PB], a2[PB], a3[PB];
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+            const int i = i0 + q * (int)blockDim.x;
+            const int ip = i < pw_n ? i : pw_n - 1, ir = i < rr_n ? i : rr_n - 1;
+            a0[q] = pf[ip];
+            a1[q] = pf[pw_n + ip];
+            a2[q] = pf[2 * pw_n + ip];
+            a3[q] = rf[ir];
         }
-        if (it != 0 && i < rr_n) v3 += rf[i];
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+            const int i = i0 + q * (int)blockDim.x;
+            if (i < pw_n) {
+                v0 += a0[q];
+                v1 += a1[q];
+                v2 += a2[q];
+            }
+            if (it != 0 && i < rr_n) v3 += a3[q];
+        }
     }
     double vv[4] = {v0, v1, v2, v3}, tot[4];
     block_bcast_sum4(vv, tot);
@@ -217,10 +239,9 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
     const int64_t pstride = nf * fstride<ST>(V);   // shift-major: p[l][f]
     const R ar = (R)alpha;
     double rn = 0.0;
-    for (int64_t s = s0; s < V; s += (int64_t)gridDim.x * blockDim.x) {
-        cplx<R> rv[12], yv[12], pv[12];
-        ld_sp((it == 0 ? src : rin) + fo, V, s, rv);
-        ld_sp(w + fo, V, s, pv);
+    // one site, from its loaded r and w
+    auto site = [&](int64_t s, cplx<R> (&rv)[12], cplx<R> (&pv)[12]) {
+        cplx<R> yv[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) rv[c] = rv[c] - ar * pv[c];
         st_sp(r + fo, V, s, rv);
@@ -261,6 +282,19 @@ __global__ __launch_bounds__(256) void k_mscg_shift(const ST *__restrict__ src, 
             st_sp(pl, V, s, nv);
         }
         if constexpr (!ALL) st_sp(y + fo, V, s, yv);
+    };
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    if (s0 < V) {
+        cplx<R> rv[12], pv[12];
+        sp_values(r_first, rv);
+        sp_values(w_first, pv);
+        site(s0, rv, pv);
+    }
+    for (int64_t s = s0 + step; s < V; s += step) {
+        cplx<R> rv[12], pv[12];
+        ld_sp((it == 0 ? src : rin) + fo, V, s, rv);
+        ld_sp(w + fo, V, s, pv);
+        site(s, rv, pv);
     }
     const double t = block_sum<256>(rn, lds);
     if (threadIdx.x == 0) rr_out[(int64_t)f * gridDim.x + blockIdx.x] = t;
@@ -423,6 +457,22 @@ static hipGraphExec_t chunk_graph(Context &c, int prec, int nf, bool all, int ch
 // out = sign(K) in, or (xs != nullptr) every shifted solution
 // xs[l][f] = (K^2 + sigma_l)^{-1} in_f, each to |zeta_l| ||r|| <= eta_f ||in_f||,
 // with no low-mode split and no final K.
+//
+// The update kernel's grid is the number of its blocks resident on the device
+// at once: it strides over the sites, and a larger grid would leave a partial
+// second round of blocks running after the first.
+template <typename ST, bool ALL>
+static unsigned upd_blocks(Context &c, int prec)
+{
+    int &n = c.upd_per_cu[prec][ALL ? 1 : 0];
+    if (n == 0) {
+        int b = 0;
+        OVL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_mscg_shift<ST, ALL>, 256, 0));
+        n = b > 0 ? b : 1;
+    }
+    return (unsigned)(n * c.num_cu);
+}
+
 template <typename ST>
 static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, void *out, int nf,
                    const double *eta, int prec, int maxiter, ovl_stats *st, void *xs = nullptr)
@@ -434,7 +484,7 @@ static void sign_t(Context &c, double rho, const ovl_zolo &z, const void *in, vo
     const unsigned nblk = site_blocks(g);
     const unsigned nblk_max = (unsigned)stencil_tiles_max(g);   // tiles of any stencil variant
     const dim3 grid(nblk, nf);
-    const unsigned nupd = std::min<unsigned>(UPD_BLOCKS, nblk);
+    const unsigned nupd = std::min<unsigned>(all ? upd_blocks<ST, true>(c, prec) : upd_blocks<ST, false>(c, prec), nblk);
     const dim3 ugrid(nupd, nf);
     const int nz = z.n_z;
     OVL_REQUIRE(nz >= 1 && nz <= NZMAX, OVL_ERR_ARG, "n_z out of range");
