@@ -412,9 +412,15 @@ ovl_status ovl_stream_bench(ovl_context *ctx, int32_t kind, const void *src_dev,
  *                    the 18 reals of each link and rebuild the third row as
  *                    the conjugate cross product of the first two, when every
  *                    loaded link passes the SU(3) test of ovl_gauge_info
- *                    (otherwise, or with the option off, the full links). */
+ *                    (otherwise, or with the option off, the full links).
+ *   OVL_OPT_OUTER_PRINTED (default off) the GMRESR outer product c = D u
+ *                    (Alg. 3) to the accuracy the algorithm prints,
+ *                    ||D u - c|| < eps ||b|| ||u|| / ||r||: the sign function
+ *                    to 2 eps ||b|| / ((1 - mu) ||r||), looser as the outer
+ *                    residual r falls; off: ||D u - c|| <= eps ||b|| / 4 at
+ *                    every outer step. */
 enum { OVL_OPT_GRAPHS = 1, OVL_OPT_AUTOTUNE = 2, OVL_OPT_ADAPTIVE_NZ = 3, OVL_OPT_BOUND_PRINTED = 4,
-       OVL_OPT_TWO_ROW_LINKS = 5 };
+       OVL_OPT_TWO_ROW_LINKS = 5, OVL_OPT_OUTER_PRINTED = 6 };
 ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value);
 
 /* The loaded links (Sec. 1, eq. 2: U_mu(x) in SU(3)).  *su3_deviation

@@ -746,7 +746,9 @@ ovl_status ovl_set_option(ovl_context *ctx, int32_t option, int32_t value)
         else if (option == OVL_OPT_TWO_ROW_LINKS) {
             ctx->two_row_opt = value != 0;
             update_link_form(*ctx);
-        } else
+        } else if (option == OVL_OPT_OUTER_PRINTED)
+            ctx->outer_printed = value != 0;
+        else
             throw Error{OVL_ERR_ARG, "unknown option"};
     });
 }

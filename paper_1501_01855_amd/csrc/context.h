@@ -113,6 +113,8 @@ struct Context {
     // sign calls inside the solvers take as few Zolotarev poles as their
     // accuracy allows (coefficients per pole count for the interval zolo_ab)
     bool adaptive_nz = false;
+    // the GMRESR outer products to the accuracy Alg. 3 prints (OVL_OPT_OUTER_PRINTED)
+    bool outer_printed = false;
     std::map<int, ovl_zolo> zolo_by_n;
     double zolo_ab[2] = {0.0, 0.0};
 

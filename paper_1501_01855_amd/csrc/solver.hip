@@ -674,13 +674,19 @@ ovl_status solve_batch(Context &c, const ovl_zolo &z, const ovl_solver_params &p
                 eig_recompute(c, rhoK, z, 1e-12, nullptr);
         }
         }
-        // c = D u, to ||D u - c|| <= eps ||b|| / 4
+        // c = D u, to ||D u - c|| <= eps ||b|| / 4, or with the option to the
+        // accuracy Alg. 3 prints, ||D u - c|| < eps ||b|| ||u|| / ||r||.  Since
+        // D u - c = (1 - mu)/2 gamma_5 (sign(K) u - s) for a sign approximation
+        // s to relative accuracy eta, these are eta = eps ||b|| / (2 (1 - mu) ||u||)
+        // and eta = 2 eps ||b|| / ((1 - mu) ||r||).
         std::vector<double> un;
-        norms(c, uu, nf, un);
+        if (!c.outer_printed) norms(c, uu, nf, un);
         std::vector<double> eta_c(nf, 0.0);
         for (int f = 0; f < nf; ++f)
             if (active[f])
-                eta_c[f] = std::fmin(1e-2, prm.tol * bn[f] / (2.0 * (1.0 - mu) * std::max(un[f], 1e-300)));
+                eta_c[f] = std::fmin(1e-2, c.outer_printed
+                                               ? 2.0 * prm.tol * bn[f] / ((1.0 - mu) * std::max(rn[f], 1e-300))
+                                               : prm.tol * bn[f] / (2.0 * (1.0 - mu) * std::max(un[f], 1e-300)));
         overlap_impl(c, rhoK, mu, z, uu, cv, nf, eta_c.data(), prec_for(prm, min_active(eta_c.data(), nf)),
                      prm.max_mscg, st, true);
         // modified Gram-Schmidt against C[0..i)

@@ -210,3 +210,32 @@ def test_solve_adaptive_poles(c1):
         ctx.close()
     print("multi-shift iterations, fixed / adaptive poles:", iters)
     assert iters[True] < iters[False]
+
+
+def test_solve_outer_accuracy_printed(c1):
+    """The GMRESR outer products at the accuracy Alg. 3 prints: each step may
+    move the true residual from the computed one by ||A u - c|| |alpha| / ||c||
+    < eps ||b|| ||u|| / ||c|| <= eps ||b|| / mu (the eigenvalues of D(mu) are at
+    least mu in modulus), so after k steps it is within eps ||b|| (1 + k / mu);
+    with the default eps ||b|| / 4 it stays <= 1e-10.  The printed bound asks
+    for no more FP64 work than the default."""
+    ovl = require_gpu()
+    ctx, zg = _ctx(ovl, c1)
+    mu, tol = 0.05, 1e-10
+    b = synth.point_source(c1.dims)
+    p = ovl.solver_defaults(rho=1.4, mu=mu, tol=tol, eta_tilde=1e-3, f32_threshold=1e-6)
+    D = krylov.Overlap(c1.sign, mu)
+    res, f64_calls = {}, {}
+    for mode in (0, 1):
+        ctx.set_option(ovl.OPT_OUTER_PRINTED, mode)
+        x, st, code = ctx.solve(to_dev(b), zg, p)
+        assert code == 0
+        s = st[0]
+        assert s.computed_relres <= tol
+        res[mode] = norm(b - D(to_host(x), 1e-15)) / norm(b)
+        f64_calls[mode] = s.dslash_calls[0]
+        k = s.gmresr_steps
+    assert res[0] <= tol
+    assert res[1] <= tol * (1.0 + k / mu)
+    assert f64_calls[1] <= f64_calls[0]
+    print("true residuals", res, "FP64 stencil calls", f64_calls)
