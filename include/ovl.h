@@ -447,14 +447,16 @@ ovl_status ovl_gauge_info(ovl_context *ctx, double *su3_deviation, int32_t *two_
  * group, so that a group's links are reused from that XCD's L2; 16 .. 19: as
  * 8 .. 11 with the tile's forward x, y, z links also staged in LDS; 20, FP16
  * storage only: one lane per site walking a group of four fields with the
- * site's eight links held in registers, links read once per tile and group).
+ * site's eight links held in registers, links read once per tile and group;
+ * 21, FP16 storage only: as 20 in the XCD column order of 4/5, the groups one
+ * after another, when the x, y, z extents split into 8 columns).
  * A key is (precision * 8 + epilogue) * 64 + min(field count, 63), the
  * epilogue 0 for the plain hopping term; variants run 0 .. OVL_STENCIL_VARIANTS - 1.
  * ovl_tuning_get copies up to cap (key, variant) pairs and sets *n to the
  * number held; ovl_tuning_set installs pairs (a variant out of range or not
  * admissible on the context's lattice and precision is an argument error),
  * so a run can reuse another run's choices. */
-enum { OVL_STENCIL_VARIANTS = 21 };
+enum { OVL_STENCIL_VARIANTS = 22 };
 ovl_status ovl_tuning_get(ovl_context *ctx, int32_t *keys, int32_t *variants, int32_t cap, int32_t *n);
 ovl_status ovl_tuning_set(ovl_context *ctx, const int32_t *keys, const int32_t *variants, int32_t n);
 

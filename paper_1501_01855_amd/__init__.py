@@ -19,7 +19,7 @@ F64, F32, HALF = 0, 1, 2
 SRC_POINT, SRC_GAUSS, SRC_Z2 = 0, 1, 2
 MAX_NZ = 64
 KERN_STENCIL, KERN_SHIFT = 0, 1
-N_STENCIL_VARIANTS = 21   # launch variants of the stencil (tuning-table values 0 .. 20)
+N_STENCIL_VARIANTS = 22   # launch variants of the stencil (tuning-table values 0 .. 21)
 OPT_GRAPHS, OPT_AUTOTUNE, OPT_ADAPTIVE_NZ, OPT_BOUND_PRINTED, OPT_TWO_ROW_LINKS, OPT_OUTER_PRINTED = 1, 2, 3, 4, 5, 6
 
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_NOMEM", -4: "ERR_NOT_CONVERGED",

@@ -690,20 +690,45 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<ST> a, const GT *__
 // two-row form rebuilt once) and then walks the MF_GROUP fields of its block
 // (grid y), so a launch over nf fields fetches each link nf / MF_GROUP times
 // instead of nf times (and the launch has nf / MF_GROUP times more blocks
-// than with every field in one block).  Tiles are lexicographic runs of 256 sites, each XCD (blocks go to
-// the eight XCDs round-robin) owning a contiguous eighth of them, so the
-// neighbouring tiles whose spinors a tile's faces read run on the same XCD.
+// than with every field in one block).  Blocks go to the eight XCDs
+// round-robin, and the groups run one after another (grid y).  Without COL,
+// tiles are lexicographic runs of 256 sites, each XCD owning a contiguous
+// eighth of them.  With COL, each XCD owns one of the eight xyz columns
+// (Geom::cb, as MAP_COL) and walks it through t a column slice at a time, so
+// that the spinors a slice fetches for its t + 1 hops are still in that
+// XCD's L2 when the next two slices use them (a column slice of a group of
+// four FP16 fields is under 1 MB on 24^3 x 48).
 static constexpr int MF_GROUP = 4;   // fields per block of the multi-field stencil
 
-template <typename GT, int EPI>
+template <typename GT, int EPI, bool COL>
 __global__ __launch_bounds__(256) void k_stencil_mf(StencilArgs<h8> a, const GT *__restrict__ U, int nf)
 {
     const Geom &g = a.g;
     const int64_t V = g.V, Pu = g.Pu;
-    const unsigned T = (unsigned)((V + 255) / 256), per = gridDim.x / 8;
-    const unsigned tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    const int64_t s = (int64_t)tile * 256 + threadIdx.x;
-    const bool valid = tile < T && s < V;
+    unsigned tile;
+    int64_t s;
+    bool valid;
+    if constexpr (COL) {
+        // grid x = 8 Lt tps (tps tiles per column slice): column x % 8, then
+        // slice t and the tile within it
+        const unsigned per_col = gridDim.x / 8, col = blockIdx.x % 8, rest = blockIdx.x / 8;
+        const unsigned tps = per_col / (unsigned)g.L[3];
+        const int32_t t = (int32_t)(rest / tps);
+        const int32_t local = (int32_t)(rest % tps) * 256 + (int32_t)threadIdx.x;
+        tile = col * per_col + rest;
+        valid = local < g.col_sites;
+        const int32_t l = valid ? local : 0;
+        const int32_t cx = (int32_t)col % g.cn[0], cy = ((int32_t)col / g.cn[0]) % g.cn[1],
+                      cz = (int32_t)col / (g.cn[0] * g.cn[1]);
+        const int32_t x0 = cx * g.cb[0] + l % g.cb[0], x1 = cy * g.cb[1] + (l / g.cb[0]) % g.cb[1],
+                      x2 = cz * g.cb[2] + l / (g.cb[0] * g.cb[1]);
+        s = x0 + (int64_t)g.L[0] * (x1 + (int64_t)g.L[1] * (x2 + (int64_t)g.L[2] * t));
+    } else {
+        const unsigned T = (unsigned)((V + 255) / 256), per = gridDim.x / 8;
+        tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+        s = (int64_t)tile * 256 + threadIdx.x;
+        valid = tile < T && s < V;
+    }
     hv2 u[8][9];        // U_mu(x) in u[mu], U_mu(x - mu) in u[4 + mu]
     int64_t nb[8];      // x + mu in nb[mu], x - mu in nb[4 + mu]
     if (valid) {
@@ -1263,7 +1288,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // 8) with the tile's forward spatial links also staged in LDS, so that the
 // backward hop of a site inside the tile reads its neighbour's link there.
 // 20 (FP16 storage) one lane per site walking a group of four fields with the
-// site's links held in registers (k_stencil_mf).
+// site's links held in registers (k_stencil_mf); 21 the same in the XCD
+// column order of 4 / 5.
 static constexpr int N_VARIANTS = OVL_STENCIL_VARIANTS;
 static bool variant_lds(int v) { return (v >= 8 && v < 12) || (v >= 16 && v < 20); }
 static int variant_tps(int v) { return (v == 2 || v == 3 || v == 5 || v == 7 || v == 13 || v == 15) ? 2 : 1; }
@@ -1307,6 +1333,7 @@ unsigned stencil_tiles(const Geom &g, int v)
         const TileShape ts = tile_shape(g, v);
         return (unsigned)(ts.n[0] * ts.n[1] * ts.n[2] * ts.nch);
     }
+    if (v == 21) return 8u * (unsigned)g.L[3] * (unsigned)((g.col_sites + 255) / 256);
     if (v >= 6) return 8u * (unsigned)((g.stride[3] + spb - 1) / spb);
     if (v >= 4) return 8u * (unsigned)g.L[3] * (unsigned)((g.col_sites + spb - 1) / spb);
     return (unsigned)((g.V * tps + 255) / 256);
@@ -1319,6 +1346,7 @@ bool stencil_variant_ok(const Geom &g, int prec, int v)
     if ((v == 6 || v == 7) && g.L[3] % 8 != 0) return false;
     if (variant_lds(v)) return prec != OVL_F64 && g.L[3] % (1 << (v >= 16 ? v - 16 : v - 8)) == 0;
     if (v == 20) return prec == OVL_HALF;
+    if (v == 21) return prec == OVL_HALF && g.col_ok;
     return true;
 }
 
@@ -1385,11 +1413,16 @@ static void launch_by_id(Context &c, int id, const StencilArgs<ST> &a, const GT 
         case 14: launch_variant<ST, GT, EPI, 1, MAP_GRP64>(c, a, U, nf, pe); break;
         case 15: launch_variant<ST, GT, EPI, 2, MAP_GRP64>(c, a, U, nf, pe); break;
         case 20:
-            if constexpr (std::is_same<ST, h8>::value)
-                launch_k(c, pe, k_stencil_mf<GT, EPI>, dim3(stencil_tiles(c.g, 20), (nf + MF_GROUP - 1) / MF_GROUP),
-                         dim3(256), 0, a, U, nf);
-            else
-                throw Error{OVL_ERR_ARG, "stencil variant 20 is for FP16 storage"};
+        case 21:
+            if constexpr (std::is_same<ST, h8>::value) {
+                const dim3 grid(stencil_tiles(c.g, id), (nf + MF_GROUP - 1) / MF_GROUP);
+                if (id == 20)
+                    launch_k(c, pe, k_stencil_mf<GT, EPI, false>, grid, dim3(256), 0, a, U, nf);
+                else
+                    launch_k(c, pe, k_stencil_mf<GT, EPI, true>, grid, dim3(256), 0, a, U, nf);
+            } else {
+                throw Error{OVL_ERR_ARG, "stencil variants 20 and 21 are for FP16 storage"};
+            }
             break;
         default: launch_tmarch<ST, GT, EPI, 2>(c, a, U, nf, pe); break;
         }

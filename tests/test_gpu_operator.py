@@ -180,9 +180,9 @@ def test_every_launch_variant(dims, form):
     tol = {ovl.F64: 1e-14, ovl.F32: 2e-6, ovl.HALF: 5e-3}
     for prec in (ovl.F64, ovl.F32, ovl.HALF):
         variants = {ovl.F64: list(range(8)) + [12, 13, 14, 15], ovl.F32: list(range(20)),
-                    ovl.HALF: list(range(21))}[prec]
-        if dims == (4, 6, 2, 8):   # no split of x, y, z into 8 columns: 4 and 5 unavailable
-            variants = [v for v in variants if v not in (4, 5)]
+                    ovl.HALF: list(range(22))}[prec]
+        if dims == (4, 6, 2, 8):   # no split of x, y, z into 8 columns: 4, 5 and 21 unavailable
+            variants = [v for v in variants if v not in (4, 5, 21)]
         for v in variants:
             ctx = ovl.Context(dims)
             ctx.gauge_load(to_dev(U))
@@ -265,4 +265,32 @@ def test_dslash_24c48_12fields_sampled(prec):
     for f in range(12):
         ref = ora.hop_sites(Bh[f], sites)
         assert max_rel_elem(got[f], ref) < {"f32": 2e-6, "half": 5e-3}[prec], f
+    ctx.close()
+
+
+@pytest.mark.parametrize("variant", [20, 21])
+def test_dslash_24c48_12fields_multifield_variants(variant):
+    """The multi-field FP16 stencils forced on twelve 24^3 x 48 fields (three
+    groups of four: lexicographic tiles, and the XCD column order): H psi_f on
+    sampled sites of every field against the oracle."""
+    ovl = require_gpu()
+    import torch
+    dims = (24, 24, 24, 48)
+    V = 24 * 24 * 24 * 48
+    ctx = ovl.Context(dims)
+    Ud = torch.zeros((V, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    ctx.gauge_generate(3, 0.25, out=Ud)
+    ctx.set_tuning({_keys(ovl.HALF, 12)[0]: variant})
+    B = torch.stack([ctx.source(ovl.SRC_GAUSS, seed=320 + f) for f in range(12)])
+    print("case", dims, "half variant", variant, flush=True)
+    h = ctx.wilson_dslash(B, ovl.HALF)
+    assert ctx.tuning()[_keys(ovl.HALF, 12)[0]] == variant
+    sites = _sample_sites(dims, 80, 5)
+    got = to_host(h)[:, sites]
+    del h
+    ora = WilsonKernel(dims, to_host(Ud), 1.4)
+    Bh = to_host(B)
+    for f in range(12):
+        ref = ora.hop_sites(Bh[f], sites)
+        assert max_rel_elem(got[f], ref) < 5e-3, f
     ctx.close()
