@@ -86,10 +86,14 @@ static const ovl_zolo &zolo_for_accuracy(Context &c, const ovl_zolo &z, double e
 
 // s = sign(K) in (FP64 packed in/out) with the multi-shift CG in precision
 // prec.  Counters: with per_field, st has nf entries and field f's work goes
-// to st[f]; otherwise st is one aggregate.
+// to st[f]; otherwise st is one aggregate.  With lo non-null, a result in
+// FP32 or FP16 storage is left where *lo points (its precision in *lo_prec)
+// and s is not written; a result computed in FP64 is in s and *lo is null.
 static void sign_f64(Context &c, double rho, const ovl_zolo &zin, const double2 *in, double2 *s, int nf,
-                     const double *eta_in, int prec, int maxiter, ovl_stats *st, bool per_field)
+                     const double *eta_in, int prec, int maxiter, ovl_stats *st, bool per_field,
+                     const void **lo = nullptr, int *lo_prec = nullptr)
 {
+    if (lo) *lo = nullptr;
     const ovl_zolo &z = zolo_for_accuracy(c, zin, min_active(eta_in, nf));
     std::vector<double> eta_v(eta_in, eta_in + nf);
     if (&z != &zin)
@@ -111,7 +115,12 @@ static void sign_f64(Context &c, double rho, const ovl_zolo &zin, const double2 
                 void *b = c.buf("u_lo_out", FB);
                 convert_spinor(c, in, OVL_F64, a, prec, nf);
                 sign_mscg(c, rho, z, a, b, nf, eta, prec, maxiter, agg);
-                convert_spinor(c, b, prec, s, OVL_F64, nf);
+                if (lo) {
+                    *lo = b;
+                    *lo_prec = prec;
+                } else {
+                    convert_spinor(c, b, prec, s, OVL_F64, nf);
+                }
             }
             break;
         } catch (const Error &e) {
@@ -130,13 +139,51 @@ static void sign_f64(Context &c, double rho, const ovl_zolo &zin, const double2 
             }
 }
 
+// u = gamma_5 s for a sign call's output s in FP32 or FP16 storage, widened to
+// FP64, with each block's partial sums of (x, u) = sum conj(x) u: the
+// widening, gamma_5 and the dot (q~, U q) that follows every application of
+// U in Alg. 2, in one pass over the fields.
+static constexpr int WD_BLOCKS = 512;   // blocks per field of the fused pass
+template <typename ST>
+__global__ __launch_bounds__(256) void k_widen_g5_dot(const ST *__restrict__ in, double2 *__restrict__ u,
+                                                      const double2 *__restrict__ x, int64_t V, double *partial)
+{
+    const int f = blockIdx.y;
+    const ST *inf = in + f * fstride<ST>(V);
+    double re = 0.0, im = 0.0;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < V; s += (int64_t)gridDim.x * blockDim.x) {
+        cplx<float> v[12];
+        ld_sp(inf, V, s, v);
+        const int64_t o = (int64_t)f * 12 * V + s;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double sg = c < 6 ? 1.0 : -1.0;   // gamma_5 = diag(1, 1, -1, -1) on the spins
+            const double ur = sg * (double)v[c].re, ui = sg * (double)v[c].im;
+            u[o + c * V] = make_double2(ur, ui);
+            const double2 a = x[o + c * V];
+            re += a.x * ur + a.y * ui;
+            im += a.x * ui - a.y * ur;
+        }
+    }
+    __shared__ double lds[4];
+    const double tr = block_sum<256>(re, lds);
+    const double ti = block_sum<256>(im, lds);
+    if (threadIdx.x == 0) {
+        partial[((int64_t)f * 2 + 0) * gridDim.x + blockIdx.x] = tr;
+        partial[((int64_t)f * 2 + 1) * gridDim.x + blockIdx.x] = ti;
+    }
+}
+
 // u = gamma_5 sign(K) q for the fields with eta[f] > 0.  The active fields
 // are grouped by the precision their own accuracy calls for, and each group
 // runs its own sign call (its own Zolotarev order with the adaptive option):
 // a field whose middle solve has just restarted at a tight accuracy does not
 // pull the others up to FP32 or FP64.
+// With dx non-null, also (dx_f, u_f) for every field into *dot (an FP32 /
+// FP16 result is widened, gamma_5 applied and the dot taken in one pass).
 static void unitary_f64(Context &c, double rho, const ovl_zolo &z, const double2 *q, double2 *u, int nf,
-                        const double *eta, const ovl_solver_params &prm, ovl_stats *st)
+                        const double *eta, const ovl_solver_params &prm, ovl_stats *st,
+                        const double2 *dx = nullptr, std::vector<std::complex<double>> *dot = nullptr)
 {
     int want[MAXF], present[3] = {0, 0, 0};
     for (int f = 0; f < nf; ++f) {
@@ -145,7 +192,23 @@ static void unitary_f64(Context &c, double rho, const ovl_zolo &z, const double2
     }
     const int groups = (present[0] > 0) + (present[1] > 0) + (present[2] > 0);
     if (groups <= 1) {
-        sign_f64(c, rho, z, q, u, nf, eta, prec_for(prm, min_active(eta, nf)), prm.max_mscg, st, true);
+        const void *lo = nullptr;
+        int lp = OVL_F64;
+        sign_f64(c, rho, z, q, u, nf, eta, prec_for(prm, min_active(eta, nf)), prm.max_mscg, st, true,
+                 dx ? &lo : nullptr, &lp);
+        if (lo) {
+            const int64_t V = c.g.V;
+            double *part = (double *)c.buf("u_wdot_part", sizeof(double) * WD_BLOCKS * 2 * nf);
+            if (lp == OVL_F32)
+                k_widen_g5_dot<float4><<<dim3(WD_BLOCKS, nf), 256, 0, c.stream>>>((const float4 *)lo, u, dx, V, part);
+            else
+                k_widen_g5_dot<h8><<<dim3(WD_BLOCKS, nf), 256, 0, c.stream>>>((const h8 *)lo, u, dx, V, part);
+            OVL_HIP(hipGetLastError());
+            const double *h = sum_partials_host(c, part, WD_BLOCKS, 2 * nf);
+            dot->resize(nf);
+            for (int f = 0; f < nf; ++f) (*dot)[f] = {h[2 * f], h[2 * f + 1]};
+            return;
+        }
     } else {
         // each group's call writes every field of its output (the others'
         // unspecified), so it goes to a scratch set and its own fields are copied out
@@ -161,6 +224,12 @@ static void unitary_f64(Context &c, double rho, const ovl_zolo &z, const double2
         }
     }
     gamma5_f64(c, u, nf);
+    if (dx) {
+        std::vector<cplx<double>> d;
+        dot_f64(c, dx, u, nf, d);
+        dot->resize(nf);
+        for (int f = 0; f < nf; ++f) (*dot)[f] = {d[f].re, d[f].im};
+    }
 }
 
 static void overlap_impl(Context &c, double rho, double mu, const ovl_zolo &z, const double2 *in, double2 *out,
@@ -386,12 +455,11 @@ static void sumr(Context &c, const ovl_zolo &z, const ovl_solver_params &prm, do
         }
         if (nact == 0) break;
         for (int f = 0; f < nf; ++f) eta[f] = F[f].active ? eta_for(F[f]) : 0.0;
-        unitary_f64(c, rhoK, z, q, u, nf, eta.data(), prm, st);
+        std::vector<zc> g;   // (q~, U q), taken with U q
+        unitary_f64(c, rhoK, z, q, u, nf, eta.data(), prm, st, qt, &g);
         if (collect)   // Alg. 5: every active field's (q, U q); one field unless collecting as a block
             for (int f = 0; f < nf; ++f)
                 if (F[f].active) eig_collect(c, q + (size_t)f * n, u + (size_t)f * n);
-        std::vector<zc> g;
-        dots(c, qt, u, nf, g);
         SumrCoef k{};
         for (int f = 0; f < nf; ++f) {
             SumrField &sf = F[f];
