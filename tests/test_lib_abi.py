@@ -46,3 +46,28 @@ def test_argument_errors_are_reported():
         ovl.zolotarev_coeffs(4, 2.0, 1.0)
     p = ovl.solver_defaults()
     assert p.tol == 1e-10 and p.relax_floor == 1e-2 and p.norm_restart == 0.1
+
+
+def test_header_constants_match_binding():
+    """Every OVL_* enumerator and numeric #define of include/ovl.h that the
+    binding mirrors has the same value there (options, precisions, sources,
+    status codes, the stencil variant count, the pole limit)."""
+    import paper_1501_01855_amd as ovl
+    text = open(os.path.join(ROOT, "include", "ovl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    consts = {k: int(v) for k, v in re.findall(r"\b(OVL_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    consts.update({k: int(v) for k, v in re.findall(r"#define\s+(OVL_[A-Z0-9_]+)\s+(-?\d+)\s*$", text, flags=re.M)})
+    checked = 0
+    for name, value in consts.items():
+        py = name[len("OVL_"):]
+        if py == "STENCIL_VARIANTS":
+            py = "N_STENCIL_VARIANTS"
+        if hasattr(ovl, py):
+            assert getattr(ovl, py) == value, name
+            checked += 1
+        elif py.startswith(("OK", "ERR_")):
+            assert ovl.STATUS[value] == py, name
+            checked += 1
+    for opt in ("GRAPHS", "AUTOTUNE", "ADAPTIVE_NZ", "BOUND_PRINTED", "TWO_ROW_LINKS", "OUTER_PRINTED"):
+        assert "OVL_OPT_" + opt in consts, opt
+    assert checked >= 20
